@@ -1,0 +1,172 @@
+/*
+ * soap_dp.h -- C ABI of libsoapdp, batched read-vs-window affine-gap
+ * alignment on AMD Instinct MI355X (gfx950).
+ *
+ * The operation (paper, Methods section 3, "GPU-accelerated dynamic
+ * programming"): for each task, a read R of length n and a candidate region
+ * (reference window) T of length m, find the sub-region T' of T whose
+ * alignment score with the whole of R is maximal.  With delta(x,y) = S_MA if
+ * x == y else S_MI, and gap scores S_GO (first base of a gap) and S_GE (each
+ * further base):
+ *
+ *   I(i,j) = max(M(i,j-1) + S_GO, I(i,j-1) + S_GE)
+ *   D(i,j) = max(M(i-1,j) + S_GO, D(i-1,j) + S_GE)
+ *   M(i,j) = max(M(i-1,j-1) + delta(T[i], R[j]), I(i,j), D(i,j))
+ *   I(i,0) = D(0,j) = -inf,  M(i,0) = 0,  M(0,j) = S_GO + (j-1) S_GE
+ *
+ * score = max_{1<=i<=m} M(i,n).  The read is aligned end to end; the window
+ * is free at both ends; there is no zero floor.
+ *
+ * Outputs are exact integers and deterministic:
+ *   ref_end    the smallest i reaching the score (0-based exclusive end)
+ *   ref_begin  0-based start of T', so T' = T[ref_begin, ref_end)
+ *   cigar      BAM-encoded runs (len << 4 | op), op M = 0, I = 1, D = 2,
+ *              no soft clips (a leading or trailing I is kept)
+ * Ties in the traceback prefer, at an M cell, the diagonal, then D, then I;
+ * inside a gap, opening before extending.
+ *
+ * Sequences are 2-bit codes A=0, C=1, G=2, T=3, sixteen to a 32-bit word,
+ * base k of a word in bits [2k, 2k+2).
+ *
+ * All functions return SOAP_DP_OK (0) or a negative error code; on error
+ * nothing has been enqueued.  Per-task problems do not fail a batch: they
+ * are reported in result.status.
+ */
+#ifndef SOAP_DP_H
+#define SOAP_DP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- error codes (return values) ---- */
+#define SOAP_DP_OK 0
+#define SOAP_DP_EINVAL (-1)   /* bad scoring, null pointer, size or stride */
+#define SOAP_DP_ENOMEM (-2)   /* workspace could not be allocated */
+#define SOAP_DP_EHIP (-3)     /* HIP runtime error; see soap_dp_last_hip_error */
+#define SOAP_DP_ENODEV (-4)   /* no usable gfx950 device */
+
+/* ---- per-task status (result.status) ---- */
+#define SOAP_DP_TASK_OK 0
+#define SOAP_DP_TASK_INVALID_LEN 1     /* n or m < 1, or above the batch bounds / limits */
+#define SOAP_DP_TASK_OK_REDONE_INT32 2 /* OK; the int16 form's range did not cover this task,
+                                          so it was computed by the exact int32 kernel */
+#define SOAP_DP_TASK_INVALID_OFFSET 3  /* read or window lies outside its buffer */
+
+/* ---- limits ---- */
+#define SOAP_DP_MAX_READ 512      /* n; the paper does not recommend reads over 500 bp */
+#define SOAP_DP_MAX_WINDOW 8192   /* m */
+#define SOAP_DP_MAX_SCORE_ABS 16384
+
+/* ---- flags for soap_dp_align_batch ---- */
+#define SOAP_DP_PLAIN 0u    /* one int32 launch, one kernel shape for the whole batch */
+#define SOAP_DP_BATCHED 1u  /* device-side length bucketing, packed int16 with int32 redo of
+                               tasks outside the int16 range, persistent kernels with a
+                               work queue, autotuned shapes, replayed as a hipGraph */
+
+/*
+ * Scores, all signed and added.  A gap of k bases scores
+ * gap_open + (k-1) * gap_extend.  Valid: 0 < match <= 2^14,
+ * mismatch < match, gap_open <= gap_extend <= 0, gap_open < 0,
+ * |every score| <= 2^14.  (BWA's "open q, extend r" convention maps to
+ * gap_open = -(q + r), gap_extend = -r.)
+ */
+typedef struct {
+  int32_t match;
+  int32_t mismatch;
+  int32_t gap_open;
+  int32_t gap_extend;
+} soap_dp_scoring;
+
+/*
+ * A batch of tasks.  Array pointers are DEVICE pointers, caller-owned, read
+ * only to the library, and must stay valid until the enqueued work has
+ * completed.  Scalars are host values.
+ *   read_codes     packed reads; read t starts at word read_word_off[t]
+ *   read_len       n_t, 1 <= n_t <= max_n
+ *   ref_codes      packed windows or a packed genome; window t starts at
+ *                  BASE offset ref_base_off[t] (any alignment), so windows
+ *                  can be cut from a device-resident genome without copies
+ *   ref_len        m_t, 1 <= m_t <= max_m
+ *   n_tasks        number of tasks (0 is a no-op)
+ *   max_n, max_m   host-side bounds on every n_t and m_t (1..512, 1..8192);
+ *                  they size the workspace and the plain kernel's shape.
+ *                  A task above them gets SOAP_DP_TASK_INVALID_LEN.
+ *   read_words     words in read_codes, ref_words words in ref_codes; a task
+ *                  whose data would lie outside gets SOAP_DP_TASK_INVALID_OFFSET
+ */
+typedef struct {
+  const uint32_t *read_codes;
+  const uint64_t *read_word_off;
+  const int32_t *read_len;
+  const uint32_t *ref_codes;
+  const uint64_t *ref_base_off;
+  const int32_t *ref_len;
+  int64_t n_tasks;
+  int32_t max_n;
+  int32_t max_m;
+  uint64_t read_words;
+  uint64_t ref_words;
+} soap_dp_batch;
+
+/*
+ * Outputs, DEVICE pointers, caller-owned, n_tasks entries each (cigar:
+ * n_tasks * cigar_stride words).  cigar_stride >= 2 * max_n - 1, the most
+ * runs an alignment of an n-base read can have.  Every task's outputs are
+ * written, zeros for an invalid task.
+ */
+typedef struct {
+  int32_t *score;
+  int32_t *ref_begin;
+  int32_t *ref_end;
+  uint32_t *cigar;
+  int32_t cigar_stride;
+  int32_t *cigar_len;
+  uint8_t *status;
+} soap_dp_result;
+
+typedef struct soap_dp_ctx soap_dp_ctx;
+
+/* Create a context on HIP device `device_ordinal`.  The context owns the
+ * device workspace (decision-bit scratch, bucketing arrays), the autotune
+ * table and the graph cache.  Returns SOAP_DP_ENODEV unless the device is
+ * gfx950. */
+int soap_dp_create(soap_dp_ctx **ctx, int device_ordinal);
+
+/* Release everything the context owns (synchronises the device first). */
+int soap_dp_destroy(soap_dp_ctx *ctx);
+
+/*
+ * Enqueue the alignment of `in` on `stream` (a hipStream_t; NULL is the null
+ * stream) and return.  Results are valid once the stream has synchronised.
+ * `flags` is SOAP_DP_PLAIN or SOAP_DP_BATCHED; both give identical outputs.
+ * The library keeps no pointer to caller buffers after the work completes.
+ * One context serves one stream at a time: calls on a context must not
+ * overlap in time on different streams (use one context per stream).
+ */
+int soap_dp_align_batch(soap_dp_ctx *ctx, const soap_dp_batch *in, const soap_dp_scoring *sc,
+                        const soap_dp_result *out, void *stream, uint32_t flags);
+
+/* Device bytes of workspace a call with these bounds needs (allocated by the
+ * context on first use and kept). */
+size_t soap_dp_workspace_bytes(const soap_dp_ctx *ctx, int64_t n_tasks, int32_t max_n,
+                               int32_t max_m, uint32_t flags);
+
+/* Allocate the workspace for these bounds now, so later calls allocate
+ * nothing (needed before capturing a call into a hipGraph). */
+int soap_dp_reserve(soap_dp_ctx *ctx, int64_t n_tasks, int32_t max_n, int32_t max_m,
+                    uint32_t flags);
+
+/* Human-readable text for an error code. */
+const char *soap_dp_strerror(int code);
+
+/* The HIP error code behind the last SOAP_DP_EHIP on this context. */
+int soap_dp_last_hip_error(const soap_dp_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SOAP_DP_H */

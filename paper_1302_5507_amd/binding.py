@@ -1,0 +1,266 @@
+"""Python binding of libsoapdp (ctypes).  Argument marshalling only: every step
+of the alignment runs in the library's HIP kernels; torch provides device
+memory and streams.  The functions ``soap_dp_*`` mirror include/soap_dp.h.
+
+Loading fails loudly when the library has not been built; there is no CPU
+fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libsoapdp.so")
+
+SOAP_DP_OK = 0
+SOAP_DP_EINVAL = -1
+SOAP_DP_ENOMEM = -2
+SOAP_DP_EHIP = -3
+SOAP_DP_ENODEV = -4
+
+TASK_OK = 0
+TASK_INVALID_LEN = 1
+TASK_OK_REDONE_INT32 = 2
+TASK_INVALID_OFFSET = 3
+
+MAX_READ = 512
+MAX_WINDOW = 8192
+
+PLAIN = 0
+BATCHED = 1
+
+EXPORTED = [
+    "soap_dp_create", "soap_dp_destroy", "soap_dp_align_batch", "soap_dp_workspace_bytes",
+    "soap_dp_reserve", "soap_dp_strerror", "soap_dp_last_hip_error",
+]
+
+
+class Scoring(ctypes.Structure):
+    _fields_ = [("match", ctypes.c_int32), ("mismatch", ctypes.c_int32),
+                ("gap_open", ctypes.c_int32), ("gap_extend", ctypes.c_int32)]
+
+
+class Batch(ctypes.Structure):
+    _fields_ = [("read_codes", ctypes.c_void_p), ("read_word_off", ctypes.c_void_p),
+                ("read_len", ctypes.c_void_p), ("ref_codes", ctypes.c_void_p),
+                ("ref_base_off", ctypes.c_void_p), ("ref_len", ctypes.c_void_p),
+                ("n_tasks", ctypes.c_int64), ("max_n", ctypes.c_int32), ("max_m", ctypes.c_int32),
+                ("read_words", ctypes.c_uint64), ("ref_words", ctypes.c_uint64)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("score", ctypes.c_void_p), ("ref_begin", ctypes.c_void_p),
+                ("ref_end", ctypes.c_void_p), ("cigar", ctypes.c_void_p),
+                ("cigar_stride", ctypes.c_int32), ("cigar_len", ctypes.c_void_p),
+                ("status", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+class SoapDpError(RuntimeError):
+    def __init__(self, code, what=""):
+        self.code = code
+        msg = lib().soap_dp_strerror(code).decode() if _lib is not None else str(code)
+        super().__init__(f"{what}: {msg} ({code})" if what else f"{msg} ({code})")
+
+
+def lib():
+    """Load libsoapdp.so (after torch, so that both share one HIP runtime)."""
+    global _lib
+    if _lib is None:
+        try:
+            import torch  # noqa: F401  (loads the HIP runtime torch uses)
+        except Exception:
+            pass
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_1302_5507_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        vp = ctypes.c_void_p
+        L.soap_dp_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int]
+        L.soap_dp_create.restype = ctypes.c_int
+        L.soap_dp_destroy.argtypes = [vp]
+        L.soap_dp_destroy.restype = ctypes.c_int
+        L.soap_dp_align_batch.argtypes = [vp, ctypes.POINTER(Batch), ctypes.POINTER(Scoring),
+                                          ctypes.POINTER(Result), vp, ctypes.c_uint32]
+        L.soap_dp_align_batch.restype = ctypes.c_int
+        L.soap_dp_workspace_bytes.argtypes = [vp, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
+                                              ctypes.c_uint32]
+        L.soap_dp_workspace_bytes.restype = ctypes.c_size_t
+        L.soap_dp_reserve.argtypes = [vp, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
+                                      ctypes.c_uint32]
+        L.soap_dp_reserve.restype = ctypes.c_int
+        L.soap_dp_strerror.argtypes = [ctypes.c_int]
+        L.soap_dp_strerror.restype = ctypes.c_char_p
+        L.soap_dp_last_hip_error.argtypes = [vp]
+        L.soap_dp_last_hip_error.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+# ---------------------------------------------------------------- raw ABI
+
+def soap_dp_create(device_ordinal: int = 0):
+    h = ctypes.c_void_p()
+    rc = lib().soap_dp_create(ctypes.byref(h), int(device_ordinal))
+    if rc != SOAP_DP_OK:
+        raise SoapDpError(rc, "soap_dp_create")
+    return h
+
+
+def soap_dp_destroy(ctx) -> int:
+    return lib().soap_dp_destroy(ctx)
+
+
+def soap_dp_align_batch(ctx, batch: Batch, sc: Scoring, res: Result, stream: int, flags: int) -> int:
+    return lib().soap_dp_align_batch(ctx, ctypes.byref(batch), ctypes.byref(sc), ctypes.byref(res),
+                                     ctypes.c_void_p(stream), int(flags))
+
+
+def soap_dp_workspace_bytes(ctx, n_tasks, max_n, max_m, flags) -> int:
+    return int(lib().soap_dp_workspace_bytes(ctx, int(n_tasks), int(max_n), int(max_m), int(flags)))
+
+
+def soap_dp_reserve(ctx, n_tasks, max_n, max_m, flags) -> int:
+    return lib().soap_dp_reserve(ctx, int(n_tasks), int(max_n), int(max_m), int(flags))
+
+
+def soap_dp_strerror(code: int) -> str:
+    return lib().soap_dp_strerror(int(code)).decode()
+
+
+def soap_dp_last_hip_error(ctx) -> int:
+    return lib().soap_dp_last_hip_error(ctx)
+
+
+# ---------------------------------------------------------------- packing
+
+def pack_words(codes: np.ndarray) -> np.ndarray:
+    """Pack base codes (uint8 0..3) 16 to a uint32 word, base k in bits 2k."""
+    codes = np.asarray(codes, dtype=np.uint8)
+    nw = (codes.size + 15) // 16
+    buf = np.zeros(nw * 16, dtype=np.uint32)
+    buf[:codes.size] = codes
+    buf = buf.reshape(nw, 16) << (2 * np.arange(16, dtype=np.uint32))
+    return np.bitwise_or.reduce(buf, axis=1).astype(np.uint32)
+
+
+def pack_reads(read_codes, read_off, read_len):
+    """Pack each read word-aligned.  Returns (words uint32, word_off uint64)."""
+    read_off = np.asarray(read_off, dtype=np.int64)
+    read_len = np.asarray(read_len, dtype=np.int64)
+    T = read_len.size
+    nw = (np.maximum(read_len, 0) + 15) // 16
+    word_off = np.zeros(T, dtype=np.int64)
+    if T:
+        word_off[1:] = np.cumsum(nw)[:-1]
+    total = int(nw.sum())
+    flat = np.zeros(max(total, 1) * 16, dtype=np.uint8)
+    if total:
+        # destination base index of every source base
+        lens = np.maximum(read_len, 0)
+        rep = np.repeat(np.arange(T), lens)
+        k = np.arange(int(lens.sum())) - np.repeat(np.cumsum(lens) - lens, lens)
+        src = read_off[rep] + k
+        flat[word_off[rep] * 16 + k] = np.asarray(read_codes, dtype=np.uint8)[src]
+    words = pack_words(flat)[:max(total, 1)]
+    return words, word_off.astype(np.uint64)
+
+
+# ---------------------------------------------------------------- convenience
+
+class DeviceWorkload:
+    """A workload resident in device memory in the library's input format."""
+
+    def __init__(self, w, device="cuda", genome_words=None):
+        import torch
+        self.n_tasks = w.n_tasks
+        rw, rwo = pack_reads(w.read_codes, w.read_off, w.read_len)
+        dev = torch.device(device)
+        t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+        self.read_words = t(rw.view(np.int32))
+        self.read_word_off = t(rwo.view(np.int64))
+        self.read_len = t(w.read_len.astype(np.int32))
+        if genome_words is None:
+            genome_words = t(pack_words(w.genome).view(np.int32))
+        self.ref_words = genome_words
+        self.ref_base_off = t(w.ref_off.astype(np.int64))
+        self.ref_len = t(w.ref_len.astype(np.int32))
+        self.max_n = int(max(1, min(MAX_READ, int(w.read_len.max()) if w.n_tasks else 1)))
+        self.max_m = int(max(1, min(MAX_WINDOW, int(w.ref_len.max()) if w.n_tasks else 1)))
+        self.cells = w.cells
+
+    def batch(self, max_n=None, max_m=None) -> Batch:
+        return Batch(self.read_words.data_ptr(), self.read_word_off.data_ptr(),
+                     self.read_len.data_ptr(), self.ref_words.data_ptr(),
+                     self.ref_base_off.data_ptr(), self.ref_len.data_ptr(), self.n_tasks,
+                     int(max_n or self.max_n), int(max_m or self.max_m),
+                     int(self.read_words.numel()), int(self.ref_words.numel()))
+
+
+class DeviceResult:
+    def __init__(self, n_tasks, cigar_stride, device="cuda"):
+        import torch
+        dev = torch.device(device)
+        T = max(int(n_tasks), 1)
+        self.n_tasks = int(n_tasks)
+        self.cigar_stride = int(cigar_stride)
+        self.score = torch.zeros(T, dtype=torch.int32, device=dev)
+        self.ref_begin = torch.zeros(T, dtype=torch.int32, device=dev)
+        self.ref_end = torch.zeros(T, dtype=torch.int32, device=dev)
+        self.cigar = torch.zeros(T * self.cigar_stride, dtype=torch.int32, device=dev)
+        self.cigar_len = torch.zeros(T, dtype=torch.int32, device=dev)
+        self.status = torch.full((T,), 255, dtype=torch.uint8, device=dev)
+
+    def abi(self) -> Result:
+        return Result(self.score.data_ptr(), self.ref_begin.data_ptr(), self.ref_end.data_ptr(),
+                      self.cigar.data_ptr(), self.cigar_stride, self.cigar_len.data_ptr(),
+                      self.status.data_ptr())
+
+    def to_host(self):
+        T = self.n_tasks
+        out = {
+            "score": self.score.cpu().numpy()[:T],
+            "ref_begin": self.ref_begin.cpu().numpy()[:T],
+            "ref_end": self.ref_end.cpu().numpy()[:T],
+            "cigar": self.cigar.cpu().numpy().view(np.uint32).reshape(-1, self.cigar_stride)[:T],
+            "cigar_len": self.cigar_len.cpu().numpy()[:T],
+            "status": self.status.cpu().numpy()[:T],
+        }
+        return out
+
+
+class Aligner:
+    """Owns a library context on one device."""
+
+    def __init__(self, device_ordinal: int = 0):
+        self.device_ordinal = device_ordinal
+        self.ctx = soap_dp_create(device_ordinal)
+
+    def close(self):
+        if self.ctx:
+            soap_dp_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def align(self, dw: DeviceWorkload, scoring=(1, -3, -5, -2), flags=PLAIN, res=None,
+              stream=None, max_n=None, max_m=None) -> DeviceResult:
+        import torch
+        if res is None:
+            res = DeviceResult(dw.n_tasks, 2 * (max_n or dw.max_n))
+        if stream is None:
+            stream = torch.cuda.current_stream().cuda_stream
+        rc = soap_dp_align_batch(self.ctx, dw.batch(max_n, max_m), Scoring(*scoring), res.abi(),
+                                 stream, flags)
+        if rc != SOAP_DP_OK:
+            raise SoapDpError(rc, "soap_dp_align_batch")
+        return res

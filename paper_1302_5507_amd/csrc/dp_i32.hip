@@ -1,0 +1,315 @@
+// int32 fill + traceback kernel for batched read-vs-window affine-gap
+// alignment (paper, Methods section 3: recurrences for I, D, M, base cases,
+// result max_i M(i, n); traceback from the D and M decisions).
+//
+// Mapping onto a 64-lane CDNA wavefront:
+//  * A task is served by L consecutive lanes (64/L tasks per wavefront).  The
+//    read is right-aligned onto the L*K columns the lanes own (K per lane),
+//    so read column n is always the last column of the last lane and the
+//    result row is read from a fixed register.  Columns left of the read are
+//    "virtual": their delta is 0 and their M stays 0, which reproduces the
+//    boundary M(i,0) = 0 exactly, and I there never beats opening a gap.
+//  * The window (rows i = 1..m) is swept along anti-diagonals: at step t lane
+//    l of a task computes row t + 1 - l for its K columns, left to right.  The
+//    only value crossing lanes is the left neighbour's last column (M and I
+//    of the current row) plus the window base of that row; it moves with one
+//    DPP wave_shr:1 per value and step.  The diagonal M of the first column is
+//    the value received one step earlier.  D and M of the previous row stay in
+//    the lane's registers.
+//  * Each cell yields four decision bits, taken as the sign of a difference
+//    that is zero exactly when the tie-broken option wins: bit3 I extended,
+//    bit2 D extended, bit1 M did not come from the diagonal, bit0 M did not
+//    come from D.  They are packed 8 cells to a dword (first cell in the top
+//    nibble) and written step-major, so every store of the wavefront is 256
+//    contiguous bytes.
+//  * After the sweep one lane per task walks the decisions back from
+//    (ref_end, n) and writes the run-length CIGAR.
+#include "dp_internal.h"
+
+namespace soapdp {
+
+__device__ __forceinline__ int32_t wave_shr1(int32_t v) {
+  // DPP wave_shr:1 -- lane k receives lane k-1; lane 0 receives 0.
+  return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xf, 0xf, false);
+}
+
+__device__ __forceinline__ uint32_t push_sign(uint32_t acc, int32_t diff) {
+  // (acc << 1) | (diff < 0): shift the sign bit of `diff` into the accumulator.
+  return __builtin_amdgcn_alignbit(acc, (uint32_t)diff, 31);
+}
+
+__device__ __forceinline__ int32_t wave_max(int32_t v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v = max(v, __shfl_xor(v, o));
+  return v;
+}
+
+// Walk the decision nibbles of one task back from (end, n) and write its
+// CIGAR.  `nib_at(i, j)` returns the decision nibble of cell (i, j).
+template <class NibFn>
+__device__ void traceback_task(const DpParams &p, int64_t task, int32_t n, int32_t end,
+                               NibFn nib_at) {
+  uint32_t *row = p.cigar + task * (int64_t)p.cigar_stride;
+  int32_t wpos = p.cigar_stride;  // runs are written backward from the row end
+  int32_t cur = -1, run = 0;
+  int32_t i = end, j = n, state = 0;  // 0 = M, 1 = D, 2 = I
+  int32_t begin = 0;
+  bool overflow = false;
+  auto emit = [&](int32_t op, int32_t len) {
+    if (op == cur) {
+      run += len;
+    } else {
+      if (run > 0) {
+        if (wpos > 0) row[--wpos] = (uint32_t)run << 4 | (uint32_t)cur;
+        else overflow = true;
+      }
+      cur = op;
+      run = len;
+    }
+  };
+  // Every iteration lowers i or j, so the walk ends within n + end steps.
+  // The guards keep a corrupted decision from reading outside the task.
+  for (int32_t guard = n + end + 1; guard > 0; --guard) {
+    if (state == 0) {
+      if (j == 0) { begin = i; break; }
+      if (i == 0) { emit(1, j); begin = 0; break; }
+    }
+    if (i < 1 || j < 1) { overflow = true; break; }
+    const uint32_t nib = nib_at(i, j);
+    if (state == 0) {
+      if (!(nib & 2u)) {          // diagonal
+        emit(0, 1);
+        --i; --j;
+        continue;
+      }
+      state = (nib & 1u) ? 2 : 1;  // from I, else from D
+    }
+    if (state == 1) {             // region base i against a space
+      emit(2, 1);
+      if (!(nib & 4u)) state = 0;
+      --i;
+    } else {                      // read base j against a space
+      emit(1, 1);
+      if (!(nib & 8u)) state = 0;
+      --j;
+    }
+  }
+  emit(-2, 0);  // flush the last run
+  const int32_t cnt = p.cigar_stride - wpos;
+  for (int32_t k = 0; k < cnt; ++k) row[k] = row[wpos + k];
+  p.cigar_len[task] = overflow ? 0 : cnt;
+  p.ref_begin[task] = begin;
+  if (overflow) p.status[task] = kTaskInvalidLen;
+}
+
+template <int L, int K>
+__global__ __launch_bounds__(kWave) void dp_i32_kernel(DpParams p) {
+  static_assert(kWave % L == 0, "lanes per task must divide the wavefront");
+  constexpr int G = kWave / L;       // tasks per wavefront
+  constexpr int W = (K + 7) / 8;     // decision dwords per lane per step
+  const int lane = threadIdx.x;
+  const int g = lane / L;
+  const int lg = lane % L;
+  const bool first = lg == 0;
+  const bool last = lg == L - 1;
+
+  __shared__ int64_t s_task[G];
+  __shared__ int32_t s_n[G], s_pad[G], s_end[G], s_score[G];
+  __shared__ uint8_t s_st[G];
+
+  uint32_t *const slot = p.scratch + (uint64_t)blockIdx.x * p.slot_dwords;
+  const int64_t n_tasks = p.task_count ? (int64_t)*p.task_count : p.n_tasks;
+  const int64_t n_items = (n_tasks + G - 1) / G;
+
+  int64_t item = blockIdx.x;
+  if (p.work_counter) {
+    int32_t v = 0;
+    if (lane == 0) v = atomicAdd(p.work_counter, 1);
+    item = __builtin_amdgcn_readfirstlane(v);
+  }
+  while (item < n_items) {
+    // ---------------- task set-up
+    const int64_t tix = item * G + g;
+    int64_t task = -1;
+    int32_t n = 0, m = 0;
+    uint64_t rwo = 0, rbo = 0;
+    uint8_t st = kTaskOk;
+    if (tix < n_tasks) {
+      task = p.task_list ? (int64_t)p.task_list[tix] : tix;
+      n = p.read_len[task];
+      m = p.ref_len[task];
+      rwo = p.read_word_off[task];
+      rbo = p.ref_base_off[task];
+      if (n < 1 || m < 1 || n > p.max_n || m > p.max_m || n > L * K)
+        st = kTaskInvalidLen;
+      else if (rwo + (uint64_t)((n + 15) >> 4) > p.read_words || rbo + (uint64_t)m > p.ref_words * 16)
+        st = kTaskInvalidOffset;
+    }
+    const bool valid = task >= 0 && st == kTaskOk;
+    const int32_t mg = valid ? m : 0;
+    const int32_t pad = L * K - n;
+    const int32_t steps = wave_max(mg) + L - 1;
+
+    int32_t Rc[K], Mi[K], H[K], F[K];
+#pragma unroll
+    for (int c = 0; c < K; ++c) {
+      const int32_t q = lg * K + c - pad;  // 0-based read index of this column
+      const bool real = valid && q >= 0;
+      uint32_t code = 4;                   // never equals a window base
+      if (real) code = (p.read_codes[rwo + (uint64_t)(q >> 4)] >> ((q & 15) * 2)) & 3u;
+      Rc[c] = (int32_t)code;
+      Mi[c] = real ? p.mi : 0;
+      H[c] = real ? p.go + q * p.ge : 0;   // M(0, q+1), or 0 left of the read
+      F[c] = kNeg32;                       // D(0, j)
+    }
+
+    // window bases, 16 at a time, realigned from the base offset
+    const uint64_t wlim = p.ref_words - 1;
+    const int32_t wsh = (int32_t)(rbo & 15) * 2;
+    auto load_block = [&](int32_t b, uint32_t &w0, uint32_t &w1) {
+      const uint64_t wi = (rbo >> 4) + (uint64_t)b;
+      w0 = p.ref_codes[wi < wlim ? wi : wlim];
+      w1 = p.ref_codes[wi + 1 < wlim ? wi + 1 : wlim];
+    };
+    uint32_t tn0, tn1, tw = 0;
+    load_block(0, tn0, tn1);
+
+    int32_t hl_out = H[K - 1];   // M(0, last column of the strip)
+    int32_t el_out = kNeg32;
+    int32_t t_out = 0;
+    int32_t hl_prev = 0;
+    int32_t best = INT32_MIN, endi = 0;
+    uint32_t acc[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) acc[w] = 0;
+
+    uint32_t *sp = slot;
+    for (int32_t t = 0; t < steps; ++t) {
+      if ((t & 15) == 0) {
+        tw = __builtin_amdgcn_alignbit(tn1, tn0, wsh);
+        load_block((t >> 4) + 1, tn0, tn1);
+      }
+      const int32_t tfirst = (int32_t)((tw >> ((t & 15) * 2)) & 3u);
+      int32_t hl = wave_shr1(hl_out);
+      int32_t el = wave_shr1(el_out);
+      int32_t T = wave_shr1(t_out);
+      int32_t hd = hl_prev;
+      if (first) { hl = 0; el = kNeg32; T = tfirst; hd = 0; }
+      hl_prev = hl;
+      t_out = T;
+      const int32_t i = t + 1 - lg;
+      if (i >= 1 && i <= mg) {
+#pragma unroll
+        for (int c = 0; c < K; ++c) {
+          const int32_t diag = hd + (Rc[c] == T ? p.ma : Mi[c]);
+          hd = H[c];
+          const int32_t ai = hl + p.go;
+          el = max(ai, el + p.ge);
+          const int32_t ad = H[c] + p.go;
+          const int32_t f = max(ad, F[c] + p.ge);
+          const int32_t h = max(max(diag, el), f);
+          uint32_t a = acc[c / 8];
+          a = push_sign(a, ai - el);
+          a = push_sign(a, ad - f);
+          a = push_sign(a, diag - h);
+          a = push_sign(a, f - h);
+          acc[c / 8] = a;
+          H[c] = h;
+          F[c] = f;
+          hl = h;
+        }
+        if (K % 8) acc[W - 1] <<= 4 * (8 - K % 8);
+        hl_out = hl;
+        el_out = el;
+        if (last && H[K - 1] > best) { best = H[K - 1]; endi = i; }
+      }
+#pragma unroll
+      for (int w = 0; w < W; ++w) sp[w * kWave + lane] = acc[w];
+      sp += W * kWave;
+    }
+
+    if (first) { s_task[g] = task; s_n[g] = n; s_pad[g] = pad; s_st[g] = st; }
+    if (last) { s_end[g] = endi; s_score[g] = best; }
+    __syncthreads();
+
+    // ---------------- traceback, one lane per task
+    if (lane < G) {
+      const int64_t tk = s_task[lane];
+      if (tk >= 0) {
+        const uint8_t tst = s_st[lane];
+        if (tst != kTaskOk) {
+          p.score[tk] = 0; p.ref_begin[tk] = 0; p.ref_end[tk] = 0; p.cigar_len[tk] = 0;
+          p.status[tk] = tst;
+        } else {
+          const int32_t tn = s_n[lane], tpad = s_pad[lane], tend = s_end[lane];
+          p.score[tk] = s_score[lane];
+          p.ref_end[tk] = tend;
+          p.status[tk] = kTaskOk;
+          const uint32_t *base = slot + lane * L;
+          auto nib_at = [&](int32_t i, int32_t j) -> uint32_t {
+            const int32_t jp = j + tpad - 1;
+            const int32_t lq = jp / K;
+            const int32_t c = jp - lq * K;
+            const int32_t ts = i - 1 + lq;
+            const uint32_t wd = base[((uint64_t)ts * W + (uint32_t)(c >> 3)) * kWave + lq];
+            return (wd >> (4 * (7 - (c & 7)))) & 15u;
+          };
+          traceback_task(p, tk, tn, tend, nib_at);
+        }
+      }
+    }
+    __syncthreads();
+
+    if (p.work_counter) {
+      int32_t v = 0;
+      if (lane == 0) v = atomicAdd(p.work_counter, 1);
+      item = __builtin_amdgcn_readfirstlane(v);
+    } else {
+      item += gridDim.x;
+    }
+  }
+}
+
+// ---------------------------------------------------------------- dispatch
+
+#define SOAPDP_I32_SHAPES(X) \
+  X(1, 8) X(2, 8) X(4, 9) X(4, 13) X(4, 19) X(8, 7) X(8, 10) X(8, 13) X(8, 19) \
+  X(16, 10) X(16, 16) X(32, 16) X(64, 8)
+
+static const Shape kShapesI32[] = {
+#define X(l, k) {l, k},
+    SOAPDP_I32_SHAPES(X)
+#undef X
+};
+
+const Shape *shapes_i32(int *count) {
+  *count = (int)(sizeof(kShapesI32) / sizeof(kShapesI32[0]));
+  return kShapesI32;
+}
+
+hipError_t launch_dp_i32(Shape s, int grid, hipStream_t stream, const DpParams &p) {
+#define X(l, k)                                                                 \
+  if (s.lanes == l && s.cells == k) {                                           \
+    hipLaunchKernelGGL((dp_i32_kernel<l, k>), dim3(grid), dim3(kWave), 0, stream, p); \
+    return hipGetLastError();                                                   \
+  }
+  SOAPDP_I32_SHAPES(X)
+#undef X
+  return hipErrorInvalidValue;
+}
+
+int occupancy_dp_i32(Shape s) {
+  int blocks = 0;
+#define X(l, k)                                                                               \
+  if (s.lanes == l && s.cells == k) {                                                         \
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, dp_i32_kernel<l, k>, kWave, 0) \
+        != hipSuccess)                                                                        \
+      blocks = 0;                                                                             \
+    return blocks;                                                                            \
+  }
+  SOAPDP_I32_SHAPES(X)
+#undef X
+  return 0;
+}
+
+}  // namespace soapdp

@@ -1,0 +1,86 @@
+"""CPU-side checks of the C ABI library: it loads, exports every function the
+public headers declare, and rejects bad arguments before touching a device.
+No compute calls are made here."""
+import ctypes
+import glob
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+from paper_1302_5507_amd import binding
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    names = set()
+    for h in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        text = open(h).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        names |= set(re.findall(r"\b(soap_dp_\w+)\s*\(", text))
+    return names
+
+
+def test_library_built_and_exports_declared_symbols():
+    assert os.path.exists(binding.LIB_PATH), "build with python -m paper_1302_5507_amd.build"
+    declared = _declared()
+    assert declared, "no declarations found"
+    out = subprocess.run(["nm", "-D", "--defined-only", binding.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r"\b(soap_dp_\w+)\b", out))
+    assert declared <= exported, declared - exported
+    lib = binding.lib()
+    for name in declared:
+        assert hasattr(lib, name)
+    assert set(binding.EXPORTED) <= declared
+
+
+def test_library_contains_gfx950_code():
+    # the offload bundle embedded by hipcc names its target
+    data = open(binding.LIB_PATH, "rb").read()
+    assert b"amdgcn-amd-amdhsa--gfx950" in data
+
+
+def test_strerror_and_null_arguments():
+    lib = binding.lib()
+    assert binding.soap_dp_strerror(0) == "ok"
+    for code in (-1, -2, -3, -4):
+        assert binding.soap_dp_strerror(code) != "unknown error"
+    assert lib.soap_dp_align_batch(None, None, None, None, None, 0) == binding.SOAP_DP_EINVAL
+    assert lib.soap_dp_create(None, 0) == binding.SOAP_DP_EINVAL
+    assert lib.soap_dp_destroy(None) == binding.SOAP_DP_EINVAL
+    assert binding.soap_dp_workspace_bytes(None, 10, 100, 250, 0) == 0
+    assert lib.soap_dp_reserve(None, 10, 100, 250, 0) == binding.SOAP_DP_EINVAL
+    assert binding.soap_dp_last_hip_error(None) == 0
+
+
+def _unpack(words, count):
+    w = np.asarray(words, dtype=np.uint32)
+    k = np.arange(count)
+    return ((w[k // 16] >> (2 * (k % 16)).astype(np.uint32)) & 3).astype(np.uint8)
+
+
+def test_pack_words_roundtrip():
+    rng = np.random.default_rng(0)
+    for n in (0, 1, 15, 16, 17, 1000):
+        codes = rng.integers(0, 4, size=n).astype(np.uint8)
+        words = binding.pack_words(codes)
+        assert words.size == (n + 15) // 16
+        assert np.array_equal(_unpack(words, n), codes)
+    # base k of a word sits in bits [2k, 2k+2)
+    assert binding.pack_words(np.array([1, 2, 3], np.uint8))[0] == 1 | 2 << 2 | 3 << 4
+
+
+def test_pack_reads_word_aligned():
+    rng = np.random.default_rng(1)
+    lens = np.array([5, 16, 17, 0, 33, 1])
+    offs = np.concatenate([[0], np.cumsum(lens)[:-1]])
+    codes = rng.integers(0, 4, size=int(lens.sum())).astype(np.uint8)
+    words, woff = binding.pack_reads(codes, offs, lens)
+    assert list(woff) == [0, 1, 2, 4, 4, 7]
+    for t in range(len(lens)):
+        got = _unpack(words[int(woff[t]):], int(lens[t]))
+        assert np.array_equal(got, codes[offs[t]:offs[t] + lens[t]])

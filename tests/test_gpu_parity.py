@@ -1,0 +1,116 @@
+"""GPU parity: every score, end, begin, CIGAR and status from the HIP path,
+called through the C ABI, equals the CPU oracle bit for bit."""
+import numpy as np
+import pytest
+
+from paper_1302_5507_amd import binding, workloads
+from tests.conftest import CONFIG_SCORING, SCORING_SETS
+from tests.gpu_util import assert_same, gpu_align, oracle_align
+
+pytestmark = pytest.mark.gpu
+
+
+def test_config1_plain_full():
+    w = workloads.config1()
+    g = gpu_align(w, CONFIG_SCORING)
+    assert_same(g, oracle_align(w, CONFIG_SCORING), label="config1")
+
+
+@pytest.mark.parametrize("sc", SCORING_SETS)
+def test_random_mixed_small(sc):
+    rng = np.random.default_rng(abs(hash(sc)) % 2**32)
+    w = workloads.random_tasks(rng, 3000, n_range=(1, 48), m_range=(1, 160))
+    g = gpu_align(w, sc)
+    assert_same(g, oracle_align(w, sc), label=f"random {sc}")
+
+
+@pytest.mark.parametrize("max_n", [8, 9, 13, 36, 50, 52, 75, 100, 104, 150, 152, 250, 256, 300, 512])
+def test_every_plain_shape(max_n):
+    """The plain kernel's shape follows max_n; cover each compiled shape with
+    reads from 1 to max_n bases (ragged against the shape's columns)."""
+    rng = np.random.default_rng(max_n)
+    w = workloads.random_tasks(rng, 700, n_range=(1, max_n), m_range=(1, 400), genome_len=20000)
+    g = gpu_align(w, CONFIG_SCORING, max_n=max_n)
+    assert_same(g, oracle_align(w, CONFIG_SCORING, stride=2 * max_n), label=f"max_n={max_n}")
+
+
+def test_edge_lengths():
+    rng = np.random.default_rng(5)
+    g = rng.integers(0, 4, size=20000).astype(np.uint8)
+    pairs = [(1, 1), (1, 8192), (512, 1), (512, 512), (512, 8192), (2, 1), (100, 8192), (17, 16),
+             (16, 17), (64, 64), (65, 3)]
+    reads, wins = [], []
+    for n, m in pairs:
+        s = int(rng.integers(0, 20000 - m))
+        win = g[s:s + m]
+        r = np.resize(win, n).copy() if rng.random() < 0.5 else rng.integers(0, 4, size=n).astype(np.uint8)
+        reads.append(r)
+        wins.append((s, m))
+    n = np.array([len(r) for r in reads])
+    w = workloads.Workload("edge", g, np.concatenate(reads), np.concatenate([[0], np.cumsum(n)[:-1]]),
+                           n.astype(np.int32), np.array([s for s, _ in wins]),
+                           np.array([m for _, m in wins], dtype=np.int32), np.full(len(n), -1))
+    got = gpu_align(w, CONFIG_SCORING, max_n=512, max_m=8192)
+    assert_same(got, oracle_align(w, CONFIG_SCORING, stride=1024), label="edges")
+
+
+def test_invalid_tasks_get_status_and_zero_outputs():
+    rng = np.random.default_rng(6)
+    w = workloads.random_tasks(rng, 200, n_range=(1, 40), m_range=(1, 80))
+    w.read_len[3] = 0          # empty read
+    w.ref_len[7] = 0           # empty window
+    w.read_len[11] = 41        # above max_n
+    w.ref_len[13] = 81         # above max_m
+    ref = oracle_align(w, CONFIG_SCORING, stride=80)
+    got = gpu_align(w, CONFIG_SCORING, max_n=40, max_m=80)
+    bad = [3, 7, 11, 13]
+    assert [int(got["status"][t]) for t in bad] == [binding.TASK_INVALID_LEN] * 4
+    for f in ("score", "ref_begin", "ref_end", "cigar_len"):
+        assert all(int(got[f][t]) == 0 for t in bad)
+    ok = np.setdiff1d(np.arange(w.n_tasks), bad)
+    sub = oracle_align(w, CONFIG_SCORING, idx=ok, stride=80)
+    assert_same(got, sub, idx=ok, label="valid rest")
+    del ref
+
+
+def test_window_outside_buffer_is_reported():
+    rng = np.random.default_rng(7)
+    w = workloads.random_tasks(rng, 64, n_range=(1, 20), m_range=(1, 30), genome_len=400)
+    w.ref_off[5] = 10**9        # far outside the genome buffer
+    got = gpu_align(w, CONFIG_SCORING)
+    assert int(got["status"][5]) == binding.TASK_INVALID_OFFSET
+    ok = np.setdiff1d(np.arange(w.n_tasks), [5])
+    assert_same(got, oracle_align(w, CONFIG_SCORING, idx=ok), idx=ok, label="rest")
+
+
+@pytest.mark.parametrize("k", [100, 128])
+def test_scaled_scoring(k):
+    """x k scaling of all scores: same alignments, k times the score."""
+    sc = tuple(k * x for x in CONFIG_SCORING)
+    w = workloads.config3(n_reads=4000)
+    g = gpu_align(w, sc)
+    ref = oracle_align(w, sc)
+    assert_same(g, ref, label=f"x{k}")
+    base = oracle_align(w, CONFIG_SCORING)
+    assert np.array_equal(ref.score, k * base.score)
+
+
+def test_order_invariance():
+    w = workloads.config3(n_reads=3000)
+    g1 = gpu_align(w, CONFIG_SCORING)
+    perm = np.random.default_rng(9).permutation(w.n_tasks)
+    g2 = gpu_align(w.subset(perm), CONFIG_SCORING)
+    for f in ("score", "ref_begin", "ref_end", "cigar_len", "status"):
+        assert np.array_equal(g1[f][perm], g2[f])
+
+
+def test_config2_full_size_sampled():
+    """1,000,000 reads x 100 bp vs 250 bp windows in one plain launch; the
+    oracle checks a seeded sample of 40,000 tasks plus the first and last."""
+    w = workloads.config2()
+    g = gpu_align(w, CONFIG_SCORING)
+    rng = np.random.default_rng(2)
+    idx = np.unique(np.concatenate([rng.choice(w.n_tasks, 40000, replace=False),
+                                    np.arange(64), np.arange(w.n_tasks - 64, w.n_tasks)]))
+    assert_same(g, oracle_align(w, CONFIG_SCORING, idx=idx), idx=idx, label="config2 sample")
+    assert (g["status"] == 0).all()
