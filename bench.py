@@ -49,7 +49,9 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--form", choices=["plain", "batched"], default="plain")
-    ap.add_argument("--cpu-tasks", type=int, default=300_000)
+    ap.add_argument("--cpu-tasks", type=int, default=1_000_000)
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
+                    help="only run device-to-device copies of BYTES (HBM counter calibration)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -62,6 +64,15 @@ def main():
     from paper_1302_5507_amd import binding, workloads
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.calibrate_copy:
+        # a plain copy of known size: reads and writes BYTES each per launch
+        a = torch.empty(args.calibrate_copy // 4, dtype=torch.int32, device="cuda").fill_(1)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes": args.calibrate_copy}), flush=True)
+        return
     w = workloads.config2()
     al = binding.Aligner(0)
     dw = binding.DeviceWorkload(w)
