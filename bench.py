@@ -1,12 +1,15 @@
-"""Benchmark: GCUPS with traceback of the batched read-vs-window affine-gap
-alignment on one MI355X, on the mate-rescue workload (1,000,000 reads x 100 bp
-against 250 bp windows; seeded synthetic data).
+"""Benchmark: GCUPS with traceback of batched read-vs-window affine-gap
+alignment on one MI355X (seeded synthetic data).
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--form plain|batched]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload config2|config3|config5]
 
-A step is one soap_dp_align_batch call over the whole batch (fill, traceback
-and CIGAR for every task), inputs already resident in device memory.  Prints
-one JSON line.
+Default workload: the mate-rescue batch, 1,000,000 reads x 100 bp against
+250 bp windows, aligned by the plain one-launch int32 kernel (`value`); the
+batched form (length classes, packed int16 with int32 re-run, persistent
+kernels, graph replay, autotuned shapes) runs on the same data and is
+reported beside it.  A step is one soap_dp_align_batch call over the whole
+batch (fill, traceback and CIGAR of every task), inputs resident in device
+memory.  Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -28,6 +31,15 @@ OPS_PER_CELL = 14            # 10 score operations + 4 decision comparisons per 
 PEAK_INT32_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12   # CUs x SIMDs x lanes x clock = 39.3 T lane-ops/s
 PEAK_INT16_TOPS = 2 * PEAK_INT32_TOPS            # packed 2 x int16 per lane
 
+WORKLOADS = {
+    "config2": ("mate-rescue: 1,000,000 reads x 100 bp vs 250 bp windows from a 1 Mbp random "
+                "genome (2% subs, 0.5% indels, 10% random reads)", "config2", "plain"),
+    "config3": ("uneven: 2,000,000 reads, n uniform over {36,50,75,100,150,250}, m = n + 160 "
+                "(4% subs, 0.5% indels up to 30 bp)", "config3", "batched"),
+    "config5": ("low-similarity: 500,000 reads x 150 bp at 60-75% identity vs 1,000 bp windows",
+                "config5", "batched"),
+}
+
 
 def cpu_baseline(w, tasks: int):
     import oracle
@@ -37,10 +49,32 @@ def cpu_baseline(w, tasks: int):
     t0 = time.perf_counter()
     oracle.align_workload(w, oracle.scoring(*SCORING), idx=idx, n_threads=threads)
     dt = time.perf_counter() - t0
+    what = "all" if idx.size == w.n_tasks else f"first {idx.size:,}"
     return {"value": round(cells / dt / 1e9, 4), "unit": "GCUPS", "cores": threads,
             "kind": "oracle",
-            "sample": f"first {idx.size:,} tasks of the same workload ({cells:.3g} cells), "
-                      f"three-table int32 C oracle with traceback, {threads} threads, {dt:.1f} s"}
+            "sample": f"{what} tasks of the same workload ({cells:.3g} cells), three-table int32 "
+                      f"C oracle with traceback, {threads} threads, {dt:.1f} s"}
+
+
+def time_form(al, dw, res, flags, steps, warmup):
+    import torch
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        al.align(dw, SCORING, flags=flags, res=res)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        ev[k][0].record(stream)
+        al.align(dw, SCORING, flags=flags, res=res)
+        ev[k][1].record(stream)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    out = res.to_host()
+    assert (out["status"] != 1).all() and (out["status"] != 3).all(), "invalid tasks in bench"
+    return elapsed / steps, float(np.mean([a.elapsed_time(b) for a, b in ev]))
 
 
 def main():
@@ -48,11 +82,13 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--form", choices=["plain", "batched"], default="plain")
+    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="config2")
+    ap.add_argument("--form", choices=["plain", "batched", "both"], default="both")
     ap.add_argument("--cpu-tasks", type=int, default=1_000_000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--tune-cache", default=os.environ.get("SOAPDP_TUNE_CACHE"))
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run device-to-device copies of BYTES (HBM counter calibration)")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build measures one GPU; the tasks are independent and would be "
@@ -73,58 +109,45 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"calibrate_copy_bytes": args.calibrate_copy}), flush=True)
         return
-    w = workloads.config2()
+
+    desc, gen, headline = WORKLOADS[args.workload]
+    w = getattr(workloads, gen)()
     al = binding.Aligner(0)
     dw = binding.DeviceWorkload(w)
     res = binding.DeviceResult(w.n_tasks, 2 * dw.max_n)
-    flags = binding.PLAIN if args.form == "plain" else binding.BATCHED
-    stream = torch.cuda.current_stream()
 
-    for _ in range(args.warmup):
-        al.align(dw, SCORING, flags=flags, res=res)
-    torch.cuda.synchronize()
+    forms = {}
+    if args.form in ("batched", "both"):
+        al.autotune(args.tune_cache)
+        s, k = time_form(al, dw, res, binding.BATCHED, args.steps, args.warmup)
+        forms["batched"] = (s, k)
+    if args.form in ("plain", "both"):
+        s, k = time_form(al, dw, res, binding.PLAIN, args.steps, args.warmup)
+        forms["plain"] = (s, k)
+    main_form = headline if headline in forms else next(iter(forms))
 
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-          for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        ev[k][0].record(stream)
-        al.align(dw, SCORING, flags=flags, res=res)
-        ev[k][1].record(stream)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    launch_ms = [a.elapsed_time(b) for a, b in ev]
+    def summary(form):
+        s, k = forms[form]
+        peak = PEAK_INT32_TOPS if form == "plain" else PEAK_INT16_TOPS
+        achieved = OPS_PER_CELL * w.cells / (k * 1e-3) / 1e12
+        return s, k, peak, achieved
 
-    out = res.to_host()
-    assert (out["status"] == 0).all(), "bench run produced invalid tasks"
-
-    ms_per_step = elapsed * 1e3 / args.steps
-    gcups = w.cells / (ms_per_step * 1e-3) / 1e9
-    kern_ms = float(np.mean(launch_ms))
-    achieved = OPS_PER_CELL * w.cells / (kern_ms * 1e-3) / 1e12
-    peak = PEAK_INT32_TOPS if args.form == "plain" else PEAK_INT16_TOPS
+    s, k, peak, achieved = summary(main_form)
     line = {
         "metric": METRIC,
-        "value": round(gcups, 2),
+        "value": round(w.cells / s / 1e9, 2),
         "unit": "GCUPS",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 3),
+        "ms_per_step": round(s * 1e3, 3),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "int32" if args.form == "plain" else "int16+int32",
+        "dtype": "int32" if main_form == "plain" else "int16+int32",
         "data": "synthetic",
-        "config": {
-            "workload": "mate-rescue: 1,000,000 reads x 100 bp vs 250 bp windows from a 1 Mbp "
-                        "random genome (2% subs, 0.5% indels, 10% random reads)",
-            "form": args.form,
-            "n_tasks": w.n_tasks,
-            "cells": w.cells,
-            "scoring": list(SCORING),
-        },
+        "config": {"workload": desc, "form": main_form, "n_tasks": w.n_tasks, "cells": w.cells,
+                   "scoring": list(SCORING)},
         "roofline": {
             "bound": "alu",
             "achieved": round(achieved, 3),
@@ -133,9 +156,15 @@ def main():
             "frac": round(achieved / peak, 4),
             "traffic": None,
             "ops_per_cell": OPS_PER_CELL,
-            "kernel_ms": round(kern_ms, 3),
+            "kernel_ms": round(k, 3),
         },
+        "forms": {},
     }
+    for form in forms:
+        fs, fk, fpeak, fach = summary(form)
+        line["forms"][form] = {"gcups": round(w.cells / fs / 1e9, 2), "ms_per_step": round(fs * 1e3, 3),
+                               "device_ms": round(fk, 3), "valu_frac": round(fach / fpeak, 4),
+                               "peak_tops": round(fpeak, 1)}
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(w, args.cpu_tasks)
     print(json.dumps(line), flush=True)

@@ -160,6 +160,39 @@ size_t soap_dp_workspace_bytes(const soap_dp_ctx *ctx, int64_t n_tasks, int32_t 
 int soap_dp_reserve(soap_dp_ctx *ctx, int64_t n_tasks, int32_t max_n, int32_t max_m,
                     uint32_t flags);
 
+/*
+ * Length classes of the batched form.  Each task goes to the smallest class
+ * whose capacity (upper bound on read length) holds its read: an int16 class
+ * when all of the task's values fit int16, else an int32 class.  Each class
+ * runs one kernel shape: `lanes` lanes of a 64-wide wavefront cooperate on a
+ * task, each owning `cells` read columns (lanes * cells >= capacity).
+ */
+typedef struct {
+  int32_t precision;  /* 16 or 32 */
+  int32_t capacity;
+  int32_t lanes;
+  int32_t cells;
+} soap_dp_class_info;
+
+/* Choose the fastest compiled shape for every class by timing each candidate
+ * on synthetic reads of the class's capacity on this device.  With a
+ * non-NULL `cache_path`, a cache written earlier for the same device kind is
+ * loaded instead (unless `force`), and a fresh result is written there
+ * (JSON).  Synchronises the device; replaces cached graphs. */
+int soap_dp_autotune(soap_dp_ctx *ctx, const char *cache_path, int force);
+
+/* Copy up to n_max class descriptions; returns the number of classes. */
+int soap_dp_get_classes(const soap_dp_ctx *ctx, soap_dp_class_info *out, int32_t n_max);
+
+/* Set the shape of the class (precision, capacity); the shape must be a
+ * compiled one with lanes * cells >= capacity (see soap_dp_list_shapes). */
+int soap_dp_set_class_shape(soap_dp_ctx *ctx, int32_t precision, int32_t capacity, int32_t lanes,
+                            int32_t cells);
+
+/* The compiled shapes of a precision (capacity = lanes * cells); returns the
+ * count, writes up to n_max. */
+int soap_dp_list_shapes(int32_t precision, soap_dp_class_info *out, int32_t n_max);
+
 /* Human-readable text for an error code. */
 const char *soap_dp_strerror(int code);
 

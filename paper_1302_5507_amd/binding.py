@@ -34,7 +34,8 @@ BATCHED = 1
 
 EXPORTED = [
     "soap_dp_create", "soap_dp_destroy", "soap_dp_align_batch", "soap_dp_workspace_bytes",
-    "soap_dp_reserve", "soap_dp_strerror", "soap_dp_last_hip_error",
+    "soap_dp_reserve", "soap_dp_strerror", "soap_dp_last_hip_error", "soap_dp_autotune",
+    "soap_dp_get_classes", "soap_dp_set_class_shape", "soap_dp_list_shapes",
 ]
 
 
@@ -56,6 +57,14 @@ class Result(ctypes.Structure):
                 ("ref_end", ctypes.c_void_p), ("cigar", ctypes.c_void_p),
                 ("cigar_stride", ctypes.c_int32), ("cigar_len", ctypes.c_void_p),
                 ("status", ctypes.c_void_p)]
+
+
+class ClassInfo(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("capacity", ctypes.c_int32),
+                ("lanes", ctypes.c_int32), ("cells", ctypes.c_int32)]
+
+    def as_tuple(self):
+        return (self.precision, self.capacity, self.lanes, self.cells)
 
 
 _lib = None
@@ -98,6 +107,15 @@ def lib():
         L.soap_dp_strerror.restype = ctypes.c_char_p
         L.soap_dp_last_hip_error.argtypes = [vp]
         L.soap_dp_last_hip_error.restype = ctypes.c_int
+        L.soap_dp_autotune.argtypes = [vp, ctypes.c_char_p, ctypes.c_int]
+        L.soap_dp_autotune.restype = ctypes.c_int
+        L.soap_dp_get_classes.argtypes = [vp, ctypes.POINTER(ClassInfo), ctypes.c_int32]
+        L.soap_dp_get_classes.restype = ctypes.c_int
+        L.soap_dp_set_class_shape.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                              ctypes.c_int32]
+        L.soap_dp_set_class_shape.restype = ctypes.c_int
+        L.soap_dp_list_shapes.argtypes = [ctypes.c_int32, ctypes.POINTER(ClassInfo), ctypes.c_int32]
+        L.soap_dp_list_shapes.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -135,6 +153,33 @@ def soap_dp_strerror(code: int) -> str:
 
 def soap_dp_last_hip_error(ctx) -> int:
     return lib().soap_dp_last_hip_error(ctx)
+
+
+def soap_dp_autotune(ctx, cache_path=None, force=False) -> int:
+    path = cache_path.encode() if cache_path else None
+    return lib().soap_dp_autotune(ctx, path, int(bool(force)))
+
+
+def soap_dp_get_classes(ctx):
+    n = lib().soap_dp_get_classes(ctx, None, 0)
+    if n < 0:
+        raise SoapDpError(n, "soap_dp_get_classes")
+    arr = (ClassInfo * max(n, 1))()
+    lib().soap_dp_get_classes(ctx, arr, n)
+    return [arr[k].as_tuple() for k in range(n)]
+
+
+def soap_dp_set_class_shape(ctx, precision, capacity, lanes, cells) -> int:
+    return lib().soap_dp_set_class_shape(ctx, int(precision), int(capacity), int(lanes), int(cells))
+
+
+def soap_dp_list_shapes(precision):
+    n = lib().soap_dp_list_shapes(int(precision), None, 0)
+    if n < 0:
+        raise SoapDpError(n, "soap_dp_list_shapes")
+    arr = (ClassInfo * max(n, 1))()
+    lib().soap_dp_list_shapes(int(precision), arr, n)
+    return [arr[k].as_tuple() for k in range(n)]
 
 
 # ---------------------------------------------------------------- packing
@@ -251,6 +296,20 @@ class Aligner:
             self.close()
         except Exception:
             pass
+
+    def autotune(self, cache_path=None, force=False):
+        rc = soap_dp_autotune(self.ctx, cache_path, force)
+        if rc != SOAP_DP_OK:
+            raise SoapDpError(rc, "soap_dp_autotune")
+        return soap_dp_get_classes(self.ctx)
+
+    def classes(self):
+        return soap_dp_get_classes(self.ctx)
+
+    def set_class_shape(self, precision, capacity, lanes, cells):
+        rc = soap_dp_set_class_shape(self.ctx, precision, capacity, lanes, cells)
+        if rc != SOAP_DP_OK:
+            raise SoapDpError(rc, "soap_dp_set_class_shape")
 
     def align(self, dw: DeviceWorkload, scoring=(1, -3, -5, -2), flags=PLAIN, res=None,
               stream=None, max_n=None, max_m=None) -> DeviceResult:

@@ -1,34 +1,85 @@
 // Host side of the C ABI declared in include/soap_dp.h: argument checking,
-// the context and its workspace, kernel-shape choice and launches.
+// the context and its workspace, kernel-shape choice, the batched form's
+// class launches and graph cache, and the autotuner.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
-#include <mutex>
+#include <iterator>
 #include <new>
+#include <string>
+#include <vector>
 
 #include "../../include/soap_dp.h"
+#include "batch.h"
 #include "dp_internal.h"
 
 using namespace soapdp;
+
+namespace {
+
+constexpr size_t kScratchCap = size_t(8) << 30;   // decision-bit scratch budget
+constexpr int kGraphCacheMax = 16;
+
+struct ClassSpec {
+  int prec;    // 16 or 32
+  int cap;     // upper bound on read length
+  Shape shape; // current kernel shape
+};
+
+// Default classes: int16 by ascending capacity, then the int32 classes that
+// serve tasks outside the int16 range.  Shapes are replaced by the autotuner.
+const ClassSpec kDefaultClasses[] = {
+    {16, 16, {2, 8}},    {16, 32, {4, 8}},    {16, 40, {4, 10}},   {16, 56, {8, 7}},
+    {16, 64, {8, 8}},    {16, 80, {8, 10}},   {16, 104, {8, 13}},  {16, 128, {8, 16}},
+    {16, 152, {8, 19}},  {16, 192, {16, 12}}, {16, 256, {16, 16}}, {16, 320, {32, 10}},
+    {16, 384, {32, 12}}, {16, 512, {32, 16}},
+    {32, 36, {4, 9}},    {32, 56, {8, 7}},    {32, 80, {8, 10}},   {32, 104, {8, 13}},
+    {32, 152, {8, 19}},  {32, 256, {16, 16}}, {32, 512, {32, 16}},
+};
+
+struct GraphKey {
+  soap_dp_batch in;
+  soap_dp_scoring sc;
+  soap_dp_result out;
+  uint64_t epoch;
+};
+
+struct GraphEntry {
+  GraphKey key;
+  hipGraphExec_t exec;
+  uint64_t last_use;
+};
+
+bool same_key(const GraphKey &a, const GraphKey &b) { return std::memcmp(&a, &b, sizeof(GraphKey)) == 0; }
+
+}  // namespace
 
 struct soap_dp_ctx {
   int device = 0;
   int cu_count = 0;
   int last_hip_error = 0;
+  std::string arch;
+  // workspace
   void *scratch = nullptr;
   size_t scratch_bytes = 0;
-  void *small = nullptr;       // counters and other small device state
-  size_t small_bytes = 0;
+  int32_t *small = nullptr;          // hist | offset | cursor | work_counter
+  uint8_t *task_class = nullptr;
+  int32_t *task_list = nullptr;
+  int64_t task_cap = 0;
+  // batched form
+  std::vector<ClassSpec> classes;
+  hipStream_t capture_stream = nullptr;
+  std::vector<GraphEntry> graphs;
+  uint64_t epoch = 1;   // bumped whenever buffers or shapes change
+  uint64_t use_clock = 0;
+  bool use_graphs = true;
 };
 
 namespace {
-
-constexpr size_t kSmallBytes = 4096;
-
-// Scratch budget: the decision bits of every workgroup in flight.
-constexpr size_t kScratchCap = size_t(8) << 30;
 
 struct DeviceGuard {
   int prev = -1;
@@ -66,8 +117,25 @@ int batch_ok(const soap_dp_batch *in, const soap_dp_result *out) {
   return SOAP_DP_OK;
 }
 
-// Plain form: the compiled shape covering max_n with the least work per task
-// (columns times sweep steps, the anti-diagonal skew included).
+bool shape_compiled(int prec, Shape s) {
+  int cnt = 0;
+  const Shape *all = prec == 16 ? shapes_i16(&cnt) : shapes_i32(&cnt);
+  for (int k = 0; k < cnt; ++k)
+    if (all[k].lanes == s.lanes && all[k].cells == s.cells) return true;
+  return false;
+}
+
+int occupancy(int prec, Shape s) {
+  const int o = prec == 16 ? occupancy_dp_i16(s) : occupancy_dp_i32(s);
+  return o < 1 ? 1 : o;
+}
+
+uint64_t slot_dwords(int prec, Shape s, int32_t max_m) {
+  return prec == 16 ? slot_dwords_i16(s, max_m) : slot_dwords_i32(s, max_m);
+}
+
+// Plain form: the compiled int32 shape covering max_n with the least work
+// per task (columns times sweep steps, the anti-diagonal skew included).
 Shape plain_shape(int32_t max_n, int32_t max_m) {
   int cnt = 0;
   const Shape *all = shapes_i32(&cnt);
@@ -83,39 +151,39 @@ Shape plain_shape(int32_t max_n, int32_t max_m) {
   return best;
 }
 
-uint64_t slot_dwords_for(Shape s, int32_t max_m) {
-  const uint64_t steps = uint64_t(max_m) + uint64_t(s.lanes) - 1;
-  const uint64_t w = uint64_t((s.cells + 7) / 8);
-  return steps * w * kWave;
-}
-
-int grid_for(const soap_dp_ctx *ctx, Shape s, int64_t n_tasks, int32_t max_m) {
-  const int64_t per_wave = kWave / s.lanes;
+// Persistent grid of one launch: every resident workgroup slot, limited by
+// the scratch budget and by the work available.
+int grid_for(const soap_dp_ctx *ctx, int prec, Shape s, int64_t n_tasks, int32_t max_m) {
+  const int64_t per_wave = (prec == 16 ? 2 : 1) * kWave / s.lanes;
   const int64_t items = (n_tasks + per_wave - 1) / per_wave;
-  int occ = occupancy_dp_i32(s);
-  if (occ < 1) occ = 1;
-  int64_t grid = int64_t(ctx->cu_count) * occ;
-  const uint64_t slot_bytes = slot_dwords_for(s, max_m) * 4;
-  const int64_t cap = int64_t(kScratchCap / slot_bytes);
-  grid = std::min<int64_t>(grid, std::max<int64_t>(cap, 1));
+  int64_t grid = int64_t(ctx->cu_count) * occupancy(prec, s);
+  const uint64_t slot_bytes = slot_dwords(prec, s, max_m) * 4;
+  grid = std::min<int64_t>(grid, std::max<int64_t>(int64_t(kScratchCap / slot_bytes), 1));
   grid = std::min<int64_t>(grid, std::max<int64_t>(items, 1));
   return int(grid);
 }
 
 int hip_fail(soap_dp_ctx *ctx, hipError_t e) {
   ctx->last_hip_error = int(e);
+  (void)hipGetLastError();
   return SOAP_DP_EHIP;
+}
+
+void clear_graphs(soap_dp_ctx *ctx) {
+  for (auto &g : ctx->graphs) (void)hipGraphExecDestroy(g.exec);
+  ctx->graphs.clear();
+  ++ctx->epoch;
 }
 
 int ensure_scratch(soap_dp_ctx *ctx, size_t bytes) {
   if (bytes <= ctx->scratch_bytes) return SOAP_DP_OK;
   if (ctx->scratch) {
-    // earlier work may still read the old buffer
-    if (hipDeviceSynchronize() != hipSuccess) return SOAP_DP_EHIP;
+    if (hipDeviceSynchronize() != hipSuccess) return SOAP_DP_EHIP;   // earlier work may read it
     (void)hipFree(ctx->scratch);
     ctx->scratch = nullptr;
     ctx->scratch_bytes = 0;
   }
+  clear_graphs(ctx);
   void *p = nullptr;
   if (hipMalloc(&p, bytes) != hipSuccess) {
     (void)hipGetLastError();
@@ -123,6 +191,30 @@ int ensure_scratch(soap_dp_ctx *ctx, size_t bytes) {
   }
   ctx->scratch = p;
   ctx->scratch_bytes = bytes;
+  return SOAP_DP_OK;
+}
+
+int ensure_task_buffers(soap_dp_ctx *ctx, int64_t n_tasks) {
+  if (n_tasks <= ctx->task_cap) return SOAP_DP_OK;
+  if (ctx->task_list) {
+    if (hipDeviceSynchronize() != hipSuccess) return SOAP_DP_EHIP;
+    (void)hipFree(ctx->task_list);
+    (void)hipFree(ctx->task_class);
+    ctx->task_list = nullptr;
+    ctx->task_class = nullptr;
+    ctx->task_cap = 0;
+  }
+  clear_graphs(ctx);
+  const int64_t cap = std::max<int64_t>(n_tasks, 1024);
+  if (hipMalloc(reinterpret_cast<void **>(&ctx->task_list), size_t(cap) * 4) != hipSuccess ||
+      hipMalloc(reinterpret_cast<void **>(&ctx->task_class), size_t(cap)) != hipSuccess) {
+    (void)hipGetLastError();
+    if (ctx->task_list) (void)hipFree(ctx->task_list);
+    ctx->task_list = nullptr;
+    ctx->task_class = nullptr;
+    return SOAP_DP_ENOMEM;
+  }
+  ctx->task_cap = cap;
   return SOAP_DP_OK;
 }
 
@@ -150,15 +242,28 @@ DpParams make_params(const soap_dp_batch *in, const soap_dp_scoring *sc, const s
   p.cigar_stride = out->cigar_stride;
   p.cigar_len = out->cigar_len;
   p.status = out->status;
+  p.ok_status = kTaskOk;
   return p;
+}
+
+hipError_t launch_shape(int prec, Shape s, int grid, hipStream_t stream, const DpParams &p) {
+  return prec == 16 ? launch_dp_i16(s, grid, stream, p) : launch_dp_i32(s, grid, stream, p);
+}
+
+// ------------------------------------------------------------------ plain
+
+size_t plain_scratch_bytes(const soap_dp_ctx *ctx, int64_t n_tasks, int32_t max_n, int32_t max_m) {
+  const Shape s = plain_shape(max_n, max_m);
+  if (s.lanes == 0) return 0;
+  return size_t(grid_for(ctx, 32, s, n_tasks, max_m)) * slot_dwords(32, s, max_m) * 4;
 }
 
 int align_plain(soap_dp_ctx *ctx, const soap_dp_batch *in, const soap_dp_scoring *sc,
                 const soap_dp_result *out, hipStream_t stream) {
   const Shape s = plain_shape(in->max_n, in->max_m);
   if (s.lanes == 0) return SOAP_DP_EINVAL;
-  const int grid = grid_for(ctx, s, in->n_tasks, in->max_m);
-  const uint64_t slot = slot_dwords_for(s, in->max_m);
+  const int grid = grid_for(ctx, 32, s, in->n_tasks, in->max_m);
+  const uint64_t slot = slot_dwords(32, s, in->max_m);
   const int rc = ensure_scratch(ctx, size_t(grid) * slot * 4);
   if (rc) return rc;
   DpParams p = make_params(in, sc, out);
@@ -167,6 +272,340 @@ int align_plain(soap_dp_ctx *ctx, const soap_dp_batch *in, const soap_dp_scoring
   const hipError_t e = launch_dp_i32(s, grid, stream, p);
   if (e != hipSuccess) return hip_fail(ctx, e);
   return SOAP_DP_OK;
+}
+
+// ---------------------------------------------------------------- batched
+
+// Classes a batch with these bounds can populate: a class receives reads
+// longer than the previous class of its precision, so classes starting at or
+// above max_n stay empty; int32 classes are needed only if some read length
+// up to max_n falls outside the int16 range of its int16 class.
+std::vector<int> live_classes(const soap_dp_ctx *ctx, int32_t max_n, const soap_dp_scoring *sc) {
+  std::vector<int> live;
+  bool need32 = false;
+  int prev16 = 0;
+  for (size_t k = 0; k < ctx->classes.size(); ++k) {
+    const ClassSpec &c = ctx->classes[k];
+    if (c.prec != 16) continue;
+    if (prev16 < max_n) {
+      live.push_back(int(k));
+      const int32_t n_hi = std::min(c.cap, max_n);
+      if (!int16_fits(n_hi, c.shape.lanes * c.shape.cells, sc->match, sc->mismatch,
+                      sc->gap_open, sc->gap_extend))
+        need32 = true;
+    }
+    prev16 = c.cap;
+  }
+  if (need32) {
+    int prev32 = 0;
+    for (size_t k = 0; k < ctx->classes.size(); ++k) {
+      const ClassSpec &c = ctx->classes[k];
+      if (c.prec != 32) continue;
+      if (prev32 < max_n) live.push_back(int(k));
+      prev32 = c.cap;
+    }
+  }
+  return live;
+}
+
+size_t batched_scratch_bytes(const soap_dp_ctx *ctx, int64_t n_tasks, int32_t max_m,
+                             const std::vector<int> &live) {
+  size_t b = 0;
+  for (int k : live) {
+    const ClassSpec &c = ctx->classes[size_t(k)];
+    const size_t s = size_t(grid_for(ctx, c.prec, c.shape, n_tasks, max_m)) *
+                     slot_dwords(c.prec, c.shape, max_m) * 4;
+    b = std::max(b, s);
+  }
+  return b;
+}
+
+ClassTable class_table(const soap_dp_ctx *ctx) {
+  ClassTable ct{};
+  ct.count = int32_t(ctx->classes.size());
+  for (size_t k = 0; k < ctx->classes.size(); ++k) {
+    ct.cap[k] = ctx->classes[k].cap;
+    ct.cols[k] = ctx->classes[k].shape.lanes * ctx->classes[k].shape.cells;
+    ct.prec[k] = ctx->classes[k].prec;
+  }
+  return ct;
+}
+
+// Enqueue the whole batched sequence on `stream` (also used under capture,
+// so the grids are computed beforehand: no runtime queries in between).
+hipError_t enqueue_batched(soap_dp_ctx *ctx, const soap_dp_batch *in, const soap_dp_scoring *sc,
+                           const soap_dp_result *out, const std::vector<int> &live,
+                           const std::vector<int> &grids, hipStream_t stream) {
+  DpParams p = make_params(in, sc, out);
+  BucketBuffers b{};
+  b.task_class = ctx->task_class;
+  b.task_list = ctx->task_list;
+  b.hist = ctx->small;
+  b.offset = ctx->small + kMaxClasses;
+  b.cursor = ctx->small + 2 * kMaxClasses;
+  b.work_counter = ctx->small + 3 * kMaxClasses;
+  hipError_t e = launch_bucketing(p, class_table(ctx), b, stream);
+  if (e != hipSuccess) return e;
+  p.scratch = static_cast<uint32_t *>(ctx->scratch);
+  p.task_list = ctx->task_list;
+  for (size_t li = 0; li < live.size(); ++li) {
+    const int k = live[li];
+    const ClassSpec &c = ctx->classes[size_t(k)];
+    DpParams q = p;
+    q.task_off = b.offset + k;
+    q.task_count = b.hist + k;
+    q.work_counter = b.work_counter + k;
+    q.slot_dwords = slot_dwords(c.prec, c.shape, in->max_m);
+    q.ok_status = c.prec == 16 ? kTaskOk : kTaskRedone;
+    e = launch_shape(c.prec, c.shape, grids[li], stream, q);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+int align_batched(soap_dp_ctx *ctx, const soap_dp_batch *in, const soap_dp_scoring *sc,
+                  const soap_dp_result *out, hipStream_t stream) {
+  const std::vector<int> live = live_classes(ctx, in->max_n, sc);
+  int rc = ensure_task_buffers(ctx, in->n_tasks);
+  if (rc) return rc;
+  rc = ensure_scratch(ctx, batched_scratch_bytes(ctx, in->n_tasks, in->max_m, live));
+  if (rc) return rc;
+  std::vector<int> grids;
+  for (int k : live) {
+    const ClassSpec &c = ctx->classes[size_t(k)];
+    grids.push_back(grid_for(ctx, c.prec, c.shape, in->n_tasks, in->max_m));
+  }
+  if (!ctx->use_graphs) {
+    const hipError_t e = enqueue_batched(ctx, in, sc, out, live, grids, stream);
+    return e == hipSuccess ? SOAP_DP_OK : hip_fail(ctx, e);
+  }
+  GraphKey key;
+  std::memset(&key, 0, sizeof(key));
+  key.in = *in;
+  key.sc = *sc;
+  key.out = *out;
+  key.epoch = ctx->epoch;
+  GraphEntry *hit = nullptr;
+  for (auto &g : ctx->graphs)
+    if (same_key(g.key, key)) { hit = &g; break; }
+  if (!hit) {
+    if (!ctx->capture_stream &&
+        hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking) != hipSuccess)
+      return hip_fail(ctx, hipGetLastError());
+    hipError_t e = hipStreamBeginCapture(ctx->capture_stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_fail(ctx, e);
+    const hipError_t le = enqueue_batched(ctx, in, sc, out, live, grids, ctx->capture_stream);
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(ctx->capture_stream, &graph);
+    if (le != hipSuccess || e != hipSuccess) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return hip_fail(ctx, le != hipSuccess ? le : e);
+    }
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return hip_fail(ctx, e);
+    if (int(ctx->graphs.size()) >= kGraphCacheMax) {
+      auto oldest = std::min_element(ctx->graphs.begin(), ctx->graphs.end(),
+                                     [](const GraphEntry &a, const GraphEntry &b) {
+                                       return a.last_use < b.last_use;
+                                     });
+      (void)hipGraphExecDestroy(oldest->exec);
+      ctx->graphs.erase(oldest);
+    }
+    ctx->graphs.push_back(GraphEntry{key, exec, 0});
+    hit = &ctx->graphs.back();
+  }
+  hit->last_use = ++ctx->use_clock;
+  const hipError_t e = hipGraphLaunch(hit->exec, stream);
+  if (e != hipSuccess) return hip_fail(ctx, e);
+  return SOAP_DP_OK;
+}
+
+// ---------------------------------------------------------------- autotune
+
+uint64_t splitmix(uint64_t &s) {
+  uint64_t z = (s += 0x9e3779b97f4a7c15ull);
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+  return z ^ (z >> 31);
+}
+
+struct TuneData {
+  uint32_t *reads = nullptr, *genome = nullptr;
+  uint64_t *rwo = nullptr, *rbo = nullptr;
+  int32_t *rl = nullptr, *ml = nullptr, *i32 = nullptr;
+  uint32_t *cigar = nullptr;
+  uint8_t *status = nullptr;
+  int64_t tasks = 0;
+  ~TuneData() {
+    for (void *q : {(void *)reads, (void *)genome, (void *)rwo, (void *)rbo, (void *)rl, (void *)ml,
+                    (void *)i32, (void *)cigar, (void *)status})
+      if (q) (void)hipFree(q);
+  }
+};
+
+// Synthetic tasks for timing one class: reads of length n copied from random
+// windows of length n + 160 with 5% substitutions.
+bool make_tune_data(TuneData &d, int32_t n, int64_t tasks) {
+  const int32_t m = n + 160;
+  const int64_t glen = 1 << 20;
+  uint64_t seed = 0x5eed0000u + uint64_t(n);
+  std::vector<uint8_t> g(static_cast<size_t>(glen));
+  for (auto &x : g) x = uint8_t(splitmix(seed) & 3);
+  const int32_t nw = (n + 15) / 16;
+  std::vector<uint32_t> gw(static_cast<size_t>(glen / 16), 0u), rw(static_cast<size_t>(tasks * nw), 0u);
+  for (int64_t k = 0; k < glen; ++k) gw[size_t(k / 16)] |= uint32_t(g[size_t(k)]) << (2 * (k % 16));
+  std::vector<uint64_t> rwo(static_cast<size_t>(tasks)), rbo(static_cast<size_t>(tasks));
+  std::vector<int32_t> rl(static_cast<size_t>(tasks), n), ml(static_cast<size_t>(tasks), m);
+  for (int64_t t = 0; t < tasks; ++t) {
+    const uint64_t off = splitmix(seed) % uint64_t(glen - m);
+    const uint64_t s = splitmix(seed) % 161;
+    rbo[size_t(t)] = off;
+    rwo[size_t(t)] = uint64_t(t) * uint64_t(nw);
+    for (int32_t q = 0; q < n; ++q) {
+      uint32_t b = g[size_t(off + s + uint64_t(q))];
+      if (splitmix(seed) % 100 < 5) b = (b + 1 + uint32_t(splitmix(seed) % 3)) & 3;
+      rw[size_t(t * nw + q / 16)] |= b << (2 * (q % 16));
+    }
+  }
+  auto up = [](void **dst, const void *src, size_t bytes) {
+    return hipMalloc(dst, bytes) == hipSuccess &&
+           hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice) == hipSuccess;
+  };
+  d.tasks = tasks;
+  return up((void **)&d.genome, gw.data(), gw.size() * 4) && up((void **)&d.reads, rw.data(), rw.size() * 4) &&
+         up((void **)&d.rwo, rwo.data(), rwo.size() * 8) && up((void **)&d.rbo, rbo.data(), rbo.size() * 8) &&
+         up((void **)&d.rl, rl.data(), rl.size() * 4) && up((void **)&d.ml, ml.data(), ml.size() * 4) &&
+         hipMalloc((void **)&d.i32, size_t(tasks) * 4 * 4) == hipSuccess &&
+         hipMalloc((void **)&d.cigar, size_t(tasks) * size_t(2 * n) * 4) == hipSuccess &&
+         hipMalloc((void **)&d.status, size_t(tasks)) == hipSuccess;
+}
+
+std::string cache_header(const soap_dp_ctx *ctx) {
+  char buf[128];
+  std::snprintf(buf, sizeof buf, "\"arch\": \"%s\", \"cus\": %d, \"version\": 1", ctx->arch.c_str(),
+                ctx->cu_count);
+  return buf;
+}
+
+bool load_cache(soap_dp_ctx *ctx, const char *path) {
+  FILE *f = std::fopen(path, "r");
+  if (!f) return false;
+  std::string text;
+  char buf[4096];
+  size_t got;
+  while ((got = std::fread(buf, 1, sizeof buf, f)) > 0) text.append(buf, got);
+  std::fclose(f);
+  if (text.find(cache_header(ctx)) == std::string::npos) return false;
+  std::vector<ClassSpec> cls = ctx->classes;
+  size_t pos = 0;
+  int found = 0;
+  while ((pos = text.find("{\"prec\":", pos)) != std::string::npos) {
+    int prec = 0, cap = 0, lanes = 0, cells = 0;
+    if (std::sscanf(text.c_str() + pos, "{\"prec\": %d, \"cap\": %d, \"lanes\": %d, \"cells\": %d",
+                    &prec, &cap, &lanes, &cells) == 4) {
+      for (auto &c : cls)
+        if (c.prec == prec && c.cap == cap && lanes * cells >= cap &&
+            shape_compiled(prec, Shape{lanes, cells})) {
+          c.shape = Shape{lanes, cells};
+          ++found;
+        }
+    }
+    ++pos;
+  }
+  if (found == 0) return false;
+  ctx->classes = cls;
+  return true;
+}
+
+bool save_cache(const soap_dp_ctx *ctx, const char *path, const std::vector<double> &gcups) {
+  const std::string tmp = std::string(path) + ".tmp";
+  FILE *f = std::fopen(tmp.c_str(), "w");
+  if (!f) return false;
+  std::fprintf(f, "{%s, \"classes\": [\n", cache_header(ctx).c_str());
+  for (size_t k = 0; k < ctx->classes.size(); ++k) {
+    const ClassSpec &c = ctx->classes[k];
+    std::fprintf(f, "  {\"prec\": %d, \"cap\": %d, \"lanes\": %d, \"cells\": %d, \"gcups\": %.1f}%s\n",
+                 c.prec, c.cap, c.shape.lanes, c.shape.cells, k < gcups.size() ? gcups[k] : 0.0,
+                 k + 1 < ctx->classes.size() ? "," : "");
+  }
+  std::fprintf(f, "]}\n");
+  std::fclose(f);
+  return std::rename(tmp.c_str(), path) == 0;
+}
+
+// Measure one shape on the class's synthetic tasks: best of three launches.
+double time_shape(soap_dp_ctx *ctx, int prec, Shape s, const TuneData &d, int32_t n, hipStream_t st) {
+  const int32_t m = n + 160;
+  soap_dp_scoring sc{1, -3, -5, -2};
+  DpParams p{};
+  p.read_codes = d.reads; p.read_word_off = d.rwo; p.read_len = d.rl;
+  p.ref_codes = d.genome; p.ref_base_off = d.rbo; p.ref_len = d.ml;
+  p.n_tasks = d.tasks;
+  p.read_words = uint64_t(d.tasks) * uint64_t((n + 15) / 16);
+  p.ref_words = (1u << 20) / 16;
+  p.max_n = n; p.max_m = m;
+  p.ma = sc.match; p.mi = sc.mismatch; p.go = sc.gap_open; p.ge = sc.gap_extend;
+  p.score = d.i32; p.ref_begin = d.i32 + d.tasks; p.ref_end = d.i32 + 2 * d.tasks;
+  p.cigar_len = d.i32 + 3 * d.tasks; p.cigar = d.cigar; p.cigar_stride = 2 * n;
+  p.status = d.status;
+  p.ok_status = kTaskOk;
+  const int grid = grid_for(ctx, prec, s, d.tasks, m);
+  p.slot_dwords = slot_dwords(prec, s, m);
+  if (ensure_scratch(ctx, size_t(grid) * p.slot_dwords * 4)) return 0;
+  p.scratch = static_cast<uint32_t *>(ctx->scratch);
+  p.work_counter = ctx->small + 3 * kMaxClasses;
+  hipEvent_t a, b;
+  (void)hipEventCreate(&a);
+  (void)hipEventCreate(&b);
+  double best_ms = 1e30;
+  for (int rep = 0; rep < 4; ++rep) {
+    if (launch_zero(p.work_counter, 1, st) != hipSuccess) break;
+    (void)hipEventRecord(a, st);
+    if (launch_shape(prec, s, grid, st, p) != hipSuccess) break;
+    (void)hipEventRecord(b, st);
+    if (hipEventSynchronize(b) != hipSuccess) break;
+    float ms = 0;
+    (void)hipEventElapsedTime(&ms, a, b);
+    if (rep > 0) best_ms = std::min(best_ms, double(ms));   // first launch warms up
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  (void)hipGetLastError();
+  if (best_ms >= 1e29) return 0;
+  return double(d.tasks) * double(n) * double(m) / (best_ms * 1e-3) / 1e9;
+}
+
+int autotune(soap_dp_ctx *ctx, std::vector<double> &gcups) {
+  hipStream_t st = nullptr;
+  if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) return hip_fail(ctx, hipGetLastError());
+  gcups.assign(ctx->classes.size(), 0.0);
+  int rc = SOAP_DP_OK;
+  for (size_t k = 0; k < ctx->classes.size() && rc == SOAP_DP_OK; ++k) {
+    ClassSpec &c = ctx->classes[k];
+    const int32_t n = c.cap, m = n + 160;
+    const int64_t tasks = std::max<int64_t>(2048, std::min<int64_t>(262144, int64_t(6e8 / (double(n) * m))));
+    TuneData d;
+    if (!make_tune_data(d, n, tasks)) { rc = SOAP_DP_ENOMEM; break; }
+    int cnt = 0;
+    const Shape *all = c.prec == 16 ? shapes_i16(&cnt) : shapes_i32(&cnt);
+    double best = -1;
+    Shape best_s = c.shape;
+    for (int q = 0; q < cnt; ++q) {
+      const Shape s = all[q];
+      const int cols = s.lanes * s.cells;
+      if (cols < c.cap || cols > c.cap + std::max(c.cap / 6, 8)) continue;
+      if (c.prec == 16 && !int16_fits(n, cols, 1, -3, -5, -2)) continue;
+      const double g = time_shape(ctx, c.prec, s, d, n, st);
+      if (g > best) { best = g; best_s = s; }
+    }
+    c.shape = best_s;
+    gcups[k] = best;
+  }
+  (void)hipStreamDestroy(st);
+  clear_graphs(ctx);
+  return rc;
 }
 
 }  // namespace
@@ -189,13 +628,17 @@ int soap_dp_create(soap_dp_ctx **out, int device_ordinal) {
   if (!ctx) return SOAP_DP_ENOMEM;
   ctx->device = device_ordinal;
   ctx->cu_count = prop.multiProcessorCount;
+  ctx->arch = "gfx950";
+  ctx->classes.assign(std::begin(kDefaultClasses), std::end(kDefaultClasses));
+  const char *ng = std::getenv("SOAPDP_NO_GRAPH");
+  ctx->use_graphs = !(ng && ng[0] && ng[0] != '0');
   {
     DeviceGuard dg(device_ordinal);
-    if (hipMalloc(&ctx->small, kSmallBytes) != hipSuccess) {
+    if (hipMalloc(reinterpret_cast<void **>(&ctx->small), 4 * kMaxClasses * sizeof(int32_t)) != hipSuccess) {
+      (void)hipGetLastError();
       delete ctx;
       return SOAP_DP_ENOMEM;
     }
-    ctx->small_bytes = kSmallBytes;
   }
   *out = ctx;
   return SOAP_DP_OK;
@@ -206,8 +649,12 @@ int soap_dp_destroy(soap_dp_ctx *ctx) {
   {
     DeviceGuard dg(ctx->device);
     (void)hipDeviceSynchronize();
+    clear_graphs(ctx);
+    if (ctx->capture_stream) (void)hipStreamDestroy(ctx->capture_stream);
     if (ctx->scratch) (void)hipFree(ctx->scratch);
     if (ctx->small) (void)hipFree(ctx->small);
+    if (ctx->task_list) (void)hipFree(ctx->task_list);
+    if (ctx->task_class) (void)hipFree(ctx->task_class);
   }
   delete ctx;
   return SOAP_DP_OK;
@@ -217,24 +664,32 @@ int soap_dp_align_batch(soap_dp_ctx *ctx, const soap_dp_batch *in, const soap_dp
                         const soap_dp_result *out, void *stream, uint32_t flags) {
   if (!ctx) return SOAP_DP_EINVAL;
   if (!scoring_ok(sc)) return SOAP_DP_EINVAL;
-  int rc = batch_ok(in, out);
+  const int rc = batch_ok(in, out);
   if (rc) return rc;
   if (flags != SOAP_DP_PLAIN && flags != SOAP_DP_BATCHED) return SOAP_DP_EINVAL;
   if (in->n_tasks == 0) return SOAP_DP_OK;
   DeviceGuard dg(ctx->device);
-  return align_plain(ctx, in, sc, out, static_cast<hipStream_t>(stream));
+  const hipStream_t st = static_cast<hipStream_t>(stream);
+  return flags == SOAP_DP_PLAIN ? align_plain(ctx, in, sc, out, st) : align_batched(ctx, in, sc, out, st);
 }
 
 size_t soap_dp_workspace_bytes(const soap_dp_ctx *ctx, int64_t n_tasks, int32_t max_n,
                                int32_t max_m, uint32_t flags) {
-  (void)flags;
   if (!ctx || n_tasks <= 0 || max_n < 1 || max_n > SOAP_DP_MAX_READ || max_m < 1 ||
       max_m > SOAP_DP_MAX_WINDOW)
     return 0;
-  const Shape s = plain_shape(max_n, max_m);
-  if (s.lanes == 0) return 0;
-  const int grid = grid_for(ctx, s, n_tasks, max_m);
-  return size_t(grid) * slot_dwords_for(s, max_m) * 4 + ctx->small_bytes;
+  const size_t small = 4 * kMaxClasses * sizeof(int32_t);
+  if (flags == SOAP_DP_PLAIN) return plain_scratch_bytes(ctx, n_tasks, max_n, max_m) + small;
+  // the int32 classes are counted too: the scoring is not known here
+  std::vector<int> live;
+  int prev16 = 0, prev32 = 0;
+  for (size_t k = 0; k < ctx->classes.size(); ++k) {
+    const ClassSpec &c = ctx->classes[k];
+    int &prev = c.prec == 16 ? prev16 : prev32;
+    if (prev < max_n) live.push_back(int(k));
+    prev = c.cap;
+  }
+  return batched_scratch_bytes(ctx, n_tasks, max_m, live) + size_t(n_tasks) * 5 + small;
 }
 
 int soap_dp_reserve(soap_dp_ctx *ctx, int64_t n_tasks, int32_t max_n, int32_t max_m,
@@ -243,7 +698,69 @@ int soap_dp_reserve(soap_dp_ctx *ctx, int64_t n_tasks, int32_t max_n, int32_t ma
   const size_t b = soap_dp_workspace_bytes(ctx, n_tasks, max_n, max_m, flags);
   if (b == 0) return SOAP_DP_EINVAL;
   DeviceGuard dg(ctx->device);
-  return ensure_scratch(ctx, b - ctx->small_bytes);
+  const size_t small = 4 * kMaxClasses * sizeof(int32_t);
+  size_t scratch = b - small;
+  if (flags != SOAP_DP_PLAIN) {
+    scratch -= size_t(n_tasks) * 5;
+    const int rc = ensure_task_buffers(ctx, n_tasks);
+    if (rc) return rc;
+  }
+  return ensure_scratch(ctx, scratch);
+}
+
+int soap_dp_autotune(soap_dp_ctx *ctx, const char *cache_path, int force) {
+  if (!ctx) return SOAP_DP_EINVAL;
+  DeviceGuard dg(ctx->device);
+  if (cache_path && !force && load_cache(ctx, cache_path)) {
+    clear_graphs(ctx);
+    return SOAP_DP_OK;
+  }
+  std::vector<double> gcups;
+  const int rc = autotune(ctx, gcups);
+  if (rc) return rc;
+  if (cache_path && !save_cache(ctx, cache_path, gcups)) return SOAP_DP_EINVAL;
+  return SOAP_DP_OK;
+}
+
+int soap_dp_get_classes(const soap_dp_ctx *ctx, soap_dp_class_info *out, int32_t n_max) {
+  if (!ctx) return SOAP_DP_EINVAL;
+  const int32_t cnt = int32_t(ctx->classes.size());
+  for (int32_t k = 0; out && k < cnt && k < n_max; ++k) {
+    out[k].precision = ctx->classes[size_t(k)].prec;
+    out[k].capacity = ctx->classes[size_t(k)].cap;
+    out[k].lanes = ctx->classes[size_t(k)].shape.lanes;
+    out[k].cells = ctx->classes[size_t(k)].shape.cells;
+  }
+  return cnt;
+}
+
+int soap_dp_set_class_shape(soap_dp_ctx *ctx, int32_t precision, int32_t capacity, int32_t lanes,
+                            int32_t cells) {
+  if (!ctx) return SOAP_DP_EINVAL;
+  const Shape s{lanes, cells};
+  if ((precision != 16 && precision != 32) || !shape_compiled(precision, s) ||
+      lanes * cells < capacity)
+    return SOAP_DP_EINVAL;
+  for (auto &c : ctx->classes)
+    if (c.prec == precision && c.cap == capacity) {
+      c.shape = s;
+      clear_graphs(ctx);
+      return SOAP_DP_OK;
+    }
+  return SOAP_DP_EINVAL;
+}
+
+int soap_dp_list_shapes(int32_t precision, soap_dp_class_info *out, int32_t n_max) {
+  if (precision != 16 && precision != 32) return SOAP_DP_EINVAL;
+  int cnt = 0;
+  const Shape *all = precision == 16 ? shapes_i16(&cnt) : shapes_i32(&cnt);
+  for (int k = 0; out && k < cnt && k < n_max; ++k) {
+    out[k].precision = precision;
+    out[k].capacity = all[k].lanes * all[k].cells;
+    out[k].lanes = all[k].lanes;
+    out[k].cells = all[k].cells;
+  }
+  return cnt;
 }
 
 const char *soap_dp_strerror(int code) {

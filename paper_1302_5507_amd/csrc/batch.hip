@@ -1,0 +1,122 @@
+// Device-side length bucketing for the batched form.  Every task is put in
+// the smallest length class whose kernel shape holds its read: a packed
+// int16 class when the task's values stay inside int16 (int16_fits), else
+// an int32 class.  Invalid tasks get their status and zero outputs here.
+// The class segments of one task list are built with per-workgroup
+// histograms and one atomic per class and workgroup, so nothing depends on
+// the host and the whole sequence can be replayed as a graph.
+#include "dp_device.h"
+#include "batch.h"
+
+namespace soapdp {
+
+namespace {
+
+constexpr int kBlock = 256;
+
+__device__ int class_of(const ClassTable &ct, int32_t n, int32_t ma, int32_t mi, int32_t go,
+                        int32_t ge) {
+  // int16 classes first (ascending capacity), then int32 classes
+  for (int k = 0; k < ct.count; ++k) {
+    if (ct.prec[k] != 16 || ct.cap[k] < n) continue;
+    if (int16_fits(n, ct.cols[k], ma, mi, go, ge)) return k;
+    break;   // a wider int16 shape only widens the range; go to int32
+  }
+  for (int k = 0; k < ct.count; ++k)
+    if (ct.prec[k] == 32 && ct.cap[k] >= n) return k;
+  return -1;
+}
+
+__global__ void zero_kernel(int32_t *a, int n) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) a[i] = 0;
+}
+
+__global__ __launch_bounds__(kBlock) void classify_kernel(DpParams p, ClassTable ct,
+                                                          uint8_t *task_class, int32_t *hist) {
+  __shared__ int32_t s_hist[kMaxClasses];
+  for (int k = threadIdx.x; k < kMaxClasses; k += kBlock) s_hist[k] = 0;
+  __syncthreads();
+  const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (t < p.n_tasks) {
+    const int32_t n = p.read_len[t];
+    const int32_t m = p.ref_len[t];
+    const uint64_t rwo = p.read_word_off[t];
+    const uint64_t rbo = p.ref_base_off[t];
+    uint8_t st = kTaskOk;
+    int k = -1;
+    if (n < 1 || m < 1 || n > p.max_n || m > p.max_m)
+      st = kTaskInvalidLen;
+    else if (rwo + (uint64_t)((n + 15) >> 4) > p.read_words || rbo + (uint64_t)m > p.ref_words * 16)
+      st = kTaskInvalidOffset;
+    else {
+      k = class_of(ct, n, p.ma, p.mi, p.go, p.ge);
+      if (k < 0) st = kTaskInvalidLen;
+    }
+    if (st != kTaskOk) {
+      p.score[t] = 0; p.ref_begin[t] = 0; p.ref_end[t] = 0; p.cigar_len[t] = 0;
+      p.status[t] = st;
+      task_class[t] = 0xff;
+    } else {
+      task_class[t] = (uint8_t)k;
+      atomicAdd(&s_hist[k], 1);
+    }
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < ct.count; k += kBlock)
+    if (s_hist[k]) atomicAdd(&hist[k], s_hist[k]);
+}
+
+// One workgroup: class offsets (exclusive scan of the histogram) and the
+// cursors the scatter advances.
+__global__ void scan_kernel(const int32_t *hist, int32_t *offset, int32_t *cursor,
+                            int32_t *work_counter, int count) {
+  if (threadIdx.x == 0) {
+    int32_t acc = 0;
+    for (int k = 0; k < count; ++k) {
+      offset[k] = acc;
+      cursor[k] = acc;
+      work_counter[k] = 0;
+      acc += hist[k];
+    }
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void scatter_kernel(const uint8_t *task_class, int64_t n_tasks,
+                                                         int32_t *cursor, int32_t *task_list) {
+  __shared__ int32_t s_cnt[kMaxClasses], s_base[kMaxClasses];
+  for (int k = threadIdx.x; k < kMaxClasses; k += kBlock) s_cnt[k] = 0;
+  __syncthreads();
+  const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  int k = 0xff, rank = 0;
+  if (t < n_tasks) {
+    k = task_class[t];
+    if (k != 0xff) rank = atomicAdd(&s_cnt[k], 1);
+  }
+  __syncthreads();
+  for (int c = threadIdx.x; c < kMaxClasses; c += kBlock)
+    s_base[c] = s_cnt[c] ? atomicAdd(&cursor[c], s_cnt[c]) : 0;
+  __syncthreads();
+  if (t < n_tasks && k != 0xff) task_list[s_base[k] + rank] = (int32_t)t;
+}
+
+}  // namespace
+
+hipError_t launch_bucketing(const DpParams &p, const ClassTable &ct, const BucketBuffers &b,
+                            hipStream_t stream) {
+  const int64_t blocks = (p.n_tasks + kBlock - 1) / kBlock;
+  hipLaunchKernelGGL(zero_kernel, dim3(1), dim3(64), 0, stream, b.hist, kMaxClasses);
+  hipLaunchKernelGGL(classify_kernel, dim3((uint32_t)blocks), dim3(kBlock), 0, stream, p, ct,
+                     b.task_class, b.hist);
+  hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(64), 0, stream, b.hist, b.offset, b.cursor,
+                     b.work_counter, ct.count);
+  hipLaunchKernelGGL(scatter_kernel, dim3((uint32_t)blocks), dim3(kBlock), 0, stream, b.task_class,
+                     p.n_tasks, b.cursor, b.task_list);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero(int32_t *a, int n, hipStream_t stream) {
+  hipLaunchKernelGGL(zero_kernel, dim3(1), dim3(256), 0, stream, a, n);
+  return hipGetLastError();
+}
+
+}  // namespace soapdp

@@ -1,0 +1,113 @@
+// Device helpers shared by the DP kernels.
+#pragma once
+#include "dp_internal.h"
+
+namespace soapdp {
+
+__device__ __forceinline__ int32_t wave_shr1(int32_t v) {
+  // DPP wave_shr:1 -- lane k receives lane k-1; lane 0 receives 0.
+  return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xf, 0xf, false);
+}
+
+__device__ __forceinline__ uint32_t push_sign(uint32_t acc, int32_t diff) {
+  // (acc << 1) | (diff < 0): shift the sign bit of `diff` into the accumulator.
+  return __builtin_amdgcn_alignbit(acc, (uint32_t)diff, 31);
+}
+
+__device__ __forceinline__ int32_t wave_max(int32_t v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v = max(v, __shfl_xor(v, o));
+  return v;
+}
+
+// Walk the decision nibbles of one task back from (end, n) and write its
+// CIGAR.  `nib_at(i, j)` returns the decision nibble of cell (i, j).
+template <class NibFn>
+__device__ void traceback_task(const DpParams &p, int64_t task, int32_t n, int32_t end,
+                               NibFn nib_at) {
+  uint32_t *row = p.cigar + task * (int64_t)p.cigar_stride;
+  int32_t wpos = p.cigar_stride;  // runs are written backward from the row end
+  int32_t cur = -1, run = 0;
+  int32_t i = end, j = n, state = 0;  // 0 = M, 1 = D, 2 = I
+  int32_t begin = 0;
+  bool overflow = false;
+  auto emit = [&](int32_t op, int32_t len) {
+    if (op == cur) {
+      run += len;
+    } else {
+      if (run > 0) {
+        if (wpos > 0) row[--wpos] = (uint32_t)run << 4 | (uint32_t)cur;
+        else overflow = true;
+      }
+      cur = op;
+      run = len;
+    }
+  };
+  // Every iteration lowers i or j, so the walk ends within n + end steps.
+  // The guards keep a corrupted decision from reading outside the task.
+  for (int32_t guard = n + end + 1; guard > 0; --guard) {
+    if (state == 0) {
+      if (j == 0) { begin = i; break; }
+      if (i == 0) { emit(1, j); begin = 0; break; }
+    }
+    if (i < 1 || j < 1) { overflow = true; break; }
+    const uint32_t nib = nib_at(i, j);
+    if (state == 0) {
+      if (!(nib & 2u)) {          // diagonal
+        emit(0, 1);
+        --i; --j;
+        continue;
+      }
+      state = (nib & 1u) ? 2 : 1;  // from I, else from D
+    }
+    if (state == 1) {             // region base i against a space
+      emit(2, 1);
+      if (!(nib & 4u)) state = 0;
+      --i;
+    } else {                      // read base j against a space
+      emit(1, 1);
+      if (!(nib & 8u)) state = 0;
+      --j;
+    }
+  }
+  emit(-2, 0);  // flush the last run
+  const int32_t cnt = p.cigar_stride - wpos;
+  for (int32_t k = 0; k < cnt; ++k) row[k] = row[wpos + k];
+  p.cigar_len[task] = overflow ? 0 : cnt;
+  p.ref_begin[task] = begin;
+  if (overflow) p.status[task] = kTaskInvalidLen;
+}
+
+
+// Resolve the task order of a work item: entry `tix` of the (segment of the)
+// task list, or `tix` itself.
+__device__ __forceinline__ int64_t task_at(const DpParams &p, const int32_t *list, int64_t tix) {
+  return list ? (int64_t)list[tix] : tix;
+}
+
+// The read words covering columns q0 .. q0+K-1 of a lane's strip (q = 0-based
+// read index; negative q lie left of the read).  A strip of K <= 32 columns
+// spans at most three words.  Loads stay inside the read's own words.
+struct StripWords {
+  uint32_t w0, w1, w2;
+  int32_t base;  // word index of w0
+  __device__ __forceinline__ void load(const uint32_t *codes, uint64_t first_word, int32_t n,
+                                       int32_t q0) {
+    const int32_t last = (n - 1) >> 4;
+    base = (q0 > 0 ? q0 : 0) >> 4;
+    const int32_t i0 = base < last ? base : last;
+    const int32_t i1 = base + 1 < last ? base + 1 : last;
+    const int32_t i2 = base + 2 < last ? base + 2 : last;
+    w0 = codes[first_word + (uint64_t)i0];
+    w1 = codes[first_word + (uint64_t)i1];
+    w2 = codes[first_word + (uint64_t)i2];
+  }
+  // code of read index q (0 <= q < n)
+  __device__ __forceinline__ uint32_t code(int32_t q) const {
+    const int32_t k = (q >> 4) - base;
+    const uint32_t w = k == 0 ? w0 : (k == 1 ? w1 : w2);
+    return (w >> ((q & 15) * 2)) & 3u;
+  }
+};
+
+}  // namespace soapdp

@@ -1,0 +1,342 @@
+// Packed int16 fill + traceback kernel (batched form).  Same recurrences and
+// tie-breaks as the int32 kernel (paper, Methods section 3), two tasks per
+// lane: the low and high 16-bit halves of every register belong to two
+// different tasks that share the lane geometry, so each packed VALU
+// instruction advances two cells.
+//
+// Differences from the int32 kernel, all exact:
+//  * Values are kept in a column-offset form  M^(i,j) = M(i,j) - j*S_MI
+//    (likewise I and D).  The diagonal step then adds delta - S_MI, which is
+//    S_MA - S_MI on a match and 0 on a mismatch, both small non-negative
+//    numbers read from an 8-byte table with one v_perm_b32 indexed by
+//    (read code XOR window base); the I recurrence adds S_GO - S_MI and
+//    S_GE - S_MI; the D recurrence is unchanged.  Columns left of the read
+//    (virtual, true value 0) index the table's upper half, which holds -S_MI.
+//  * Adds and subtracts saturate (v_pk_*_i16 clamp).  A task runs here only
+//    if every maximum, widened by the largest constant added, stays well
+//    inside int16 (int16_fits); clamped candidates then always lose, and
+//    -32768 serves as minus infinity.  Other tasks are left to the int32
+//    kernel.
+//  * Decision bits: the sign of each packed difference is replicated into a
+//    byte with v_perm_b32 (selectors 8..11) and merged with v_and_or_b32 into
+//    bit c%8 of that byte.  Per 8 columns a lane writes two dwords:
+//      A: byte h = D extended, byte 2+h = I extended        (h = 0 low task,
+//      B: byte h = not from D, byte 2+h = not diagonal         1 high task)
+#include "dp_device.h"
+
+namespace soapdp {
+
+namespace {
+
+typedef short s16x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ s16x2 v2(uint32_t x) { return __builtin_bit_cast(s16x2, x); }
+__device__ __forceinline__ uint32_t u32(s16x2 x) { return __builtin_bit_cast(uint32_t, x); }
+__device__ __forceinline__ uint32_t add16(uint32_t a, uint32_t b) {
+  return u32(__builtin_elementwise_add_sat(v2(a), v2(b)));
+}
+__device__ __forceinline__ uint32_t sub16(uint32_t a, uint32_t b) {
+  return u32(__builtin_elementwise_sub_sat(v2(a), v2(b)));
+}
+__device__ __forceinline__ uint32_t max16(uint32_t a, uint32_t b) {
+  return u32(__builtin_elementwise_max(v2(a), v2(b)));
+}
+__device__ __forceinline__ uint32_t pack16(int32_t lo, int32_t hi) {
+  return ((uint32_t)lo & 0xffffu) | ((uint32_t)hi << 16);
+}
+
+constexpr uint32_t kNeg16x2 = 0x80008000u;   // (-32768, -32768)
+constexpr uint32_t kSignSel = 0x0b0a0908u;   // v_perm: replicate the four sign bits
+
+}  // namespace
+
+template <int L, int K>
+__global__ __launch_bounds__(kWave) void dp_i16_kernel(DpParams p) {
+  static_assert(kWave % L == 0, "lanes per task must divide the wavefront");
+  constexpr int G = kWave / L;       // lane groups per wavefront
+  constexpr int TPW = 2 * G;         // tasks per wavefront (low and high halves)
+  static_assert(TPW <= kWave, "one traceback lane per task");
+  constexpr int W = (K + 7) / 8;     // 8-column groups per lane
+  const int lane = threadIdx.x;
+  const int g = lane / L;
+  const int lg = lane % L;
+  const bool first = lg == 0;
+  const bool last = lg == L - 1;
+
+  __shared__ int64_t s_task[TPW];
+  __shared__ int32_t s_n[TPW], s_pad[TPW], s_end[TPW], s_score[TPW];
+  __shared__ uint8_t s_st[TPW];
+
+  uint32_t *const slot = p.scratch + (uint64_t)blockIdx.x * p.slot_dwords;
+  const int64_t n_tasks = p.task_count ? (int64_t)*p.task_count : p.n_tasks;
+  const int32_t *const list = (p.task_list && p.task_off) ? p.task_list + *p.task_off : p.task_list;
+  const int64_t n_items = (n_tasks + TPW - 1) / TPW;
+
+  const int32_t ma = p.ma, mi = p.mi, go = p.go, ge = p.ge;
+  const uint32_t c_goi = pack16(go - mi, go - mi);   // I open, column-offset form
+  const uint32_t c_gei = pack16(ge - mi, ge - mi);   // I extend
+  const uint32_t c_god = pack16(go, go);             // D open
+  const uint32_t c_ged = pack16(ge, ge);             // D extend
+  const uint32_t tab_lo = (uint32_t)(ma - mi) & 0xffu;          // x = 0 match, 1..3 mismatch
+  const uint32_t tab_hi = ((uint32_t)(-mi) & 0xffu) * 0x01010101u;  // x = 4..7 virtual
+
+  int64_t item = blockIdx.x;
+  if (p.work_counter) {
+    int32_t v = 0;
+    if (lane == 0) v = atomicAdd(p.work_counter, 1);
+    item = __builtin_amdgcn_readfirstlane(v);
+  }
+  while (item < n_items) {
+    // ---------------- set-up of the two tasks of this lane group
+    int64_t task[2];
+    int32_t n[2], m[2], pad[2], mg[2];
+    uint64_t rwo[2], rbo[2];
+    uint8_t st[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int64_t tix = item * TPW + h * G + g;
+      task[h] = -1; n[h] = 0; m[h] = 0; rwo[h] = 0; rbo[h] = 0; st[h] = kTaskOk;
+      if (tix < n_tasks) {
+        task[h] = task_at(p, list, tix);
+        n[h] = p.read_len[task[h]];
+        m[h] = p.ref_len[task[h]];
+        rwo[h] = p.read_word_off[task[h]];
+        rbo[h] = p.ref_base_off[task[h]];
+        if (n[h] < 1 || m[h] < 1 || n[h] > p.max_n || m[h] > p.max_m || n[h] > L * K)
+          st[h] = kTaskInvalidLen;
+        else if (rwo[h] + (uint64_t)((n[h] + 15) >> 4) > p.read_words ||
+                 rbo[h] + (uint64_t)m[h] > p.ref_words * 16)
+          st[h] = kTaskInvalidOffset;
+        else if (!int16_fits(n[h], L * K, ma, mi, go, ge))
+          task[h] = -1;   // outside the int16 range: the int32 kernel owns it
+      }
+      const bool valid = task[h] >= 0 && st[h] == kTaskOk;
+      mg[h] = valid ? m[h] : 0;
+      pad[h] = valid ? L * K - n[h] : 0;
+    }
+    const int32_t mlane = max(mg[0], mg[1]);
+    const int32_t steps = wave_max(mlane) + L - 1;
+    // per-task bookkeeping for the traceback goes to LDS now, so it does not
+    // occupy registers during the sweep
+    if (first) {
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int u = h * G + g;
+        s_task[u] = task[h]; s_n[u] = n[h]; s_pad[u] = pad[h]; s_st[u] = st[h];
+      }
+    }
+
+    StripWords rw[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      rw[h] = StripWords{0, 0, 0, 0};
+      if (mg[h] > 0) rw[h].load(p.read_codes, rwo[h], n[h], lg * K - pad[h]);
+    }
+    uint32_t Rc[K], H[K], F[K];
+#pragma unroll
+    for (int c = 0; c < K; ++c) {
+      int32_t hv[2];
+      uint32_t code[2];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int32_t q = lg * K + c - pad[h];   // 0-based read index of this column
+        const bool real = mg[h] > 0 && q >= 0;
+        code[h] = real ? rw[h].code(q) : 4u;     // virtual: table entries 4..7
+        // M^(0, j) with j = q + 1: S_GO + (j-1) S_GE - j S_MI, or -j S_MI left of the read
+        hv[h] = real ? go + q * ge - (q + 1) * mi : -(q + 1) * mi;
+      }
+      Rc[c] = (code[0] | 0x0c00u) | ((code[1] | 0x0c00u) << 16);
+      H[c] = pack16(hv[0], hv[1]);
+      F[c] = kNeg16x2;
+    }
+    // left boundary M^(i, -pad) = pad * S_MI (true value 0)
+    const uint32_t bnd = pack16(pad[0] * mi, pad[1] * mi);
+
+    // window bases, 16 at a time per task, realigned from the base offset
+    const uint64_t wlim = p.ref_words - 1;
+    const int32_t wsh0 = (int32_t)(rbo[0] & 15) * 2, wsh1 = (int32_t)(rbo[1] & 15) * 2;
+    auto ldw = [&](uint64_t wi) { return p.ref_codes[wi < wlim ? wi : wlim]; };
+    uint32_t a0 = ldw(rbo[0] >> 4), a1 = ldw((rbo[0] >> 4) + 1);
+    uint32_t b0 = ldw(rbo[1] >> 4), b1 = ldw((rbo[1] >> 4) + 1);
+    uint32_t twa = 0, twb = 0;
+
+    uint32_t hl_out = H[K - 1];
+    uint32_t el_out = kNeg16x2;
+    uint32_t t_out = 0;
+    uint32_t hl_prev = bnd;
+    int32_t best0 = INT32_MIN, best1 = INT32_MIN;
+    uint32_t accA[W], accB[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) { accA[w] = 0; accB[w] = 0; }
+
+    uint2 *sp = reinterpret_cast<uint2 *>(slot);
+    for (int32_t t = 0; t < steps; ++t) {
+      if ((t & 15) == 0) {
+        twa = __builtin_amdgcn_alignbit(a1, a0, wsh0);
+        twb = __builtin_amdgcn_alignbit(b1, b0, wsh1);
+        const uint64_t nb = (uint64_t)(t >> 4) + 1;
+        a0 = ldw((rbo[0] >> 4) + nb); a1 = ldw((rbo[0] >> 4) + nb + 1);
+        b0 = ldw((rbo[1] >> 4) + nb); b1 = ldw((rbo[1] >> 4) + nb + 1);
+      }
+      const uint32_t sh = (uint32_t)(t & 15) * 2;
+      const uint32_t tfirst = ((twa >> sh) & 3u) | (((twb >> sh) & 3u) << 16);
+      uint32_t hl = (uint32_t)wave_shr1((int32_t)hl_out);
+      uint32_t el = (uint32_t)wave_shr1((int32_t)el_out);
+      uint32_t T = (uint32_t)wave_shr1((int32_t)t_out);
+      uint32_t hd = hl_prev;
+      if (first) { hl = bnd; el = kNeg16x2; T = tfirst; hd = bnd; }
+      hl_prev = hl;
+      t_out = T;
+      const int32_t i = t + 1 - lg;
+      if (i >= 1 && i <= mlane) {
+        // The diagonal candidate of column c+1 is formed from the old H[c]
+        // before H[c] is overwritten, so every update happens in place.
+        uint32_t diag = add16(hd, __builtin_amdgcn_perm(tab_hi, tab_lo, Rc[0] ^ T));
+#pragma unroll
+        for (int c = 0; c < K; ++c) {
+          const uint32_t ad = add16(H[c], c_god);
+          const uint32_t fe = add16(F[c], c_ged);
+          uint32_t diag_next = 0;
+          if (c + 1 < K) diag_next = add16(H[c], __builtin_amdgcn_perm(tab_hi, tab_lo, Rc[c + 1] ^ T));
+          const uint32_t ai = add16(hl, c_goi);
+          el = max16(ai, add16(el, c_gei));
+          const uint32_t f = max16(ad, fe);
+          const uint32_t hv = max16(max16(diag, el), f);
+          const uint32_t tA = __builtin_amdgcn_perm(sub16(ai, el), sub16(ad, f), kSignSel);
+          const uint32_t tB = __builtin_amdgcn_perm(sub16(diag, hv), sub16(f, hv), kSignSel);
+          const uint32_t msk = 0x01010101u << (c & 7);
+          if ((c & 7) == 0) {
+            accA[c / 8] = tA & msk;
+            accB[c / 8] = tB & msk;
+          } else {
+            accA[c / 8] |= tA & msk;
+            accB[c / 8] |= tB & msk;
+          }
+          H[c] = hv;
+          F[c] = f;
+          hl = hv;
+          diag = diag_next;
+          // keep each column's decisions next to its scores: without this the
+          // optimiser sinks them below all columns and every column's
+          // candidates stay live (bounds live registers)
+          asm volatile("" : "+v"(accA[c / 8]), "+v"(accB[c / 8]));
+          __builtin_amdgcn_sched_barrier(0);
+        }
+        hl_out = hl;
+        el_out = el;
+        if (last) {
+          // key = (M^(i, n) << 16) | (0xffff - i): the max is the best score,
+          // then the smallest row
+          const uint32_t inv = 0xffffu - (uint32_t)i;
+          const int32_t k0 = (int32_t)((H[K - 1] << 16) | inv);
+          const int32_t k1 = (int32_t)((H[K - 1] & 0xffff0000u) | inv);
+          if (i <= mg[0]) best0 = max(best0, k0);
+          if (i <= mg[1]) best1 = max(best1, k1);
+        }
+      }
+#pragma unroll
+      for (int w = 0; w < W; ++w) sp[w * kWave + lane] = make_uint2(accA[w], accB[w]);
+      sp += W * kWave;
+    }
+
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int u = h * G + g;
+      if (last) {
+        const int32_t b = h ? best1 : best0;
+        s_end[u] = 0xffff - (b & 0xffff);
+        s_score[u] = b >> 16;   // M^(end, n); the traceback lane adds n * S_MI
+      }
+    }
+    __syncthreads();
+
+    // ---------------- traceback, one lane per task
+    if (lane < TPW) {
+      const int64_t tk = s_task[lane];
+      if (tk >= 0) {
+        const uint8_t tst = s_st[lane];
+        if (tst != kTaskOk) {
+          p.score[tk] = 0; p.ref_begin[tk] = 0; p.ref_end[tk] = 0; p.cigar_len[tk] = 0;
+          p.status[tk] = tst;
+        } else {
+          const int h = lane / G, gq = lane % G;
+          const int32_t tn = s_n[lane], tpad = s_pad[lane], tend = s_end[lane];
+          p.score[tk] = s_score[lane] + tn * mi;
+          p.ref_end[tk] = tend;
+          p.status[tk] = p.ok_status;
+          const uint2 *base = reinterpret_cast<const uint2 *>(slot) + gq * L;
+          const uint32_t shA = 8u * (2 + h), shD = 8u * h;
+          auto nib_at = [&](int32_t i, int32_t j) -> uint32_t {
+            const int32_t jp = j + tpad - 1;
+            const int32_t lq = jp / K;
+            const int32_t c = jp - lq * K;
+            const int32_t ts = i - 1 + lq;
+            const uint2 v = base[((uint64_t)ts * W + (uint32_t)(c >> 3)) * kWave + lq];
+            const uint32_t b = (uint32_t)(c & 7);
+            return ((v.x >> (shA + b)) & 1u) << 3 | ((v.x >> (shD + b)) & 1u) << 2 |
+                   ((v.y >> (shA + b)) & 1u) << 1 | ((v.y >> (shD + b)) & 1u);
+          };
+          traceback_task(p, tk, tn, tend, nib_at);
+        }
+      }
+    }
+    __syncthreads();
+
+    if (p.work_counter) {
+      int32_t v = 0;
+      if (lane == 0) v = atomicAdd(p.work_counter, 1);
+      item = __builtin_amdgcn_readfirstlane(v);
+    } else {
+      item += gridDim.x;
+    }
+  }
+}
+
+// ---------------------------------------------------------------- dispatch
+
+#define SOAPDP_I16_SHAPES(X)                                                            \
+  X(2, 8) X(4, 4) X(4, 8) X(2, 16) X(4, 10) X(8, 5) X(4, 14) X(8, 7) X(4, 16) X(8, 8)   \
+  X(4, 20) X(8, 10) X(8, 13) X(16, 7) X(8, 16) X(16, 8) X(8, 19) X(16, 10) X(8, 24)     \
+  X(16, 12) X(16, 16) X(32, 8) X(16, 20) X(32, 10) X(16, 24) X(32, 12) X(32, 16) X(64, 8)
+
+static const Shape kShapesI16[] = {
+#define X(l, k) {l, k},
+    SOAPDP_I16_SHAPES(X)
+#undef X
+};
+
+const Shape *shapes_i16(int *count) {
+  *count = (int)(sizeof(kShapesI16) / sizeof(kShapesI16[0]));
+  return kShapesI16;
+}
+
+uint64_t slot_dwords_i16(Shape s, int32_t max_m) {
+  return (uint64_t(max_m) + uint64_t(s.lanes) - 1) * uint64_t((s.cells + 7) / 8) * kWave * 2;
+}
+
+hipError_t launch_dp_i16(Shape s, int grid, hipStream_t stream, const DpParams &p) {
+#define X(l, k)                                                                 \
+  if (s.lanes == l && s.cells == k) {                                           \
+    hipLaunchKernelGGL((dp_i16_kernel<l, k>), dim3(grid), dim3(kWave), 0, stream, p); \
+    return hipGetLastError();                                                   \
+  }
+  SOAPDP_I16_SHAPES(X)
+#undef X
+  return hipErrorInvalidValue;
+}
+
+int occupancy_dp_i16(Shape s) {
+  int blocks = 0;
+#define X(l, k)                                                                               \
+  if (s.lanes == l && s.cells == k) {                                                         \
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, dp_i16_kernel<l, k>, kWave, 0) \
+        != hipSuccess)                                                                        \
+      blocks = 0;                                                                             \
+    return blocks;                                                                            \
+  }
+  SOAPDP_I16_SHAPES(X)
+#undef X
+  return 0;
+}
+
+}  // namespace soapdp

@@ -24,83 +24,9 @@
 //    contiguous bytes.
 //  * After the sweep one lane per task walks the decisions back from
 //    (ref_end, n) and writes the run-length CIGAR.
-#include "dp_internal.h"
+#include "dp_device.h"
 
 namespace soapdp {
-
-__device__ __forceinline__ int32_t wave_shr1(int32_t v) {
-  // DPP wave_shr:1 -- lane k receives lane k-1; lane 0 receives 0.
-  return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xf, 0xf, false);
-}
-
-__device__ __forceinline__ uint32_t push_sign(uint32_t acc, int32_t diff) {
-  // (acc << 1) | (diff < 0): shift the sign bit of `diff` into the accumulator.
-  return __builtin_amdgcn_alignbit(acc, (uint32_t)diff, 31);
-}
-
-__device__ __forceinline__ int32_t wave_max(int32_t v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v = max(v, __shfl_xor(v, o));
-  return v;
-}
-
-// Walk the decision nibbles of one task back from (end, n) and write its
-// CIGAR.  `nib_at(i, j)` returns the decision nibble of cell (i, j).
-template <class NibFn>
-__device__ void traceback_task(const DpParams &p, int64_t task, int32_t n, int32_t end,
-                               NibFn nib_at) {
-  uint32_t *row = p.cigar + task * (int64_t)p.cigar_stride;
-  int32_t wpos = p.cigar_stride;  // runs are written backward from the row end
-  int32_t cur = -1, run = 0;
-  int32_t i = end, j = n, state = 0;  // 0 = M, 1 = D, 2 = I
-  int32_t begin = 0;
-  bool overflow = false;
-  auto emit = [&](int32_t op, int32_t len) {
-    if (op == cur) {
-      run += len;
-    } else {
-      if (run > 0) {
-        if (wpos > 0) row[--wpos] = (uint32_t)run << 4 | (uint32_t)cur;
-        else overflow = true;
-      }
-      cur = op;
-      run = len;
-    }
-  };
-  // Every iteration lowers i or j, so the walk ends within n + end steps.
-  // The guards keep a corrupted decision from reading outside the task.
-  for (int32_t guard = n + end + 1; guard > 0; --guard) {
-    if (state == 0) {
-      if (j == 0) { begin = i; break; }
-      if (i == 0) { emit(1, j); begin = 0; break; }
-    }
-    if (i < 1 || j < 1) { overflow = true; break; }
-    const uint32_t nib = nib_at(i, j);
-    if (state == 0) {
-      if (!(nib & 2u)) {          // diagonal
-        emit(0, 1);
-        --i; --j;
-        continue;
-      }
-      state = (nib & 1u) ? 2 : 1;  // from I, else from D
-    }
-    if (state == 1) {             // region base i against a space
-      emit(2, 1);
-      if (!(nib & 4u)) state = 0;
-      --i;
-    } else {                      // read base j against a space
-      emit(1, 1);
-      if (!(nib & 8u)) state = 0;
-      --j;
-    }
-  }
-  emit(-2, 0);  // flush the last run
-  const int32_t cnt = p.cigar_stride - wpos;
-  for (int32_t k = 0; k < cnt; ++k) row[k] = row[wpos + k];
-  p.cigar_len[task] = overflow ? 0 : cnt;
-  p.ref_begin[task] = begin;
-  if (overflow) p.status[task] = kTaskInvalidLen;
-}
 
 template <int L, int K>
 __global__ __launch_bounds__(kWave) void dp_i32_kernel(DpParams p) {
@@ -119,6 +45,7 @@ __global__ __launch_bounds__(kWave) void dp_i32_kernel(DpParams p) {
 
   uint32_t *const slot = p.scratch + (uint64_t)blockIdx.x * p.slot_dwords;
   const int64_t n_tasks = p.task_count ? (int64_t)*p.task_count : p.n_tasks;
+  const int32_t *const list = (p.task_list && p.task_off) ? p.task_list + *p.task_off : p.task_list;
   const int64_t n_items = (n_tasks + G - 1) / G;
 
   int64_t item = blockIdx.x;
@@ -135,7 +62,7 @@ __global__ __launch_bounds__(kWave) void dp_i32_kernel(DpParams p) {
     uint64_t rwo = 0, rbo = 0;
     uint8_t st = kTaskOk;
     if (tix < n_tasks) {
-      task = p.task_list ? (int64_t)p.task_list[tix] : tix;
+      task = task_at(p, list, tix);
       n = p.read_len[task];
       m = p.ref_len[task];
       rwo = p.read_word_off[task];
@@ -149,14 +76,17 @@ __global__ __launch_bounds__(kWave) void dp_i32_kernel(DpParams p) {
     const int32_t mg = valid ? m : 0;
     const int32_t pad = L * K - n;
     const int32_t steps = wave_max(mg) + L - 1;
+    // bookkeeping for the traceback goes to LDS now, out of the sweep's registers
+    if (first) { s_task[g] = task; s_n[g] = n; s_pad[g] = pad; s_st[g] = st; }
 
+    StripWords rw{0, 0, 0, 0};
+    if (valid) rw.load(p.read_codes, rwo, n, lg * K - pad);
     int32_t Rc[K], Mi[K], H[K], F[K];
 #pragma unroll
     for (int c = 0; c < K; ++c) {
       const int32_t q = lg * K + c - pad;  // 0-based read index of this column
       const bool real = valid && q >= 0;
-      uint32_t code = 4;                   // never equals a window base
-      if (real) code = (p.read_codes[rwo + (uint64_t)(q >> 4)] >> ((q & 15) * 2)) & 3u;
+      const uint32_t code = real ? rw.code(q) : 4u;   // 4 never equals a window base
       Rc[c] = (int32_t)code;
       Mi[c] = real ? p.mi : 0;
       H[c] = real ? p.go + q * p.ge : 0;   // M(0, q+1), or 0 left of the read
@@ -199,14 +129,18 @@ __global__ __launch_bounds__(kWave) void dp_i32_kernel(DpParams p) {
       t_out = T;
       const int32_t i = t + 1 - lg;
       if (i >= 1 && i <= mg) {
+        // The diagonal candidate of column c+1 is formed from the old H[c]
+        // before H[c] is overwritten, so every update happens in place.
+        int32_t diag = hd + (Rc[0] == T ? p.ma : Mi[0]);
 #pragma unroll
         for (int c = 0; c < K; ++c) {
-          const int32_t diag = hd + (Rc[c] == T ? p.ma : Mi[c]);
-          hd = H[c];
+          const int32_t ad = H[c] + p.go;
+          const int32_t fe = F[c] + p.ge;
+          int32_t diag_next = 0;
+          if (c + 1 < K) diag_next = H[c] + (Rc[c + 1] == T ? p.ma : Mi[c + 1]);
           const int32_t ai = hl + p.go;
           el = max(ai, el + p.ge);
-          const int32_t ad = H[c] + p.go;
-          const int32_t f = max(ad, F[c] + p.ge);
+          const int32_t f = max(ad, fe);
           const int32_t h = max(max(diag, el), f);
           uint32_t a = acc[c / 8];
           a = push_sign(a, ai - el);
@@ -217,6 +151,12 @@ __global__ __launch_bounds__(kWave) void dp_i32_kernel(DpParams p) {
           H[c] = h;
           F[c] = f;
           hl = h;
+          diag = diag_next;
+          // keep each column's decisions next to its scores: without this the
+          // optimiser sinks them below all columns and every column's
+          // candidates stay live (bounds live registers)
+          asm volatile("" : "+v"(acc[c / 8]));
+          __builtin_amdgcn_sched_barrier(0);
         }
         if (K % 8) acc[W - 1] <<= 4 * (8 - K % 8);
         hl_out = hl;
@@ -228,7 +168,6 @@ __global__ __launch_bounds__(kWave) void dp_i32_kernel(DpParams p) {
       sp += W * kWave;
     }
 
-    if (first) { s_task[g] = task; s_n[g] = n; s_pad[g] = pad; s_st[g] = st; }
     if (last) { s_end[g] = endi; s_score[g] = best; }
     __syncthreads();
 
@@ -244,7 +183,7 @@ __global__ __launch_bounds__(kWave) void dp_i32_kernel(DpParams p) {
           const int32_t tn = s_n[lane], tpad = s_pad[lane], tend = s_end[lane];
           p.score[tk] = s_score[lane];
           p.ref_end[tk] = tend;
-          p.status[tk] = kTaskOk;
+          p.status[tk] = p.ok_status;
           const uint32_t *base = slot + lane * L;
           auto nib_at = [&](int32_t i, int32_t j) -> uint32_t {
             const int32_t jp = j + tpad - 1;
@@ -281,6 +220,10 @@ static const Shape kShapesI32[] = {
     SOAPDP_I32_SHAPES(X)
 #undef X
 };
+
+uint64_t slot_dwords_i32(Shape s, int32_t max_m) {
+  return (uint64_t(max_m) + uint64_t(s.lanes) - 1) * uint64_t((s.cells + 7) / 8) * kWave;
+}
 
 const Shape *shapes_i32(int *count) {
   *count = (int)(sizeof(kShapesI32) / sizeof(kShapesI32[0]));

@@ -43,8 +43,14 @@ struct DpParams {
   // groups of (tasks per wave) consecutive entries of that order.
   const int32_t *task_list;
   const int32_t *task_count;   // device count overriding n_tasks when non-null
+  // When non-null, the task order starts at task_list + *task_off (a class
+  // segment of the batched form, located on the device).
+  const int32_t *task_off;
   // Optional dynamic work counter (nullptr: static grid-stride schedule).
   int32_t *work_counter;
+  // Status written for a task this kernel completes (kTaskOk, or kTaskRedone
+  // when the int32 kernel re-runs tasks outside the int16 range).
+  uint8_t ok_status;
 };
 
 // A kernel shape: L lanes cooperate on one task, each owning K read columns.
@@ -53,11 +59,38 @@ struct Shape {
   int cells;
 };
 
+// int16 form: a task can run in packed int16 iff every value the kernel
+// forms stays inside int16 (the bound on all maxima, widened by the largest
+// constant added to a value and by the column offset) and the substitution
+// scores fit the byte table.  Evaluated identically on host and device.
+__host__ __device__ inline bool int16_fits(int32_t n, int32_t cols, int32_t ma, int32_t mi,
+                                           int32_t go, int32_t ge) {
+  if (mi > 0 || ma - mi > 255 || -mi > 255) return false;
+  auto iabs = [](int32_t v) { return v < 0 ? -v : v; };
+  int32_t s = ma - mi;
+  s = s > iabs(go - mi) ? s : iabs(go - mi);
+  s = s > iabs(ge - mi) ? s : iabs(ge - mi);
+  s = s > iabs(go) ? s : iabs(go);
+  s = s > iabs(ge) ? s : iabs(ge);
+  const int64_t lo = 2 * int64_t(go) + int64_t(n - 1) * ge;     // lowest maximum
+  const int64_t hi = int64_t(n) * (ma - mi);                      // highest offset value
+  const int64_t virt = int64_t(cols) * iabs(mi);                  // virtual-column offset
+  return lo - 2 * s > -32000 && hi + 2 * s < 32000 && virt + 2 * s < 32000;
+}
+
 // Launch the int32 kernel of shape `s` (must be one of the compiled shapes).
 hipError_t launch_dp_i32(Shape s, int grid, hipStream_t stream, const DpParams &p);
 // Occupancy (workgroups of one wave per CU) of the int32 kernel of shape `s`.
 int occupancy_dp_i32(Shape s);
 // The compiled int32 shapes.
 const Shape *shapes_i32(int *count);
+
+// Same for the packed int16 kernel (two tasks per lane, lo and hi halves).
+hipError_t launch_dp_i16(Shape s, int grid, hipStream_t stream, const DpParams &p);
+int occupancy_dp_i16(Shape s);
+const Shape *shapes_i16(int *count);
+// Decision-scratch dwords of one workgroup slot.
+uint64_t slot_dwords_i32(Shape s, int32_t max_m);
+uint64_t slot_dwords_i16(Shape s, int32_t max_m);
 
 }  // namespace soapdp
