@@ -165,6 +165,15 @@ def main():
         line["forms"][form] = {"gcups": round(w.cells / fs / 1e9, 2), "ms_per_step": round(fs * 1e3, 3),
                                "device_ms": round(fk, 3), "valu_frac": round(fach / fpeak, 4),
                                "peak_tops": round(fpeak, 1)}
+    if "batched" in forms:
+        lengths = sorted(set(int(x) for x in np.unique(w.read_len)))
+        shapes = {}
+        for prec, cap, lanes, cells in al.classes():
+            hit = [n for n in lengths if n <= cap and not any(n <= c for p2, c, _, _ in al.classes()
+                                                                if p2 == prec and c < cap)]
+            if prec == 16 and hit:
+                shapes[str(cap)] = f"{lanes}x{cells}"
+        line["forms"]["batched"]["shapes"] = shapes
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(w, args.cpu_tasks)
     print(json.dumps(line), flush=True)

@@ -6,7 +6,32 @@ namespace soapdp {
 
 __device__ __forceinline__ int32_t wave_shr1(int32_t v) {
   // DPP wave_shr:1 -- lane k receives lane k-1; lane 0 receives 0.
-  return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xf, 0xf, false);
+  return __builtin_amdgcn_mov_dpp(v, 0x138, 0xf, 0xf, true);
+}
+
+// Shift every value one lane to the right inside groups of L lanes: lane k
+// receives lane k-1, and the first lane of each group receives `first_val`.
+// With L = 16 the groups are DPP rows and with L = 64 the whole wavefront,
+// so the DPP "old" operand supplies the boundary at no cost; other group
+// sizes patch the first lanes with one select.
+template <int L>
+__device__ __forceinline__ int32_t group_shr1(int32_t v, int32_t first_val, bool first) {
+  if constexpr (L == 16) {
+    return __builtin_amdgcn_update_dpp(first_val, v, 0x111, 0xf, 0xf, false);   // row_shr:1
+  } else if constexpr (L == 64) {
+    return __builtin_amdgcn_update_dpp(first_val, v, 0x138, 0xf, 0xf, false);   // wave_shr:1
+  } else {
+    const int32_t s = __builtin_amdgcn_mov_dpp(v, 0x138, 0xf, 0xf, true);
+    return first ? first_val : s;
+  }
+}
+
+// First work item of a persistent workgroup is its own index; later ones
+// come from the shared counter (so a launch with no work makes no atomics).
+__device__ __forceinline__ int64_t next_item(int32_t *counter, int lane) {
+  int32_t v = 0;
+  if (lane == 0) v = atomicAdd(counter, 1);
+  return (int64_t)__builtin_amdgcn_readfirstlane(v) + gridDim.x;
 }
 
 __device__ __forceinline__ uint32_t push_sign(uint32_t acc, int32_t diff) {

@@ -81,11 +81,6 @@ __global__ __launch_bounds__(kWave) void dp_i16_kernel(DpParams p) {
   const uint32_t tab_hi = ((uint32_t)(-mi) & 0xffu) * 0x01010101u;  // x = 4..7 virtual
 
   int64_t item = blockIdx.x;
-  if (p.work_counter) {
-    int32_t v = 0;
-    if (lane == 0) v = atomicAdd(p.work_counter, 1);
-    item = __builtin_amdgcn_readfirstlane(v);
-  }
   while (item < n_items) {
     // ---------------- set-up of the two tasks of this lane group
     int64_t task[2];
@@ -115,7 +110,8 @@ __global__ __launch_bounds__(kWave) void dp_i16_kernel(DpParams p) {
       pad[h] = valid ? L * K - n[h] : 0;
     }
     const int32_t mlane = max(mg[0], mg[1]);
-    const int32_t steps = wave_max(mlane) + L - 1;
+    // uniform trip count: keeps the step loop under scalar control
+    const int32_t steps = __builtin_amdgcn_readfirstlane(wave_max(mlane)) + L - 1;
     // per-task bookkeeping for the traceback goes to LDS now, so it does not
     // occupy registers during the sweep
     if (first) {
@@ -148,6 +144,9 @@ __global__ __launch_bounds__(kWave) void dp_i16_kernel(DpParams p) {
       Rc[c] = (code[0] | 0x0c00u) | ((code[1] | 0x0c00u) << 16);
       H[c] = pack16(hv[0], hv[1]);
       F[c] = kNeg16x2;
+      // finish each column before the next: bounds live registers in set-up
+      asm volatile("" : "+v"(Rc[c]), "+v"(H[c]));
+      __builtin_amdgcn_sched_barrier(0);
     }
     // left boundary M^(i, -pad) = pad * S_MI (true value 0)
     const uint32_t bnd = pack16(pad[0] * mi, pad[1] * mi);
@@ -180,15 +179,16 @@ __global__ __launch_bounds__(kWave) void dp_i16_kernel(DpParams p) {
       }
       const uint32_t sh = (uint32_t)(t & 15) * 2;
       const uint32_t tfirst = ((twa >> sh) & 3u) | (((twb >> sh) & 3u) << 16);
-      uint32_t hl = (uint32_t)wave_shr1((int32_t)hl_out);
-      uint32_t el = (uint32_t)wave_shr1((int32_t)el_out);
-      uint32_t T = (uint32_t)wave_shr1((int32_t)t_out);
-      uint32_t hd = hl_prev;
-      if (first) { hl = bnd; el = kNeg16x2; T = tfirst; hd = bnd; }
+      // the first lane of a task receives the left boundary and the row's
+      // window base; its diagonal is the boundary received one step earlier
+      uint32_t hl = (uint32_t)group_shr1<L>((int32_t)hl_out, (int32_t)bnd, first);
+      uint32_t el = (uint32_t)group_shr1<L>((int32_t)el_out, (int32_t)kNeg16x2, first);
+      const uint32_t T = (uint32_t)group_shr1<L>((int32_t)t_out, (int32_t)tfirst, first);
+      const uint32_t hd = hl_prev;
       hl_prev = hl;
       t_out = T;
       const int32_t i = t + 1 - lg;
-      if (i >= 1 && i <= mlane) {
+      if ((uint32_t)(t - lg) < (uint32_t)mlane) {   // 1 <= i <= mlane
         // The diagonal candidate of column c+1 is formed from the old H[c]
         // before H[c] is overwritten, so every update happens in place.
         uint32_t diag = add16(hd, __builtin_amdgcn_perm(tab_hi, tab_lo, Rc[0] ^ T));
@@ -282,13 +282,7 @@ __global__ __launch_bounds__(kWave) void dp_i16_kernel(DpParams p) {
     }
     __syncthreads();
 
-    if (p.work_counter) {
-      int32_t v = 0;
-      if (lane == 0) v = atomicAdd(p.work_counter, 1);
-      item = __builtin_amdgcn_readfirstlane(v);
-    } else {
-      item += gridDim.x;
-    }
+    item = p.work_counter ? next_item(p.work_counter, lane) : item + gridDim.x;
   }
 }
 

@@ -49,11 +49,6 @@ __global__ __launch_bounds__(kWave) void dp_i32_kernel(DpParams p) {
   const int64_t n_items = (n_tasks + G - 1) / G;
 
   int64_t item = blockIdx.x;
-  if (p.work_counter) {
-    int32_t v = 0;
-    if (lane == 0) v = atomicAdd(p.work_counter, 1);
-    item = __builtin_amdgcn_readfirstlane(v);
-  }
   while (item < n_items) {
     // ---------------- task set-up
     const int64_t tix = item * G + g;
@@ -75,7 +70,8 @@ __global__ __launch_bounds__(kWave) void dp_i32_kernel(DpParams p) {
     const bool valid = task >= 0 && st == kTaskOk;
     const int32_t mg = valid ? m : 0;
     const int32_t pad = L * K - n;
-    const int32_t steps = wave_max(mg) + L - 1;
+    // uniform trip count: keeps the step loop under scalar control
+    const int32_t steps = __builtin_amdgcn_readfirstlane(wave_max(mg)) + L - 1;
     // bookkeeping for the traceback goes to LDS now, out of the sweep's registers
     if (first) { s_task[g] = task; s_n[g] = n; s_pad[g] = pad; s_st[g] = st; }
 
@@ -91,6 +87,9 @@ __global__ __launch_bounds__(kWave) void dp_i32_kernel(DpParams p) {
       Mi[c] = real ? p.mi : 0;
       H[c] = real ? p.go + q * p.ge : 0;   // M(0, q+1), or 0 left of the read
       F[c] = kNeg32;                       // D(0, j)
+      // finish each column before the next: bounds live registers in set-up
+      asm volatile("" : "+v"(Rc[c]), "+v"(Mi[c]), "+v"(H[c]));
+      __builtin_amdgcn_sched_barrier(0);
     }
 
     // window bases, 16 at a time, realigned from the base offset
@@ -120,15 +119,17 @@ __global__ __launch_bounds__(kWave) void dp_i32_kernel(DpParams p) {
         load_block((t >> 4) + 1, tn0, tn1);
       }
       const int32_t tfirst = (int32_t)((tw >> ((t & 15) * 2)) & 3u);
-      int32_t hl = wave_shr1(hl_out);
-      int32_t el = wave_shr1(el_out);
-      int32_t T = wave_shr1(t_out);
-      int32_t hd = hl_prev;
-      if (first) { hl = 0; el = kNeg32; T = tfirst; hd = 0; }
+      // the first lane of a task receives the left boundary M = 0, I = -inf
+      // and the row's window base; its diagonal is the boundary received one
+      // step earlier
+      int32_t hl = group_shr1<L>(hl_out, 0, first);
+      int32_t el = group_shr1<L>(el_out, kNeg32, first);
+      const int32_t T = group_shr1<L>(t_out, tfirst, first);
+      const int32_t hd = hl_prev;
       hl_prev = hl;
       t_out = T;
       const int32_t i = t + 1 - lg;
-      if (i >= 1 && i <= mg) {
+      if ((uint32_t)(t - lg) < (uint32_t)mg) {   // 1 <= i <= mg
         // The diagonal candidate of column c+1 is formed from the old H[c]
         // before H[c] is overwritten, so every update happens in place.
         int32_t diag = hd + (Rc[0] == T ? p.ma : Mi[0]);
@@ -199,13 +200,7 @@ __global__ __launch_bounds__(kWave) void dp_i32_kernel(DpParams p) {
     }
     __syncthreads();
 
-    if (p.work_counter) {
-      int32_t v = 0;
-      if (lane == 0) v = atomicAdd(p.work_counter, 1);
-      item = __builtin_amdgcn_readfirstlane(v);
-    } else {
-      item += gridDim.x;
-    }
+    item = p.work_counter ? next_item(p.work_counter, lane) : item + gridDim.x;
   }
 }
 
