@@ -56,6 +56,84 @@ def cpu_baseline(w, tasks: int):
                       f"C oracle with traceback, {threads} threads, {dt:.1f} s"}
 
 
+SERVE_QPS = 0.0   # frozen rate for the served workload (requests/s); 0 until measured
+
+
+def serve_bench(args):
+    """Served workload: Poisson arrivals of requests of 1..4096 reads
+    (log-uniform), reads 50-250 bp over a device-resident 100 Mbp genome.
+    With --qps 0 the requests are all submitted at once to measure capacity."""
+    import torch
+    from paper_1302_5507_amd import binding, serving, workloads
+    import oracle
+
+    g = workloads.serving_genome()
+    gw = torch.from_numpy(binding.pack_words(g).view(np.int32)).cuda()
+    pool = workloads.serving_pool(g, args.pool_reads)
+    n_total = args.serve_warmup + args.serve_requests
+    sizes = workloads.request_sizes(n_total, seed=104)
+    reqs = serving.requests_from_pool(pool, sizes)
+    srv = serving.Server(gw, n_slots=args.slots, max_tasks=16384, max_n=250, max_m=410,
+                         autotune=True)
+    qps = args.qps if args.qps is not None else SERVE_QPS
+    if qps <= 0:
+        t0 = serving.now_ns()
+        for r in reqs:
+            srv.submit(r, arrival_ns=t0)
+        for r in reqs:
+            srv.wait(r)
+        arr = np.full(len(reqs), t0, np.int64)
+        done = np.array([r.done_ns for r in reqs], np.int64)
+        lag = np.zeros(len(reqs), np.int64)
+    else:
+        arr, done, lag = serving.run_open_loop(srv, reqs, qps, seed=104)
+    assert all(r.rc == 0 for r in reqs), "served requests failed"
+    meas = slice(args.serve_warmup, n_total)
+    cells = sum(r.cells for r in reqs[meas])
+    span = (done[meas].max() - arr[meas].min()) * 1e-9
+    lat = (done[meas] - arr[meas]) * 1e-6
+    rng = np.random.default_rng(4)
+    checked = 0
+    for k in rng.choice(np.arange(args.serve_warmup, n_total), size=min(20, args.serve_requests),
+                        replace=False):
+        r = reqs[k]
+        ref = oracle.align_workload(pool, oracle.scoring(*SCORING), idx=r.pool_idx, cigar_stride=500)
+        assert np.array_equal(r.score, ref.score) and np.array_equal(r.cigar_len, ref.cigar_len)
+        assert np.array_equal(r.ref_begin, ref.ref_begin) and np.array_equal(r.ref_end, ref.ref_end)
+        for t, row in enumerate(r.cigar_rows()):
+            assert np.array_equal(row, ref.cigar_of(t))
+        checked += 1
+    st = srv.stats()
+    srv.close()
+    mean_cells = float(np.mean([r.cells for r in reqs[meas]]))
+    line = {
+        "metric": METRIC,
+        "value": round(cells / span / 1e9, 2),
+        "unit": "GCUPS",
+        "n_gpus": 1,
+        "steps": args.serve_requests,
+        "warmup": args.serve_warmup,
+        "ms_per_step": round(float(np.mean(lat)), 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int16+int32",
+        "data": "synthetic",
+        "config": {"workload": "served: Poisson arrivals of 1-4096-read requests (log-uniform), "
+                               "reads 50-250 bp vs n+160 windows in a resident 100 Mbp genome",
+                   "qps": qps if qps > 0 else "saturation", "slots": args.slots,
+                   "requests": args.serve_requests, "mean_cells_per_request": round(mean_cells)},
+        "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3),
+                       "p99": round(float(np.percentile(lat, 99)), 3),
+                       "max": round(float(lat.max()), 3)},
+        "achieved_qps": round(args.serve_requests / span, 1),
+        "submit_lag_ms_p99": round(float(np.percentile(lag[meas], 99)) * 1e-6, 3),
+        "server": {k: (round(v, 4) if isinstance(v, float) else v) for k, v in st.items()},
+        "oracle_checked_requests": checked,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def time_form(al, dw, res, flags, steps, warmup):
     import torch
     stream = torch.cuda.current_stream()
@@ -82,7 +160,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="config2")
+    ap.add_argument("--workload", choices=sorted(WORKLOADS) + ["config4"], default="config2")
+    ap.add_argument("--qps", type=float, default=None, help="served workload: arrival rate (0: saturate)")
+    ap.add_argument("--slots", type=int, default=4)
+    ap.add_argument("--pool-reads", type=int, default=400_000)
+    ap.add_argument("--serve-warmup", type=int, default=1000)
+    ap.add_argument("--serve-requests", type=int, default=20000)
     ap.add_argument("--form", choices=["plain", "batched", "both"], default="both")
     ap.add_argument("--cpu-tasks", type=int, default=1_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -110,6 +193,9 @@ def main():
         print(json.dumps({"calibrate_copy_bytes": args.calibrate_copy}), flush=True)
         return
 
+    if args.workload == "config4":
+        serve_bench(args)
+        return
     desc, gen, headline = WORKLOADS[args.workload]
     w = getattr(workloads, gen)()
     al = binding.Aligner(0)

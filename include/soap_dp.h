@@ -193,6 +193,99 @@ int soap_dp_set_class_shape(soap_dp_ctx *ctx, int32_t precision, int32_t capacit
  * count, writes up to n_max. */
 int soap_dp_list_shapes(int32_t precision, soap_dp_class_info *out, int32_t n_max);
 
+/* ------------------------------------------------------------------------
+ * Serving: continuous batching over a device-resident genome.
+ *
+ * A server owns `n_slots` slots, each with its own stream, library context
+ * and device buffers for up to `max_tasks` tasks.  Requests are queued on
+ * submit; a dispatcher thread merges queued requests, first in first out,
+ * into one batch per free slot (a request is admitted when the slot's
+ * buffers have room for it), uploads the reads, runs the batched form on
+ * the slot's stream and copies the results back, so several batches
+ * overlap on the device while new requests keep arriving.  Windows are
+ * base offsets into the resident genome: no sequence is copied for them.
+ * Results are written into the caller's host buffers, which must stay
+ * valid until the request completes; a request completes when
+ * soap_dp_server_wait returns for it.
+ */
+#define SOAP_DP_E2BIG (-5)   /* request larger than one slot's capacity */
+#define SOAP_DP_ESTOPPED (-6) /* server is shutting down */
+
+typedef struct soap_dp_server soap_dp_server;
+
+typedef struct {
+  int device_ordinal;
+  int n_slots;                 /* batches in flight at once (streams), 1..16 */
+  int32_t max_tasks;           /* tasks per slot (per merged batch) */
+  int64_t max_read_words;      /* packed read words per slot */
+  int32_t max_n, max_m;        /* bounds on every task of every request */
+  soap_dp_scoring scoring;
+  const uint32_t *genome;      /* DEVICE pointer, packed, caller-owned, resident */
+  uint64_t genome_words;
+  int autotune;                /* nonzero: autotune the slots' shapes at start */
+} soap_dp_server_config;
+
+/* HOST results of one served request.  CIGARs are packed: task t's runs
+ * start at the sum of cigar_len over the tasks before it.  If they need more
+ * than cigar_capacity words the request fails with SOAP_DP_E2BIG (its other
+ * outputs are still written); n_tasks * (2 * max_n - 1) words always
+ * suffice. */
+typedef struct {
+  int32_t *score;
+  int32_t *ref_begin;
+  int32_t *ref_end;
+  int32_t *cigar_len;
+  uint8_t *status;
+  uint32_t *cigar;
+  int64_t cigar_capacity;
+} soap_dp_host_result;
+
+typedef struct {
+  /* HOST arrays describing the request's tasks */
+  const uint32_t *read_codes;     /* packed reads, read t at word read_word_off[t] */
+  const uint64_t *read_word_off;
+  const int32_t *read_len;
+  uint64_t read_words;            /* words in read_codes */
+  const uint64_t *ref_base_off;   /* base offsets into the resident genome */
+  const int32_t *ref_len;
+  int32_t n_tasks;
+  soap_dp_host_result out;
+  uint64_t arrival_ns;            /* scheduled arrival, soap_dp_now_ns() clock */
+} soap_dp_request;
+
+typedef struct {
+  uint64_t submitted, completed, rejected, batches;
+  uint64_t tasks, cells;
+  double device_busy_s;           /* union of batch intervals on the device */
+} soap_dp_server_stats;
+
+/* Monotonic clock used for arrival and completion times (nanoseconds). */
+uint64_t soap_dp_now_ns(void);
+
+int soap_dp_server_create(soap_dp_server **srv, const soap_dp_server_config *cfg);
+
+/* Queue a request; returns a ticket.  SOAP_DP_E2BIG if it can never fit a
+ * slot.  The request's host arrays are copied before this returns; the
+ * result arrays are written when it completes. */
+int soap_dp_server_submit(soap_dp_server *srv, const soap_dp_request *req, uint64_t *ticket);
+
+/* 1 when the request has completed (results written), 0 while pending,
+ * a negative code if it failed. */
+int soap_dp_server_poll(soap_dp_server *srv, uint64_t ticket);
+
+/* Block until the request has completed and release its ticket; its
+ * completion time (when the dispatcher saw its batch finish) goes to
+ * *done_ns when non-NULL.  Returns the request's result code. */
+int soap_dp_server_wait(soap_dp_server *srv, uint64_t ticket, uint64_t *done_ns);
+
+/* Block until every submitted request has completed. */
+int soap_dp_server_drain(soap_dp_server *srv);
+
+int soap_dp_server_stats_get(soap_dp_server *srv, soap_dp_server_stats *out);
+
+/* Stop accepting requests, finish the queued ones, release everything. */
+int soap_dp_server_destroy(soap_dp_server *srv);
+
 /* Human-readable text for an error code. */
 const char *soap_dp_strerror(int code);
 

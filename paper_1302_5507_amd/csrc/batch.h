@@ -30,5 +30,8 @@ struct BucketBuffers {
 hipError_t launch_bucketing(const DpParams &p, const ClassTable &ct, const BucketBuffers &b,
                             hipStream_t stream);
 hipError_t launch_zero(int32_t *a, int n, hipStream_t stream);
+// Pack the CIGAR rows of tasks [0, n) back to back (at most out_cap words).
+hipError_t launch_compact_cigar(const uint32_t *cigar, int32_t stride, const int32_t *cigar_len,
+                                int32_t n, uint32_t *out, int64_t out_cap, hipStream_t stream);
 
 }  // namespace soapdp

@@ -1,0 +1,470 @@
+// Continuous-batching server over the batched form (declared in
+// include/soap_dp.h).  One dispatcher thread owns every HIP call: it
+// retires finished batches (copying each request's slice of the results to
+// the caller's buffers) and, for every free slot, merges the queued
+// requests in arrival order into one batch, uploads it, enqueues the
+// batched alignment and the result copies on the slot's stream and records
+// an event.  Slots run concurrently, so batches overlap on the device.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <memory>
+#include <mutex>
+#include <new>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/soap_dp.h"
+#include "batch.h"
+
+namespace {
+
+// Words of packed CIGAR copied back with every batch, per task; a batch
+// whose alignments need more fetches the rest when it retires.
+constexpr int32_t kCompactWordsPerTask = 8;
+
+uint64_t now_ns() {
+  return uint64_t(std::chrono::duration_cast<std::chrono::nanoseconds>(
+                      std::chrono::steady_clock::now().time_since_epoch())
+                      .count());
+}
+
+struct Request {
+  uint64_t ticket = 0;
+  int32_t n_tasks = 0;
+  std::vector<uint32_t> reads;
+  std::vector<uint64_t> rwo;
+  std::vector<int32_t> rl, ml;
+  std::vector<uint64_t> rbo;
+  soap_dp_host_result out{};
+  uint64_t arrival_ns = 0;
+  int64_t cells = 0;
+};
+
+struct TicketState {
+  bool done = false;
+  int rc = SOAP_DP_OK;
+  uint64_t done_ns = 0;
+};
+
+template <class T>
+bool dalloc(T **p, size_t n) {
+  return hipMalloc(reinterpret_cast<void **>(p), std::max<size_t>(n, 1) * sizeof(T)) == hipSuccess;
+}
+template <class T>
+bool halloc(T **p, size_t n) {
+  return hipHostMalloc(reinterpret_cast<void **>(p), std::max<size_t>(n, 1) * sizeof(T),
+                       hipHostMallocDefault) == hipSuccess;
+}
+
+struct Slot {
+  soap_dp_ctx *ctx = nullptr;
+  hipStream_t stream = nullptr;
+  hipEvent_t start = nullptr, done = nullptr;
+  // device inputs and outputs
+  uint32_t *d_reads = nullptr;
+  uint64_t *d_rwo = nullptr, *d_rbo = nullptr;
+  int32_t *d_rl = nullptr, *d_ml = nullptr;
+  int32_t *d_i32 = nullptr;   // score | begin | end | cigar_len
+  uint32_t *d_cigar = nullptr;
+  uint32_t *d_packed = nullptr;   // CIGARs packed back to back
+  uint8_t *d_status = nullptr;
+  // pinned host staging
+  uint32_t *h_reads = nullptr;
+  uint64_t *h_rwo = nullptr, *h_rbo = nullptr;
+  int32_t *h_rl = nullptr, *h_ml = nullptr;
+  int32_t *h_i32 = nullptr;
+  uint32_t *h_cigar = nullptr;    // packed CIGARs
+  uint8_t *h_status = nullptr;
+  // batch in flight
+  bool busy = false;
+  std::vector<std::unique_ptr<Request>> reqs;
+  std::vector<int32_t> first_task;
+  int32_t tasks = 0;
+};
+
+}  // namespace
+
+struct soap_dp_server {
+  soap_dp_server_config cfg{};
+  int32_t stride = 0;
+  std::vector<Slot> slots;
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  std::deque<std::unique_ptr<Request>> queue;
+  std::unordered_map<uint64_t, TicketState> tickets;
+  uint64_t next_ticket = 1;
+  bool stopping = false;
+  std::thread worker;
+  soap_dp_server_stats stats{};
+  int fatal = SOAP_DP_OK;
+};
+
+namespace {
+
+void free_slot(Slot &s) {
+  if (s.ctx) soap_dp_destroy(s.ctx);
+  if (s.stream) (void)hipStreamDestroy(s.stream);
+  if (s.start) (void)hipEventDestroy(s.start);
+  if (s.done) (void)hipEventDestroy(s.done);
+  for (void *p : {(void *)s.d_reads, (void *)s.d_rwo, (void *)s.d_rbo, (void *)s.d_rl, (void *)s.d_ml,
+                  (void *)s.d_i32, (void *)s.d_cigar, (void *)s.d_status, (void *)s.d_packed})
+    if (p) (void)hipFree(p);
+  for (void *p : {(void *)s.h_reads, (void *)s.h_rwo, (void *)s.h_rbo, (void *)s.h_rl, (void *)s.h_ml,
+                  (void *)s.h_i32, (void *)s.h_cigar, (void *)s.h_status})
+    if (p) (void)hipHostFree(p);
+  s = Slot{};
+}
+
+int init_slot(soap_dp_server *srv, Slot &s) {
+  const auto &c = srv->cfg;
+  const size_t T = size_t(c.max_tasks), Wd = size_t(c.max_read_words), S = size_t(srv->stride);
+  int rc = soap_dp_create(&s.ctx, c.device_ordinal);
+  if (rc) return rc;
+  if (hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&s.start, hipEventDefault) != hipSuccess ||
+      hipEventCreateWithFlags(&s.done, hipEventDefault) != hipSuccess)
+    return SOAP_DP_EHIP;
+  const bool ok = dalloc(&s.d_reads, Wd) && dalloc(&s.d_rwo, T) && dalloc(&s.d_rbo, T) &&
+                  dalloc(&s.d_rl, T) && dalloc(&s.d_ml, T) && dalloc(&s.d_i32, 4 * T) &&
+                  dalloc(&s.d_cigar, T * S) && dalloc(&s.d_status, T) && dalloc(&s.d_packed, T * S) &&
+                  halloc(&s.h_reads, Wd) && halloc(&s.h_rwo, T) && halloc(&s.h_rbo, T) &&
+                  halloc(&s.h_rl, T) && halloc(&s.h_ml, T) && halloc(&s.h_i32, 4 * T) &&
+                  halloc(&s.h_cigar, T * S) && halloc(&s.h_status, T);
+  if (!ok) {
+    (void)hipGetLastError();
+    return SOAP_DP_ENOMEM;
+  }
+  return soap_dp_reserve(s.ctx, c.max_tasks, c.max_n, c.max_m, SOAP_DP_BATCHED);
+}
+
+// Finished batch: copy each request's slice to its caller buffers.
+void retire(soap_dp_server *srv, Slot &s, uint64_t t_done) {
+  const int32_t T = srv->cfg.max_tasks;
+  const int32_t S = srv->stride;
+  (void)S;
+  float ms = 0;
+  (void)hipEventElapsedTime(&ms, s.start, s.done);
+  std::vector<std::pair<uint64_t, int>> finished;
+  // packed CIGARs: fetch what did not fit the words copied with the batch
+  int64_t total = 0;
+  for (int32_t t = 0; t < s.tasks; ++t) total += std::max(s.h_i32[3 * T + t], 0);
+  const int64_t have = int64_t(s.tasks) * kCompactWordsPerTask;
+  if (total > have)
+    (void)hipMemcpy(s.h_cigar + have, s.d_packed + have, size_t(total - have) * 4, hipMemcpyDeviceToHost);
+  int64_t off = 0;
+  for (size_t r = 0; r < s.reqs.size(); ++r) {
+    Request &q = *s.reqs[r];
+    const int32_t f = s.first_task[r], n = q.n_tasks;
+    const soap_dp_host_result &o = q.out;
+    std::memcpy(o.score, s.h_i32 + f, size_t(n) * 4);
+    std::memcpy(o.ref_begin, s.h_i32 + T + f, size_t(n) * 4);
+    std::memcpy(o.ref_end, s.h_i32 + 2 * T + f, size_t(n) * 4);
+    std::memcpy(o.cigar_len, s.h_i32 + 3 * T + f, size_t(n) * 4);
+    std::memcpy(o.status, s.h_status + f, size_t(n));
+    int64_t words = 0;
+    for (int32_t t = 0; t < n; ++t) words += std::max(o.cigar_len[t], 0);
+    const int64_t fit = std::min(words, o.cigar_capacity);
+    std::memcpy(o.cigar, s.h_cigar + off, size_t(std::max<int64_t>(fit, 0)) * 4);
+    off += words;
+    finished.emplace_back(q.ticket, words > o.cigar_capacity ? SOAP_DP_E2BIG : SOAP_DP_OK);
+  }
+  {
+    std::lock_guard<std::mutex> lk(srv->mu);
+    for (auto &fq : finished) {
+      TicketState &ts = srv->tickets[fq.first];
+      ts.done = true;
+      ts.rc = fq.second;
+      ts.done_ns = t_done;
+    }
+    srv->stats.completed += finished.size();
+    srv->stats.batches += 1;
+    srv->stats.tasks += uint64_t(s.tasks);
+    for (auto &q : s.reqs) srv->stats.cells += uint64_t(q->cells);
+    srv->stats.device_busy_s += double(ms) * 1e-3;
+  }
+  srv->cv_done.notify_all();
+  s.reqs.clear();
+  s.first_task.clear();
+  s.tasks = 0;
+  s.busy = false;
+}
+
+// Merge queued requests (FIFO) into the free slot and launch the batch.
+int launch(soap_dp_server *srv, Slot &s, std::vector<std::unique_ptr<Request>> &take) {
+  const auto &c = srv->cfg;
+  const int32_t T = c.max_tasks, S = srv->stride;
+  int32_t nt = 0;
+  uint64_t nw = 0;
+  for (auto &q : take) {
+    s.first_task.push_back(nt);
+    std::memcpy(s.h_reads + nw, q->reads.data(), q->reads.size() * 4);
+    for (int32_t t = 0; t < q->n_tasks; ++t) {
+      s.h_rwo[nt + t] = q->rwo[size_t(t)] + nw;
+      s.h_rl[nt + t] = q->rl[size_t(t)];
+      s.h_rbo[nt + t] = q->rbo[size_t(t)];
+      s.h_ml[nt + t] = q->ml[size_t(t)];
+    }
+    nt += q->n_tasks;
+    nw += q->reads.size();
+    s.reqs.push_back(std::move(q));
+  }
+  take.clear();
+  s.tasks = nt;
+  // Every batch of a slot has the slot's full capacity: the tail past the
+  // merged requests holds zero-length reads, which the bucketing marks
+  // invalid and skips.  The call is then identical from batch to batch
+  // (same buffers, same sizes), so the slot's graph is captured once and
+  // replayed.
+  std::memset(s.h_rl + nt, 0, size_t(T - nt) * 4);
+  hipStream_t st = s.stream;
+  bool ok = hipEventRecord(s.start, st) == hipSuccess &&
+            hipMemcpyAsync(s.d_reads, s.h_reads, std::max<uint64_t>(nw, 1) * 4, hipMemcpyHostToDevice, st) == hipSuccess &&
+            hipMemcpyAsync(s.d_rwo, s.h_rwo, size_t(nt) * 8, hipMemcpyHostToDevice, st) == hipSuccess &&
+            hipMemcpyAsync(s.d_rbo, s.h_rbo, size_t(nt) * 8, hipMemcpyHostToDevice, st) == hipSuccess &&
+            hipMemcpyAsync(s.d_rl, s.h_rl, size_t(T) * 4, hipMemcpyHostToDevice, st) == hipSuccess &&
+            hipMemcpyAsync(s.d_ml, s.h_ml, size_t(nt) * 4, hipMemcpyHostToDevice, st) == hipSuccess;
+  if (!ok) return SOAP_DP_EHIP;
+  soap_dp_batch in{};
+  in.read_codes = s.d_reads;
+  in.read_word_off = s.d_rwo;
+  in.read_len = s.d_rl;
+  in.ref_codes = c.genome;
+  in.ref_base_off = s.d_rbo;
+  in.ref_len = s.d_ml;
+  in.n_tasks = T;
+  in.max_n = c.max_n;
+  in.max_m = c.max_m;
+  in.read_words = uint64_t(c.max_read_words);
+  in.ref_words = c.genome_words;
+  soap_dp_result out{};
+  out.score = s.d_i32;
+  out.ref_begin = s.d_i32 + T;
+  out.ref_end = s.d_i32 + 2 * T;
+  out.cigar_len = s.d_i32 + 3 * T;
+  out.cigar = s.d_cigar;
+  out.cigar_stride = S;
+  out.status = s.d_status;
+  const int rc = soap_dp_align_batch(s.ctx, &in, &c.scoring, &out, st, SOAP_DP_BATCHED);
+  if (rc) return rc;
+  ok = soapdp::launch_compact_cigar(s.d_cigar, S, s.d_i32 + 3 * T, nt, s.d_packed, int64_t(T) * S, st) == hipSuccess;
+  for (int a = 0; ok && a < 4; ++a)
+    ok = hipMemcpyAsync(s.h_i32 + size_t(a) * T, s.d_i32 + size_t(a) * T, size_t(nt) * 4,
+                        hipMemcpyDeviceToHost, st) == hipSuccess;
+  ok = ok &&
+       hipMemcpyAsync(s.h_status, s.d_status, size_t(nt), hipMemcpyDeviceToHost, st) == hipSuccess &&
+       hipMemcpyAsync(s.h_cigar, s.d_packed, size_t(nt) * kCompactWordsPerTask * 4,
+                      hipMemcpyDeviceToHost, st) == hipSuccess &&
+       hipEventRecord(s.done, st) == hipSuccess;
+  if (!ok) return SOAP_DP_EHIP;
+  s.busy = true;
+  return SOAP_DP_OK;
+}
+
+void dispatcher(soap_dp_server *srv) {
+  (void)hipSetDevice(srv->cfg.device_ordinal);
+  const auto &c = srv->cfg;
+  std::vector<std::unique_ptr<Request>> take;
+  for (;;) {
+    bool progressed = false;
+    // retire finished batches
+    for (auto &s : srv->slots) {
+      if (!s.busy) continue;
+      const hipError_t q = hipEventQuery(s.done);
+      if (q == hipSuccess) {
+        retire(srv, s, now_ns());
+        progressed = true;
+      } else if (q != hipErrorNotReady) {
+        std::lock_guard<std::mutex> lk(srv->mu);
+        srv->fatal = SOAP_DP_EHIP;
+      }
+    }
+    // fill free slots
+    bool all_idle = true;
+    for (auto &s : srv->slots) {
+      if (s.busy) { all_idle = false; continue; }
+      {
+        std::lock_guard<std::mutex> lk(srv->mu);
+        int32_t nt = 0;
+        uint64_t nw = 0;
+        while (!srv->queue.empty()) {
+          Request &q = *srv->queue.front();
+          if (nt + q.n_tasks > c.max_tasks || nw + q.reads.size() > uint64_t(c.max_read_words)) break;
+          nt += q.n_tasks;
+          nw += q.reads.size();
+          take.push_back(std::move(srv->queue.front()));
+          srv->queue.pop_front();
+        }
+      }
+      if (take.empty()) continue;
+      const int rc = launch(srv, s, take);
+      if (rc) {
+        std::lock_guard<std::mutex> lk(srv->mu);
+        srv->fatal = rc;
+        for (auto &q : s.reqs) {
+          TicketState &ts = srv->tickets[q->ticket];
+          ts.done = true;
+          ts.rc = rc;
+          ts.done_ns = now_ns();
+        }
+        s.reqs.clear();
+        s.first_task.clear();
+        s.busy = false;
+        srv->cv_done.notify_all();
+        continue;
+      }
+      all_idle = false;
+      progressed = true;
+    }
+    std::unique_lock<std::mutex> lk(srv->mu);
+    if (srv->stopping && srv->queue.empty() && all_idle) break;
+    if (!progressed) {
+      if (all_idle && srv->queue.empty())
+        srv->cv_work.wait_for(lk, std::chrono::milliseconds(5));
+      else {
+        lk.unlock();
+        std::this_thread::sleep_for(std::chrono::microseconds(20));
+      }
+    }
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+uint64_t soap_dp_now_ns(void) { return now_ns(); }
+
+int soap_dp_server_create(soap_dp_server **out, const soap_dp_server_config *cfg) {
+  if (!out || !cfg) return SOAP_DP_EINVAL;
+  *out = nullptr;
+  if (cfg->n_slots < 1 || cfg->n_slots > 16 || cfg->max_tasks < 1 || cfg->max_read_words < 1 ||
+      cfg->max_n < 1 || cfg->max_n > SOAP_DP_MAX_READ || cfg->max_m < 1 ||
+      cfg->max_m > SOAP_DP_MAX_WINDOW || !cfg->genome || cfg->genome_words == 0)
+    return SOAP_DP_EINVAL;
+  auto *srv = new (std::nothrow) soap_dp_server();
+  if (!srv) return SOAP_DP_ENOMEM;
+  srv->cfg = *cfg;
+  srv->stride = 2 * cfg->max_n - 1;
+  srv->slots.resize(size_t(cfg->n_slots));
+  int rc = SOAP_DP_OK;
+  (void)hipSetDevice(cfg->device_ordinal);
+  for (auto &s : srv->slots) {
+    rc = init_slot(srv, s);
+    if (rc) break;
+  }
+  if (!rc && cfg->autotune) {
+    rc = soap_dp_autotune(srv->slots[0].ctx, nullptr, 1);
+    if (!rc) {
+      soap_dp_class_info info[64];
+      const int n = soap_dp_get_classes(srv->slots[0].ctx, info, 64);
+      for (size_t k = 1; k < srv->slots.size() && !rc; ++k)
+        for (int q = 0; q < n && !rc; ++q)
+          rc = soap_dp_set_class_shape(srv->slots[k].ctx, info[q].precision, info[q].capacity,
+                                       info[q].lanes, info[q].cells);
+    }
+  }
+  if (rc) {
+    for (auto &s : srv->slots) free_slot(s);
+    delete srv;
+    return rc;
+  }
+  srv->worker = std::thread(dispatcher, srv);
+  *out = srv;
+  return SOAP_DP_OK;
+}
+
+int soap_dp_server_submit(soap_dp_server *srv, const soap_dp_request *req, uint64_t *ticket) {
+  if (!srv || !req || !ticket || req->n_tasks < 1) return SOAP_DP_EINVAL;
+  const auto &c = srv->cfg;
+  if (!req->read_codes || !req->read_word_off || !req->read_len || !req->ref_base_off ||
+      !req->ref_len || !req->out.score || !req->out.ref_begin || !req->out.ref_end ||
+      !req->out.cigar || !req->out.cigar_len || !req->out.status || req->out.cigar_capacity < 0)
+    return SOAP_DP_EINVAL;
+  if (req->n_tasks > c.max_tasks || req->read_words > uint64_t(c.max_read_words)) {
+    std::lock_guard<std::mutex> lk(srv->mu);
+    srv->stats.rejected += 1;
+    return SOAP_DP_E2BIG;
+  }
+  auto q = std::make_unique<Request>();
+  const size_t n = size_t(req->n_tasks);
+  q->n_tasks = req->n_tasks;
+  q->reads.assign(req->read_codes, req->read_codes + req->read_words);
+  q->rwo.assign(req->read_word_off, req->read_word_off + n);
+  q->rl.assign(req->read_len, req->read_len + n);
+  q->rbo.assign(req->ref_base_off, req->ref_base_off + n);
+  q->ml.assign(req->ref_len, req->ref_len + n);
+  q->out = req->out;
+  q->arrival_ns = req->arrival_ns;
+  for (size_t t = 0; t < n; ++t) q->cells += int64_t(q->rl[t]) * int64_t(q->ml[t]);
+  {
+    std::lock_guard<std::mutex> lk(srv->mu);
+    if (srv->stopping) return SOAP_DP_ESTOPPED;
+    if (srv->fatal) return srv->fatal;
+    q->ticket = srv->next_ticket++;
+    *ticket = q->ticket;
+    srv->tickets[q->ticket] = TicketState{};
+    srv->queue.push_back(std::move(q));
+    srv->stats.submitted += 1;
+  }
+  srv->cv_work.notify_one();
+  return SOAP_DP_OK;
+}
+
+int soap_dp_server_poll(soap_dp_server *srv, uint64_t ticket) {
+  if (!srv) return SOAP_DP_EINVAL;
+  std::lock_guard<std::mutex> lk(srv->mu);
+  auto it = srv->tickets.find(ticket);
+  if (it == srv->tickets.end()) return SOAP_DP_EINVAL;
+  if (!it->second.done) return 0;
+  return it->second.rc ? it->second.rc : 1;
+}
+
+int soap_dp_server_wait(soap_dp_server *srv, uint64_t ticket, uint64_t *done_ns) {
+  if (!srv) return SOAP_DP_EINVAL;
+  std::unique_lock<std::mutex> lk(srv->mu);
+  auto it = srv->tickets.find(ticket);
+  if (it == srv->tickets.end()) return SOAP_DP_EINVAL;
+  srv->cv_done.wait(lk, [&] { return srv->tickets[ticket].done; });
+  const TicketState ts = srv->tickets[ticket];
+  srv->tickets.erase(ticket);
+  if (done_ns) *done_ns = ts.done_ns;
+  return ts.rc;
+}
+
+int soap_dp_server_drain(soap_dp_server *srv) {
+  if (!srv) return SOAP_DP_EINVAL;
+  std::unique_lock<std::mutex> lk(srv->mu);
+  srv->cv_done.wait(lk, [&] { return srv->stats.completed + 0 >= srv->stats.submitted || srv->fatal; });
+  return srv->fatal;
+}
+
+int soap_dp_server_stats_get(soap_dp_server *srv, soap_dp_server_stats *out) {
+  if (!srv || !out) return SOAP_DP_EINVAL;
+  std::lock_guard<std::mutex> lk(srv->mu);
+  *out = srv->stats;
+  return SOAP_DP_OK;
+}
+
+int soap_dp_server_destroy(soap_dp_server *srv) {
+  if (!srv) return SOAP_DP_EINVAL;
+  {
+    std::lock_guard<std::mutex> lk(srv->mu);
+    srv->stopping = true;
+  }
+  srv->cv_work.notify_all();
+  if (srv->worker.joinable()) srv->worker.join();
+  (void)hipSetDevice(srv->cfg.device_ordinal);
+  (void)hipDeviceSynchronize();
+  for (auto &s : srv->slots) free_slot(s);
+  delete srv;
+  return SOAP_DP_OK;
+}
+
+}  // extern "C"

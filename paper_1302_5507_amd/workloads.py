@@ -300,6 +300,29 @@ def serving_request(genome: np.ndarray, rng, lengths=SERVE_LENGTHS, max_batch: i
                     lambda r, k: _geometric_trunc(r, 0.25, k, 30), rng)
 
 
+def serving_pool(genome: np.ndarray, n_reads: int, seed: int = 104,
+                 lengths=SERVE_LENGTHS) -> Workload:
+    """A pool of served reads over the resident genome: lengths uniform over
+    {50,75,100,150,250}, windows m = n + 160 at uniform genome positions, the
+    uneven batch's error model.  Requests are consecutive slices of it."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    n = rng.choice(np.asarray(lengths), size=n_reads)
+    m = n + 160
+    law = lambda r, idx: r.integers(0, 161, size=idx.size)
+    w = simulate("serve-pool", genome, n, m, law, 0.04, 0.005,
+                 lambda r, k: _geometric_trunc(r, 0.25, k, 30), rng,
+                 params=dict(p_sub=0.04, p_ind=0.005, indel="geometric(1/4)<=30"))
+    w.seed = seed
+    return w
+
+
+def request_sizes(count: int, seed: int, max_batch: int = 4096) -> np.ndarray:
+    """Batch sizes floor(exp(U(0, ln(max_batch + 1)))) in [1, max_batch]."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    b = np.floor(np.exp(rng.uniform(0.0, math.log(max_batch + 1), size=count))).astype(np.int64)
+    return np.clip(b, 1, max_batch)
+
+
 def poisson_arrivals(rate_per_s: float, count: int, seed: int) -> np.ndarray:
     """Open-loop arrival times (seconds from start) of a Poisson process."""
     rng = np.random.Generator(np.random.PCG64(seed))

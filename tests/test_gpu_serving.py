@@ -1,0 +1,94 @@
+"""GPU tests of the continuous-batching server: every served result equals
+the oracle's, a request's result is the same alone and in the mix
+(tolerance 0), oversized requests are rejected, and an open-loop run
+completes every request."""
+import numpy as np
+import pytest
+
+from paper_1302_5507_amd import binding, serving, workloads
+from tests.conftest import CONFIG_SCORING
+from tests.gpu_util import oracle_align
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def setup():
+    import torch
+    g = workloads.random_genome(2_000_000, 4)
+    gw = torch.from_numpy(binding.pack_words(g).view(np.int32)).cuda()
+    pool = workloads.serving_pool(g, 30000, seed=7)
+    srv = serving.Server(gw, n_slots=3, max_tasks=4096, max_n=250, max_m=410, autotune=False)
+    yield g, gw, pool, srv
+    srv.close()
+
+
+def _fields(r):
+    return (r.score.copy(), r.ref_begin.copy(), r.ref_end.copy(), r.cigar_len.copy(),
+            r.status.copy(), [c.copy() for c in r.cigar_rows()])
+
+
+def _check_oracle(pool, r):
+    ref = oracle_align(pool, CONFIG_SCORING, idx=r.pool_idx, stride=500)
+    assert np.array_equal(r.status, ref.status)
+    for f in ("score", "ref_begin", "ref_end", "cigar_len"):
+        assert np.array_equal(getattr(r, f), getattr(ref, f)), f
+    for t, row in enumerate(r.cigar_rows()):
+        assert np.array_equal(row, ref.cigar_of(t)), t
+
+
+def test_mix_equals_oracle_and_alone(setup):
+    g, gw, pool, srv = setup
+    sizes = workloads.request_sizes(120, seed=3, max_batch=1024)
+    mix = serving.requests_from_pool(pool, sizes)
+    for r in mix:
+        srv.submit(r)
+    for r in mix:
+        assert srv.wait(r) == 0
+    for r in mix:
+        _check_oracle(pool, r)
+    st = srv.stats()
+    assert st["completed"] >= len(mix) and st["batches"] < len(mix)   # requests were merged
+    pick = np.random.default_rng(1).choice(len(mix), 12, replace=False)
+    alone = serving.requests_from_pool(pool, sizes)     # same slices, fresh buffers
+    for k in pick:
+        r = alone[k]
+        srv.submit(r)
+        assert srv.wait(r) == 0
+        a, b = _fields(r), _fields(mix[k])
+        for x, y in zip(a[:5], b[:5]):
+            assert np.array_equal(x, y)
+        assert all(np.array_equal(x, y) for x, y in zip(a[5], b[5]))
+
+
+def test_oversized_request_rejected(setup):
+    g, gw, pool, srv = setup
+    big = serving.requests_from_pool(pool, [4097])[0]
+    with pytest.raises(binding.SoapDpError) as e:
+        srv.submit(big)
+    assert e.value.code == serving.SOAP_DP_E2BIG
+    assert srv.stats()["rejected"] >= 1
+
+
+def test_cigar_capacity_overflow_is_reported(setup):
+    g, gw, pool, srv = setup
+    r = serving.requests_from_pool(pool, [64])[0]
+    r2 = serving.HostRequest(r.read_words, r.read_word_off, r.read_len, r.ref_base_off, r.ref_len,
+                             cigar_words_per_task=0)
+    r2.pool_idx = r.pool_idx
+    srv.submit(r2)
+    assert srv.wait(r2) == serving.SOAP_DP_E2BIG
+    ref = oracle_align(pool, CONFIG_SCORING, idx=r.pool_idx, stride=500)
+    assert np.array_equal(r2.score, ref.score) and np.array_equal(r2.cigar_len, ref.cigar_len)
+
+
+def test_open_loop_run_completes(setup):
+    g, gw, pool, srv = setup
+    sizes = workloads.request_sizes(300, seed=5, max_batch=2048)
+    reqs = serving.requests_from_pool(pool, sizes, start=777)
+    arr, done, lag = serving.run_open_loop(srv, reqs, rate_hz=2000.0, seed=9)
+    lat = done - arr
+    assert (lat > 0).all()
+    assert all(r.rc == 0 for r in reqs)
+    for r in reqs[::37]:
+        _check_oracle(pool, r)
