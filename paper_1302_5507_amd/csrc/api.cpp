@@ -73,6 +73,11 @@ struct soap_dp_ctx {
   // batched form
   std::vector<ClassSpec> classes;
   hipStream_t capture_stream = nullptr;
+  // class kernels run concurrently: one stream and join event per class,
+  // forked from the caller's stream after bucketing
+  std::vector<hipStream_t> class_streams;
+  std::vector<hipEvent_t> join_events;
+  hipEvent_t fork_event = nullptr;
   std::vector<GraphEntry> graphs;
   uint64_t epoch = 1;   // bumped whenever buffers or shapes change
   uint64_t use_clock = 0;
@@ -308,16 +313,36 @@ std::vector<int> live_classes(const soap_dp_ctx *ctx, int32_t max_n, const soap_
   return live;
 }
 
+// Scratch of one class's launch, rounded up to 256 bytes.
+size_t class_scratch_bytes(const soap_dp_ctx *ctx, const ClassSpec &c, int64_t n_tasks,
+                           int32_t max_m) {
+  const size_t b = size_t(grid_for(ctx, c.prec, c.shape, n_tasks, max_m)) *
+                   slot_dwords(c.prec, c.shape, max_m) * 4;
+  return (b + 255) & ~size_t(255);
+}
+
+// The live classes run concurrently, each in its own scratch region.
 size_t batched_scratch_bytes(const soap_dp_ctx *ctx, int64_t n_tasks, int32_t max_m,
                              const std::vector<int> &live) {
   size_t b = 0;
-  for (int k : live) {
-    const ClassSpec &c = ctx->classes[size_t(k)];
-    const size_t s = size_t(grid_for(ctx, c.prec, c.shape, n_tasks, max_m)) *
-                     slot_dwords(c.prec, c.shape, max_m) * 4;
-    b = std::max(b, s);
-  }
+  for (int k : live) b += class_scratch_bytes(ctx, ctx->classes[size_t(k)], n_tasks, max_m);
   return b;
+}
+
+int ensure_class_streams(soap_dp_ctx *ctx, size_t n) {
+  if (!ctx->fork_event &&
+      hipEventCreateWithFlags(&ctx->fork_event, hipEventDisableTiming) != hipSuccess)
+    return hip_fail(ctx, hipGetLastError());
+  while (ctx->class_streams.size() < n) {
+    hipStream_t st = nullptr;
+    hipEvent_t ev = nullptr;
+    if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess)
+      return hip_fail(ctx, hipGetLastError());
+    ctx->class_streams.push_back(st);
+    ctx->join_events.push_back(ev);
+  }
+  return SOAP_DP_OK;
 }
 
 ClassTable class_table(const soap_dp_ctx *ctx) {
@@ -346,19 +371,27 @@ hipError_t enqueue_batched(soap_dp_ctx *ctx, const soap_dp_batch *in, const soap
   b.work_counter = ctx->small + 3 * kMaxClasses;
   hipError_t e = launch_bucketing(p, class_table(ctx), b, stream);
   if (e != hipSuccess) return e;
-  p.scratch = static_cast<uint32_t *>(ctx->scratch);
+  // fork: every class kernel waits for the bucketing only, then they run
+  // concurrently; the caller's stream joins them all
+  if ((e = hipEventRecord(ctx->fork_event, stream)) != hipSuccess) return e;
   p.task_list = ctx->task_list;
+  size_t scratch_off = 0;
   for (size_t li = 0; li < live.size(); ++li) {
     const int k = live[li];
     const ClassSpec &c = ctx->classes[size_t(k)];
+    hipStream_t cs = ctx->class_streams[li];
+    if ((e = hipStreamWaitEvent(cs, ctx->fork_event, 0)) != hipSuccess) return e;
     DpParams q = p;
+    q.scratch = reinterpret_cast<uint32_t *>(static_cast<char *>(ctx->scratch) + scratch_off);
+    scratch_off += class_scratch_bytes(ctx, c, in->n_tasks, in->max_m);
     q.task_off = b.offset + k;
     q.task_count = b.hist + k;
     q.work_counter = b.work_counter + k;
     q.slot_dwords = slot_dwords(c.prec, c.shape, in->max_m);
     q.ok_status = c.prec == 16 ? kTaskOk : kTaskRedone;
-    e = launch_shape(c.prec, c.shape, grids[li], stream, q);
-    if (e != hipSuccess) return e;
+    if ((e = launch_shape(c.prec, c.shape, grids[li], cs, q)) != hipSuccess) return e;
+    if ((e = hipEventRecord(ctx->join_events[li], cs)) != hipSuccess) return e;
+    if ((e = hipStreamWaitEvent(stream, ctx->join_events[li], 0)) != hipSuccess) return e;
   }
   return hipSuccess;
 }
@@ -367,6 +400,8 @@ int align_batched(soap_dp_ctx *ctx, const soap_dp_batch *in, const soap_dp_scori
                   const soap_dp_result *out, hipStream_t stream) {
   const std::vector<int> live = live_classes(ctx, in->max_n, sc);
   int rc = ensure_task_buffers(ctx, in->n_tasks);
+  if (rc) return rc;
+  rc = ensure_class_streams(ctx, live.size());
   if (rc) return rc;
   rc = ensure_scratch(ctx, batched_scratch_bytes(ctx, in->n_tasks, in->max_m, live));
   if (rc) return rc;
@@ -651,6 +686,9 @@ int soap_dp_destroy(soap_dp_ctx *ctx) {
     (void)hipDeviceSynchronize();
     clear_graphs(ctx);
     if (ctx->capture_stream) (void)hipStreamDestroy(ctx->capture_stream);
+    for (auto st : ctx->class_streams) (void)hipStreamDestroy(st);
+    for (auto ev : ctx->join_events) (void)hipEventDestroy(ev);
+    if (ctx->fork_event) (void)hipEventDestroy(ctx->fork_event);
     if (ctx->scratch) (void)hipFree(ctx->scratch);
     if (ctx->small) (void)hipFree(ctx->small);
     if (ctx->task_list) (void)hipFree(ctx->task_list);

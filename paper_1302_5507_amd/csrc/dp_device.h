@@ -46,63 +46,90 @@ __device__ __forceinline__ int32_t wave_max(int32_t v) {
 }
 
 // Walk the decision nibbles of one task back from (end, n) and write its
-// CIGAR.  `nib_at(i, j)` returns the decision nibble of cell (i, j).
+// CIGAR.  `nib_at(i, j)` returns the decision nibble of cell (i, j):
+// bit3 I extended, bit2 D extended, bit1 M not from the diagonal, bit0 M not
+// from D.  One iteration per emitted operation; the state update is
+// select-based so that lanes tracing different tasks stay converged.
 template <class NibFn>
 __device__ void traceback_task(const DpParams &p, int64_t task, int32_t n, int32_t end,
                                NibFn nib_at) {
   uint32_t *row = p.cigar + task * (int64_t)p.cigar_stride;
   int32_t wpos = p.cigar_stride;  // runs are written backward from the row end
-  int32_t cur = -1, run = 0;
+  int32_t cur = 3, run = 0;       // current run (3: none yet)
   int32_t i = end, j = n, state = 0;  // 0 = M, 1 = D, 2 = I
-  int32_t begin = 0;
-  bool overflow = false;
-  auto emit = [&](int32_t op, int32_t len) {
-    if (op == cur) {
-      run += len;
+  bool bad = false;
+  // Every iteration lowers i or j, so the walk ends within n + end steps.
+  // The guard keeps a corrupted decision from reading outside the task.
+  for (int32_t guard = n + end + 1; guard > 0; --guard) {
+    if (state == 0 && (i == 0 || j == 0)) break;
+    if (i < 1 || j < 1) { bad = true; break; }
+    const uint32_t nib = nib_at(i, j);
+    const bool in_m = state == 0;
+    const bool diag = in_m && !(nib & 2u);
+    const bool to_d = in_m ? ((nib & 3u) == 2u) : state == 1;   // M from D, or still in D
+    const int32_t op = diag ? 0 : (to_d ? 2 : 1);              // M = 0, I = 1, D = 2
+    const int32_t next = diag ? 0 : (to_d ? ((nib & 4u) ? 1 : 0) : ((nib & 8u) ? 2 : 0));
+    if (op != cur && run > 0) {
+      if (wpos > 0) row[--wpos] = (uint32_t)run << 4 | (uint32_t)cur;
+      else bad = true;
+    }
+    run = op == cur ? run + 1 : 1;
+    cur = op;
+    i -= op != 1;   // M and D consume a region base
+    j -= op != 2;   // M and I consume a read base
+    state = next;
+  }
+  int32_t begin = i;
+  if (!bad && state == 0 && i == 0 && j > 0) {   // base case M(0, j): j insertions
+    if (cur == 1) {
+      run += j;
     } else {
       if (run > 0) {
         if (wpos > 0) row[--wpos] = (uint32_t)run << 4 | (uint32_t)cur;
-        else overflow = true;
+        else bad = true;
       }
-      cur = op;
-      run = len;
+      cur = 1;
+      run = j;
     }
-  };
-  // Every iteration lowers i or j, so the walk ends within n + end steps.
-  // The guards keep a corrupted decision from reading outside the task.
-  for (int32_t guard = n + end + 1; guard > 0; --guard) {
-    if (state == 0) {
-      if (j == 0) { begin = i; break; }
-      if (i == 0) { emit(1, j); begin = 0; break; }
-    }
-    if (i < 1 || j < 1) { overflow = true; break; }
-    const uint32_t nib = nib_at(i, j);
-    if (state == 0) {
-      if (!(nib & 2u)) {          // diagonal
-        emit(0, 1);
-        --i; --j;
-        continue;
-      }
-      state = (nib & 1u) ? 2 : 1;  // from I, else from D
-    }
-    if (state == 1) {             // region base i against a space
-      emit(2, 1);
-      if (!(nib & 4u)) state = 0;
-      --i;
-    } else {                      // read base j against a space
-      emit(1, 1);
-      if (!(nib & 8u)) state = 0;
-      --j;
-    }
+    begin = 0;
   }
-  emit(-2, 0);  // flush the last run
+  if (run > 0) {
+    if (wpos > 0) row[--wpos] = (uint32_t)run << 4 | (uint32_t)cur;
+    else bad = true;
+  }
   const int32_t cnt = p.cigar_stride - wpos;
   for (int32_t k = 0; k < cnt; ++k) row[k] = row[wpos + k];
-  p.cigar_len[task] = overflow ? 0 : cnt;
-  p.ref_begin[task] = begin;
-  if (overflow) p.status[task] = kTaskInvalidLen;
+  p.cigar_len[task] = bad ? 0 : cnt;
+  p.ref_begin[task] = bad ? 0 : begin;
+  if (bad) p.status[task] = kTaskInvalidLen;
 }
 
+// Per-lane cache of one (lane, column-group) word over four consecutive
+// sweep steps [top - 3, top], held in LDS (`slots` points at this lane's four
+// entries): a diagonal or vertical move of the traceback usually stays inside
+// it, and a refill issues its four loads at once.
+template <class Word>
+struct StepCache {
+  int32_t lq = -1, w = -1, top = -1;
+  // `base` points at step 0 of this (lq, w); consecutive steps are `stride`
+  // Words apart.  Steps below 0 are clamped to 0 (never used).
+  __device__ __forceinline__ Word get(Word *slots, const Word *base, int32_t ts, int32_t lq_,
+                                      int32_t w_, uint32_t stride) {
+    uint32_t d = (uint32_t)(top - ts);
+    if (lq_ != lq || w_ != w || d > 3u) {
+      lq = lq_;
+      w = w_;
+      top = ts;
+      d = 0;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int32_t tk = ts - k > 0 ? ts - k : 0;
+        slots[k] = base[(uint64_t)(uint32_t)tk * stride];
+      }
+    }
+    return slots[d];
+  }
+};
 
 // Resolve the task order of a work item: entry `tix` of the (segment of the)
 // task list, or `tix` itself.

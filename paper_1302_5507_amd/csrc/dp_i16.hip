@@ -66,6 +66,7 @@ __global__ __launch_bounds__(kWave) void dp_i16_kernel(DpParams p) {
   __shared__ int64_t s_task[TPW];
   __shared__ int32_t s_n[TPW], s_pad[TPW], s_end[TPW], s_score[TPW];
   __shared__ uint8_t s_st[TPW];
+  __shared__ uint2 s_tbc[TPW][4];   // traceback step caches
 
   uint32_t *const slot = p.scratch + (uint64_t)blockIdx.x * p.slot_dwords;
   const int64_t n_tasks = p.task_count ? (int64_t)*p.task_count : p.n_tasks;
@@ -266,12 +267,15 @@ __global__ __launch_bounds__(kWave) void dp_i16_kernel(DpParams p) {
           p.status[tk] = p.ok_status;
           const uint2 *base = reinterpret_cast<const uint2 *>(slot) + gq * L;
           const uint32_t shA = 8u * (2 + h), shD = 8u * h;
+          StepCache<uint2> cache;
           auto nib_at = [&](int32_t i, int32_t j) -> uint32_t {
-            const int32_t jp = j + tpad - 1;
-            const int32_t lq = jp / K;
-            const int32_t c = jp - lq * K;
-            const int32_t ts = i - 1 + lq;
-            const uint2 v = base[((uint64_t)ts * W + (uint32_t)(c >> 3)) * kWave + lq];
+            const uint32_t jp = (uint32_t)(j + tpad - 1);
+            const uint32_t lq = jp / K;
+            const uint32_t c = jp - lq * K;
+            const int32_t ts = i - 1 + (int32_t)lq;
+            const uint32_t w = c >> 3;
+            const uint2 v = cache.get(s_tbc[lane], base + w * kWave + lq, ts, (int32_t)lq, (int32_t)w,
+                                      (uint32_t)(W * kWave));
             const uint32_t b = (uint32_t)(c & 7);
             return ((v.x >> (shA + b)) & 1u) << 3 | ((v.x >> (shD + b)) & 1u) << 2 |
                    ((v.y >> (shA + b)) & 1u) << 1 | ((v.y >> (shD + b)) & 1u);

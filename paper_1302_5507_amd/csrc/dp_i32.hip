@@ -42,6 +42,7 @@ __global__ __launch_bounds__(kWave) void dp_i32_kernel(DpParams p) {
   __shared__ int64_t s_task[G];
   __shared__ int32_t s_n[G], s_pad[G], s_end[G], s_score[G];
   __shared__ uint8_t s_st[G];
+  __shared__ uint32_t s_tbc[G][4];   // traceback step caches
 
   uint32_t *const slot = p.scratch + (uint64_t)blockIdx.x * p.slot_dwords;
   const int64_t n_tasks = p.task_count ? (int64_t)*p.task_count : p.n_tasks;
@@ -186,12 +187,15 @@ __global__ __launch_bounds__(kWave) void dp_i32_kernel(DpParams p) {
           p.ref_end[tk] = tend;
           p.status[tk] = p.ok_status;
           const uint32_t *base = slot + lane * L;
+          StepCache<uint32_t> cache;
           auto nib_at = [&](int32_t i, int32_t j) -> uint32_t {
-            const int32_t jp = j + tpad - 1;
-            const int32_t lq = jp / K;
-            const int32_t c = jp - lq * K;
-            const int32_t ts = i - 1 + lq;
-            const uint32_t wd = base[((uint64_t)ts * W + (uint32_t)(c >> 3)) * kWave + lq];
+            const uint32_t jp = (uint32_t)(j + tpad - 1);
+            const uint32_t lq = jp / K;
+            const uint32_t c = jp - lq * K;
+            const int32_t ts = i - 1 + (int32_t)lq;
+            const uint32_t w = c >> 3;
+            const uint32_t wd = cache.get(s_tbc[lane], base + w * kWave + lq, ts, (int32_t)lq, (int32_t)w,
+                                          (uint32_t)(W * kWave));
             return (wd >> (4 * (7 - (c & 7)))) & 15u;
           };
           traceback_task(p, tk, tn, tend, nib_at);
