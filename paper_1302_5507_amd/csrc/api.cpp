@@ -248,7 +248,35 @@ DpParams make_params(const soap_dp_batch *in, const soap_dp_scoring *sc, const s
   p.cigar_len = out->cigar_len;
   p.status = out->status;
   p.ok_status = kTaskOk;
+  p.defer = 1;
   return p;
+}
+
+// Work items of one launch and the tasks each serves.
+int64_t tasks_per_item(int prec, Shape s) { return (prec == 16 ? 2 : 1) * kWave / s.lanes; }
+
+// Grid, traceback deferral and scratch of one kernel launch.
+struct LaunchPlan {
+  int grid = 0;
+  int defer = 1;
+  uint64_t slot_dwords = 0;
+  size_t bytes() const { return (size_t(grid) * size_t(defer) * slot_dwords * 4 + 255) & ~size_t(255); }
+};
+
+// Deferral: as many slots per workgroup as one traceback pass has lanes for,
+// but no more than the work items a workgroup can expect, and within
+// `budget` bytes of scratch.
+LaunchPlan plan_launch(const soap_dp_ctx *ctx, int prec, Shape s, int64_t n_tasks, int32_t max_m,
+                       size_t budget) {
+  LaunchPlan q;
+  q.grid = grid_for(ctx, prec, s, n_tasks, max_m);
+  q.slot_dwords = slot_dwords(prec, s, max_m);
+  const int64_t per = tasks_per_item(prec, s);
+  const int64_t items = (n_tasks + per - 1) / per;
+  const int64_t per_block = (items + q.grid - 1) / q.grid;
+  q.defer = int(std::max<int64_t>(1, std::min<int64_t>(kWave / per, per_block)));
+  while (q.defer > 1 && q.bytes() > budget) --q.defer;
+  return q;
 }
 
 hipError_t launch_shape(int prec, Shape s, int grid, hipStream_t stream, const DpParams &p) {
@@ -260,21 +288,21 @@ hipError_t launch_shape(int prec, Shape s, int grid, hipStream_t stream, const D
 size_t plain_scratch_bytes(const soap_dp_ctx *ctx, int64_t n_tasks, int32_t max_n, int32_t max_m) {
   const Shape s = plain_shape(max_n, max_m);
   if (s.lanes == 0) return 0;
-  return size_t(grid_for(ctx, 32, s, n_tasks, max_m)) * slot_dwords(32, s, max_m) * 4;
+  return plan_launch(ctx, 32, s, n_tasks, max_m, kScratchCap).bytes();
 }
 
 int align_plain(soap_dp_ctx *ctx, const soap_dp_batch *in, const soap_dp_scoring *sc,
                 const soap_dp_result *out, hipStream_t stream) {
   const Shape s = plain_shape(in->max_n, in->max_m);
   if (s.lanes == 0) return SOAP_DP_EINVAL;
-  const int grid = grid_for(ctx, 32, s, in->n_tasks, in->max_m);
-  const uint64_t slot = slot_dwords(32, s, in->max_m);
-  const int rc = ensure_scratch(ctx, size_t(grid) * slot * 4);
+  const LaunchPlan q = plan_launch(ctx, 32, s, in->n_tasks, in->max_m, kScratchCap);
+  const int rc = ensure_scratch(ctx, q.bytes());
   if (rc) return rc;
   DpParams p = make_params(in, sc, out);
   p.scratch = static_cast<uint32_t *>(ctx->scratch);
-  p.slot_dwords = slot;
-  const hipError_t e = launch_dp_i32(s, grid, stream, p);
+  p.slot_dwords = q.slot_dwords;
+  p.defer = q.defer;
+  const hipError_t e = launch_dp_i32(s, q.grid, stream, p);
   if (e != hipSuccess) return hip_fail(ctx, e);
   return SOAP_DP_OK;
 }
@@ -313,19 +341,35 @@ std::vector<int> live_classes(const soap_dp_ctx *ctx, int32_t max_n, const soap_
   return live;
 }
 
-// Scratch of one class's launch, rounded up to 256 bytes.
-size_t class_scratch_bytes(const soap_dp_ctx *ctx, const ClassSpec &c, int64_t n_tasks,
-                           int32_t max_m) {
-  const size_t b = size_t(grid_for(ctx, c.prec, c.shape, n_tasks, max_m)) *
-                   slot_dwords(c.prec, c.shape, max_m) * 4;
-  return (b + 255) & ~size_t(255);
+// Launch plans of the live classes, which run concurrently, each in its own
+// scratch region.  The host does not know how the tasks split over the
+// classes, so each class is planned for the whole batch; deferral is then
+// trimmed, largest region first, until the regions fit the scratch budget.
+std::vector<LaunchPlan> batched_plans(const soap_dp_ctx *ctx, int64_t n_tasks, int32_t max_m,
+                                      const std::vector<int> &live) {
+  std::vector<LaunchPlan> plans;
+  size_t total = 0;
+  for (int k : live) {
+    const ClassSpec &c = ctx->classes[size_t(k)];
+    plans.push_back(plan_launch(ctx, c.prec, c.shape, n_tasks, max_m, kScratchCap));
+    total += plans.back().bytes();
+  }
+  while (total > kScratchCap) {
+    size_t worst = 0;
+    for (size_t i = 1; i < plans.size(); ++i)
+      if (plans[i].bytes() > plans[worst].bytes()) worst = i;
+    if (plans.empty() || plans[worst].defer == 1) break;
+    total -= plans[worst].bytes();
+    --plans[worst].defer;
+    total += plans[worst].bytes();
+  }
+  return plans;
 }
 
-// The live classes run concurrently, each in its own scratch region.
 size_t batched_scratch_bytes(const soap_dp_ctx *ctx, int64_t n_tasks, int32_t max_m,
                              const std::vector<int> &live) {
   size_t b = 0;
-  for (int k : live) b += class_scratch_bytes(ctx, ctx->classes[size_t(k)], n_tasks, max_m);
+  for (const LaunchPlan &q : batched_plans(ctx, n_tasks, max_m, live)) b += q.bytes();
   return b;
 }
 
@@ -357,10 +401,10 @@ ClassTable class_table(const soap_dp_ctx *ctx) {
 }
 
 // Enqueue the whole batched sequence on `stream` (also used under capture,
-// so the grids are computed beforehand: no runtime queries in between).
+// so the launch plans are computed beforehand: no runtime queries in between).
 hipError_t enqueue_batched(soap_dp_ctx *ctx, const soap_dp_batch *in, const soap_dp_scoring *sc,
                            const soap_dp_result *out, const std::vector<int> &live,
-                           const std::vector<int> &grids, hipStream_t stream) {
+                           const std::vector<LaunchPlan> &plans, hipStream_t stream) {
   DpParams p = make_params(in, sc, out);
   BucketBuffers b{};
   b.task_class = ctx->task_class;
@@ -383,13 +427,14 @@ hipError_t enqueue_batched(soap_dp_ctx *ctx, const soap_dp_batch *in, const soap
     if ((e = hipStreamWaitEvent(cs, ctx->fork_event, 0)) != hipSuccess) return e;
     DpParams q = p;
     q.scratch = reinterpret_cast<uint32_t *>(static_cast<char *>(ctx->scratch) + scratch_off);
-    scratch_off += class_scratch_bytes(ctx, c, in->n_tasks, in->max_m);
+    scratch_off += plans[li].bytes();
     q.task_off = b.offset + k;
     q.task_count = b.hist + k;
     q.work_counter = b.work_counter + k;
-    q.slot_dwords = slot_dwords(c.prec, c.shape, in->max_m);
+    q.slot_dwords = plans[li].slot_dwords;
+    q.defer = plans[li].defer;
     q.ok_status = c.prec == 16 ? kTaskOk : kTaskRedone;
-    if ((e = launch_shape(c.prec, c.shape, grids[li], cs, q)) != hipSuccess) return e;
+    if ((e = launch_shape(c.prec, c.shape, plans[li].grid, cs, q)) != hipSuccess) return e;
     if ((e = hipEventRecord(ctx->join_events[li], cs)) != hipSuccess) return e;
     if ((e = hipStreamWaitEvent(stream, ctx->join_events[li], 0)) != hipSuccess) return e;
   }
@@ -403,15 +448,13 @@ int align_batched(soap_dp_ctx *ctx, const soap_dp_batch *in, const soap_dp_scori
   if (rc) return rc;
   rc = ensure_class_streams(ctx, live.size());
   if (rc) return rc;
-  rc = ensure_scratch(ctx, batched_scratch_bytes(ctx, in->n_tasks, in->max_m, live));
+  const std::vector<LaunchPlan> plans = batched_plans(ctx, in->n_tasks, in->max_m, live);
+  size_t need = 0;
+  for (const LaunchPlan &q : plans) need += q.bytes();
+  rc = ensure_scratch(ctx, need);
   if (rc) return rc;
-  std::vector<int> grids;
-  for (int k : live) {
-    const ClassSpec &c = ctx->classes[size_t(k)];
-    grids.push_back(grid_for(ctx, c.prec, c.shape, in->n_tasks, in->max_m));
-  }
   if (!ctx->use_graphs) {
-    const hipError_t e = enqueue_batched(ctx, in, sc, out, live, grids, stream);
+    const hipError_t e = enqueue_batched(ctx, in, sc, out, live, plans, stream);
     return e == hipSuccess ? SOAP_DP_OK : hip_fail(ctx, e);
   }
   GraphKey key;
@@ -429,7 +472,7 @@ int align_batched(soap_dp_ctx *ctx, const soap_dp_batch *in, const soap_dp_scori
       return hip_fail(ctx, hipGetLastError());
     hipError_t e = hipStreamBeginCapture(ctx->capture_stream, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return hip_fail(ctx, e);
-    const hipError_t le = enqueue_batched(ctx, in, sc, out, live, grids, ctx->capture_stream);
+    const hipError_t le = enqueue_batched(ctx, in, sc, out, live, plans, ctx->capture_stream);
     hipGraph_t graph = nullptr;
     e = hipStreamEndCapture(ctx->capture_stream, &graph);
     if (le != hipSuccess || e != hipSuccess) {
@@ -586,9 +629,11 @@ double time_shape(soap_dp_ctx *ctx, int prec, Shape s, const TuneData &d, int32_
   p.cigar_len = d.i32 + 3 * d.tasks; p.cigar = d.cigar; p.cigar_stride = 2 * n;
   p.status = d.status;
   p.ok_status = kTaskOk;
-  const int grid = grid_for(ctx, prec, s, d.tasks, m);
-  p.slot_dwords = slot_dwords(prec, s, m);
-  if (ensure_scratch(ctx, size_t(grid) * p.slot_dwords * 4)) return 0;
+  const LaunchPlan q = plan_launch(ctx, prec, s, d.tasks, m, kScratchCap);
+  const int grid = q.grid;
+  p.slot_dwords = q.slot_dwords;
+  p.defer = q.defer;
+  if (ensure_scratch(ctx, q.bytes())) return 0;
   p.scratch = static_cast<uint32_t *>(ctx->scratch);
   p.work_counter = ctx->small + 3 * kMaxClasses;
   hipEvent_t a, b;

@@ -63,12 +63,17 @@ __global__ __launch_bounds__(kWave) void dp_i16_kernel(DpParams p) {
   const bool first = lg == 0;
   const bool last = lg == L - 1;
 
-  __shared__ int64_t s_task[TPW];
-  __shared__ int32_t s_n[TPW], s_pad[TPW], s_end[TPW], s_score[TPW];
-  __shared__ uint8_t s_st[TPW];
-  __shared__ uint2 s_tbc[TPW][4];   // traceback step caches
+  // bookkeeping of the deferred work items, entry r * TPW + h * G + g
+  __shared__ int64_t s_task[kWave];
+  __shared__ int32_t s_n[kWave], s_pad[kWave], s_end[kWave], s_score[kWave];
+  __shared__ uint8_t s_st[kWave];
+  __shared__ uint2 s_tbc[kWave][4];   // traceback step caches
 
-  uint32_t *const slot = p.scratch + (uint64_t)blockIdx.x * p.slot_dwords;
+  // `defer` work items are swept into consecutive slots before one
+  // traceback pass serves all their tasks, one lane per task
+  const int32_t defer = min(max(p.defer, 1), kWave / TPW);
+  uint32_t *const slots = p.scratch + (uint64_t)blockIdx.x * p.slot_dwords * (uint64_t)defer;
+  int32_t r = 0;   // slot of the current work item
   const int64_t n_tasks = p.task_count ? (int64_t)*p.task_count : p.n_tasks;
   const int32_t *const list = (p.task_list && p.task_off) ? p.task_list + *p.task_off : p.task_list;
   const int64_t n_items = (n_tasks + TPW - 1) / TPW;
@@ -118,7 +123,7 @@ __global__ __launch_bounds__(kWave) void dp_i16_kernel(DpParams p) {
     if (first) {
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
-        const int u = h * G + g;
+        const int u = r * TPW + h * G + g;
         s_task[u] = task[h]; s_n[u] = n[h]; s_pad[u] = pad[h]; s_st[u] = st[h];
       }
     }
@@ -169,7 +174,7 @@ __global__ __launch_bounds__(kWave) void dp_i16_kernel(DpParams p) {
 #pragma unroll
     for (int w = 0; w < W; ++w) { accA[w] = 0; accB[w] = 0; }
 
-    uint2 *sp = reinterpret_cast<uint2 *>(slot);
+    uint2 *sp = reinterpret_cast<uint2 *>(slots + (uint64_t)r * p.slot_dwords);
     for (int32_t t = 0; t < steps; ++t) {
       if ((t & 15) == 0) {
         twa = __builtin_amdgcn_alignbit(a1, a0, wsh0);
@@ -242,17 +247,20 @@ __global__ __launch_bounds__(kWave) void dp_i16_kernel(DpParams p) {
 
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
-      const int u = h * G + g;
+      const int u = r * TPW + h * G + g;
       if (last) {
         const int32_t b = h ? best1 : best0;
         s_end[u] = 0xffff - (b & 0xffff);
         s_score[u] = b >> 16;   // M^(end, n); the traceback lane adds n * S_MI
       }
     }
-    __syncthreads();
+    ++r;
+    item = p.work_counter ? next_item(p.work_counter, lane) : item + gridDim.x;
+    if (r < defer && item < n_items) continue;
 
-    // ---------------- traceback, one lane per task
-    if (lane < TPW) {
+    // ---------------- traceback of the deferred items, one lane per task
+    __syncthreads();
+    if (lane < r * TPW) {
       const int64_t tk = s_task[lane];
       if (tk >= 0) {
         const uint8_t tst = s_st[lane];
@@ -260,12 +268,14 @@ __global__ __launch_bounds__(kWave) void dp_i16_kernel(DpParams p) {
           p.score[tk] = 0; p.ref_begin[tk] = 0; p.ref_end[tk] = 0; p.cigar_len[tk] = 0;
           p.status[tk] = tst;
         } else {
-          const int h = lane / G, gq = lane % G;
+          const int rs = lane / TPW, ui = lane % TPW;
+          const int h = ui / G, gq = ui % G;
           const int32_t tn = s_n[lane], tpad = s_pad[lane], tend = s_end[lane];
           p.score[tk] = s_score[lane] + tn * mi;
           p.ref_end[tk] = tend;
           p.status[tk] = p.ok_status;
-          const uint2 *base = reinterpret_cast<const uint2 *>(slot) + gq * L;
+          const uint2 *base =
+              reinterpret_cast<const uint2 *>(slots + (uint64_t)rs * p.slot_dwords) + gq * L;
           const uint32_t shA = 8u * (2 + h), shD = 8u * h;
           StepCache<uint2> cache;
           auto nib_at = [&](int32_t i, int32_t j) -> uint32_t {
@@ -285,8 +295,7 @@ __global__ __launch_bounds__(kWave) void dp_i16_kernel(DpParams p) {
       }
     }
     __syncthreads();
-
-    item = p.work_counter ? next_item(p.work_counter, lane) : item + gridDim.x;
+    r = 0;
   }
 }
 

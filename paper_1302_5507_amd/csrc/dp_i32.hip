@@ -22,8 +22,10 @@
 //    come from D.  They are packed 8 cells to a dword (first cell in the top
 //    nibble) and written step-major, so every store of the wavefront is 256
 //    contiguous bytes.
-//  * After the sweep one lane per task walks the decisions back from
-//    (ref_end, n) and writes the run-length CIGAR.
+//  * A wavefront sweeps up to 64/G work items into consecutive scratch slots,
+//    then one lane per task of all of them walks the decisions back from
+//    (ref_end, n) and writes the run-length CIGAR, so the walk, which is
+//    bound by dependent loads, keeps every lane busy.
 #include "dp_device.h"
 
 namespace soapdp {
@@ -39,12 +41,17 @@ __global__ __launch_bounds__(kWave) void dp_i32_kernel(DpParams p) {
   const bool first = lg == 0;
   const bool last = lg == L - 1;
 
-  __shared__ int64_t s_task[G];
-  __shared__ int32_t s_n[G], s_pad[G], s_end[G], s_score[G];
-  __shared__ uint8_t s_st[G];
-  __shared__ uint32_t s_tbc[G][4];   // traceback step caches
+  // bookkeeping of the deferred work items, entry r * G + g
+  __shared__ int64_t s_task[kWave];
+  __shared__ int32_t s_n[kWave], s_pad[kWave], s_end[kWave], s_score[kWave];
+  __shared__ uint8_t s_st[kWave];
+  __shared__ uint32_t s_tbc[kWave][4];   // traceback step caches
 
-  uint32_t *const slot = p.scratch + (uint64_t)blockIdx.x * p.slot_dwords;
+  // `defer` work items are swept into consecutive slots before one
+  // traceback pass serves all their tasks, one lane per task
+  const int32_t defer = min(max(p.defer, 1), kWave / G);
+  uint32_t *const slots = p.scratch + (uint64_t)blockIdx.x * p.slot_dwords * (uint64_t)defer;
+  int32_t r = 0;   // slot of the current work item
   const int64_t n_tasks = p.task_count ? (int64_t)*p.task_count : p.n_tasks;
   const int32_t *const list = (p.task_list && p.task_off) ? p.task_list + *p.task_off : p.task_list;
   const int64_t n_items = (n_tasks + G - 1) / G;
@@ -74,7 +81,8 @@ __global__ __launch_bounds__(kWave) void dp_i32_kernel(DpParams p) {
     // uniform trip count: keeps the step loop under scalar control
     const int32_t steps = __builtin_amdgcn_readfirstlane(wave_max(mg)) + L - 1;
     // bookkeeping for the traceback goes to LDS now, out of the sweep's registers
-    if (first) { s_task[g] = task; s_n[g] = n; s_pad[g] = pad; s_st[g] = st; }
+    const int u0 = r * G + g;
+    if (first) { s_task[u0] = task; s_n[u0] = n; s_pad[u0] = pad; s_st[u0] = st; }
 
     StripWords rw{0, 0, 0, 0};
     if (valid) rw.load(p.read_codes, rwo, n, lg * K - pad);
@@ -113,7 +121,7 @@ __global__ __launch_bounds__(kWave) void dp_i32_kernel(DpParams p) {
 #pragma unroll
     for (int w = 0; w < W; ++w) acc[w] = 0;
 
-    uint32_t *sp = slot;
+    uint32_t *sp = slots + (uint64_t)r * p.slot_dwords;
     for (int32_t t = 0; t < steps; ++t) {
       if ((t & 15) == 0) {
         tw = __builtin_amdgcn_alignbit(tn1, tn0, wsh);
@@ -170,11 +178,14 @@ __global__ __launch_bounds__(kWave) void dp_i32_kernel(DpParams p) {
       sp += W * kWave;
     }
 
-    if (last) { s_end[g] = endi; s_score[g] = best; }
-    __syncthreads();
+    if (last) { s_end[u0] = endi; s_score[u0] = best; }
+    ++r;
+    item = p.work_counter ? next_item(p.work_counter, lane) : item + gridDim.x;
+    if (r < defer && item < n_items) continue;
 
-    // ---------------- traceback, one lane per task
-    if (lane < G) {
+    // ---------------- traceback of the deferred items, one lane per task
+    __syncthreads();
+    if (lane < r * G) {
       const int64_t tk = s_task[lane];
       if (tk >= 0) {
         const uint8_t tst = s_st[lane];
@@ -186,7 +197,8 @@ __global__ __launch_bounds__(kWave) void dp_i32_kernel(DpParams p) {
           p.score[tk] = s_score[lane];
           p.ref_end[tk] = tend;
           p.status[tk] = p.ok_status;
-          const uint32_t *base = slot + lane * L;
+          const int rs = lane / G, gq = lane % G;
+          const uint32_t *base = slots + (uint64_t)rs * p.slot_dwords + gq * L;
           StepCache<uint32_t> cache;
           auto nib_at = [&](int32_t i, int32_t j) -> uint32_t {
             const uint32_t jp = (uint32_t)(j + tpad - 1);
@@ -203,8 +215,7 @@ __global__ __launch_bounds__(kWave) void dp_i32_kernel(DpParams p) {
       }
     }
     __syncthreads();
-
-    item = p.work_counter ? next_item(p.work_counter, lane) : item + gridDim.x;
+    r = 0;
   }
 }
 

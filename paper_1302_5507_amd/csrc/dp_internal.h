@@ -36,9 +36,12 @@ struct DpParams {
   int32_t cigar_stride;
   int32_t *cigar_len;
   uint8_t *status;
-  // Decision-bit scratch: one slot of `slot_dwords` per workgroup of the grid.
+  // Decision-bit scratch: `defer` slots of `slot_dwords` per workgroup of the
+  // grid.  A workgroup sweeps up to `defer` work items (one per slot) before
+  // it traces them back together; 1 <= defer <= 64 / tasks per work item.
   uint32_t *scratch;
   uint64_t slot_dwords;
+  int32_t defer;
   // Optional task order (nullptr: identity) and its length; work items are
   // groups of (tasks per wave) consecutive entries of that order.
   const int32_t *task_list;
