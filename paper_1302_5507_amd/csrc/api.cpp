@@ -311,9 +311,11 @@ int align_plain(soap_dp_ctx *ctx, const soap_dp_batch *in, const soap_dp_scoring
 
 // Classes a batch with these bounds can populate: a class receives reads
 // longer than the previous class of its precision, so classes starting at or
-// above max_n stay empty; int32 classes are needed only if some read length
-// up to max_n falls outside the int16 range of its int16 class.
-std::vector<int> live_classes(const soap_dp_ctx *ctx, int32_t max_n, const soap_dp_scoring *sc) {
+// above max_n stay empty; int32 classes are needed only if some task (read
+// up to max_n, window up to max_m) falls outside the int16 range of its
+// int16 class.
+std::vector<int> live_classes(const soap_dp_ctx *ctx, int32_t max_n, int32_t max_m,
+                              const soap_dp_scoring *sc) {
   std::vector<int> live;
   bool need32 = false;
   int prev16 = 0;
@@ -323,7 +325,7 @@ std::vector<int> live_classes(const soap_dp_ctx *ctx, int32_t max_n, const soap_
     if (prev16 < max_n) {
       live.push_back(int(k));
       const int32_t n_hi = std::min(c.cap, max_n);
-      if (!int16_fits(n_hi, c.shape.lanes * c.shape.cells, sc->match, sc->mismatch,
+      if (!int16_fits(n_hi, max_m, c.shape.lanes * c.shape.cells, sc->match, sc->mismatch,
                       sc->gap_open, sc->gap_extend))
         need32 = true;
     }
@@ -443,7 +445,7 @@ hipError_t enqueue_batched(soap_dp_ctx *ctx, const soap_dp_batch *in, const soap
 
 int align_batched(soap_dp_ctx *ctx, const soap_dp_batch *in, const soap_dp_scoring *sc,
                   const soap_dp_result *out, hipStream_t stream) {
-  const std::vector<int> live = live_classes(ctx, in->max_n, sc);
+  const std::vector<int> live = live_classes(ctx, in->max_n, in->max_m, sc);
   int rc = ensure_task_buffers(ctx, in->n_tasks);
   if (rc) return rc;
   rc = ensure_class_streams(ctx, live.size());
@@ -676,7 +678,7 @@ int autotune(soap_dp_ctx *ctx, std::vector<double> &gcups) {
       const Shape s = all[q];
       const int cols = s.lanes * s.cells;
       if (cols < c.cap || cols > c.cap + std::max(c.cap / 6, 8)) continue;
-      if (c.prec == 16 && !int16_fits(n, cols, 1, -3, -5, -2)) continue;
+      if (c.prec == 16 && !int16_fits(n, n + 160, cols, 1, -3, -5, -2)) continue;
       const double g = time_shape(ctx, c.prec, s, d, n, st);
       if (g > best) { best = g; best_s = s; }
     }

@@ -14,13 +14,13 @@ namespace {
 
 constexpr int kBlock = 256;
 
-__device__ int class_of(const ClassTable &ct, int32_t n, int32_t ma, int32_t mi, int32_t go,
-                        int32_t ge) {
+__device__ int class_of(const ClassTable &ct, int32_t n, int32_t m, int32_t ma, int32_t mi,
+                        int32_t go, int32_t ge) {
   // int16 classes first (ascending capacity), then int32 classes
   for (int k = 0; k < ct.count; ++k) {
     if (ct.prec[k] != 16 || ct.cap[k] < n) continue;
-    if (int16_fits(n, ct.cols[k], ma, mi, go, ge)) return k;
-    break;   // a wider int16 shape only widens the range; go to int32
+    if (int16_fits(n, m, ct.cols[k], ma, mi, go, ge)) return k;
+    break;   // a wider int16 shape only narrows the range; go to int32
   }
   for (int k = 0; k < ct.count; ++k)
     if (ct.prec[k] == 32 && ct.cap[k] >= n) return k;
@@ -49,7 +49,7 @@ __global__ __launch_bounds__(kBlock) void classify_kernel(DpParams p, ClassTable
     else if (rwo + (uint64_t)((n + 15) >> 4) > p.read_words || rbo + (uint64_t)m > p.ref_words * 16)
       st = kTaskInvalidOffset;
     else {
-      k = class_of(ct, n, p.ma, p.mi, p.go, p.ge);
+      k = class_of(ct, n, m, p.ma, p.mi, p.go, p.ge);
       if (k < 0) st = kTaskInvalidLen;
     }
     if (st != kTaskOk) {

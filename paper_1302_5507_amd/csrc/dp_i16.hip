@@ -4,19 +4,18 @@
 // different tasks that share the lane geometry, so each packed VALU
 // instruction advances two cells.
 //
-// Differences from the int32 kernel, all exact:
-//  * Values are kept in a column-offset form  M^(i,j) = M(i,j) - j*S_MI
-//    (likewise I and D).  The diagonal step then adds delta - S_MI, which is
-//    S_MA - S_MI on a match and 0 on a mismatch, both small non-negative
-//    numbers read from an 8-byte table with one v_perm_b32 indexed by
-//    (read code XOR window base); the I recurrence adds S_GO - S_MI and
-//    S_GE - S_MI; the D recurrence is unchanged.  Columns left of the read
-//    (virtual, true value 0) index the table's upper half, which holds -S_MI.
+// Same offset form as the int32 kernel, X^(i,j) = X(i,j) - (i+j)*S_GE, so
+// gap extension adds nothing.  Differences from the int32 kernel, all exact:
+//  * The diagonal adds delta - 2 S_GE: S_MA - 2 S_GE on a match and
+//    S_MI - 2 S_GE on a mismatch, small non-negative numbers read from an
+//    8-byte table with one v_perm_b32 indexed by (read code XOR window base).
+//    Columns left of the read (virtual, true value 0) index the table's upper
+//    half, which holds -2 S_GE.
 //  * Adds and subtracts saturate (v_pk_*_i16 clamp).  A task runs here only
-//    if every maximum, widened by the largest constant added, stays well
-//    inside int16 (int16_fits); clamped candidates then always lose, and
-//    -32768 serves as minus infinity.  Other tasks are left to the int32
-//    kernel.
+//    if every value, widened by the largest constant added, stays well inside
+//    int16 and the table entries fit a byte (int16_fits); clamped candidates
+//    then always lose, and -32768 serves as minus infinity.  Other tasks are
+//    left to the int32 kernel.
 //  * Decision bits: the sign of each packed difference is replicated into a
 //    byte with v_perm_b32 (selectors 8..11) and merged with v_and_or_b32 into
 //    bit c%8 of that byte.  Per 8 columns a lane writes two dwords:
@@ -79,12 +78,13 @@ __global__ __launch_bounds__(kWave) void dp_i16_kernel(DpParams p) {
   const int64_t n_items = (n_tasks + TPW - 1) / TPW;
 
   const int32_t ma = p.ma, mi = p.mi, go = p.go, ge = p.ge;
-  const uint32_t c_goi = pack16(go - mi, go - mi);   // I open, column-offset form
-  const uint32_t c_gei = pack16(ge - mi, ge - mi);   // I extend
-  const uint32_t c_god = pack16(go, go);             // D open
-  const uint32_t c_ged = pack16(ge, ge);             // D extend
-  const uint32_t tab_lo = (uint32_t)(ma - mi) & 0xffu;          // x = 0 match, 1..3 mismatch
-  const uint32_t tab_hi = ((uint32_t)(-mi) & 0xffu) * 0x01010101u;  // x = 4..7 virtual
+  const uint32_t c_go = pack16(go - ge, go - ge);    // gap open, offset form
+  const uint32_t c_ge = pack16(ge, ge);
+  const uint32_t c_nge = pack16(-ge, -ge);
+  // x = 0 match, 1..3 mismatch, 4..7 virtual
+  const uint32_t tab_lo = ((uint32_t)(ma - 2 * ge) & 0xffu) |
+                          ((uint32_t)(mi - 2 * ge) & 0xffu) * 0x01010100u;
+  const uint32_t tab_hi = ((uint32_t)(-2 * ge) & 0xffu) * 0x01010101u;
 
   int64_t item = blockIdx.x;
   while (item < n_items) {
@@ -108,7 +108,7 @@ __global__ __launch_bounds__(kWave) void dp_i16_kernel(DpParams p) {
         else if (rwo[h] + (uint64_t)((n[h] + 15) >> 4) > p.read_words ||
                  rbo[h] + (uint64_t)m[h] > p.ref_words * 16)
           st[h] = kTaskInvalidOffset;
-        else if (!int16_fits(n[h], L * K, ma, mi, go, ge))
+        else if (!int16_fits(n[h], m[h], L * K, ma, mi, go, ge))
           task[h] = -1;   // outside the int16 range: the int32 kernel owns it
       }
       const bool valid = task[h] >= 0 && st[h] == kTaskOk;
@@ -144,8 +144,8 @@ __global__ __launch_bounds__(kWave) void dp_i16_kernel(DpParams p) {
         const int32_t q = lg * K + c - pad[h];   // 0-based read index of this column
         const bool real = mg[h] > 0 && q >= 0;
         code[h] = real ? rw[h].code(q) : 4u;     // virtual: table entries 4..7
-        // M^(0, j) with j = q + 1: S_GO + (j-1) S_GE - j S_MI, or -j S_MI left of the read
-        hv[h] = real ? go + q * ge - (q + 1) * mi : -(q + 1) * mi;
+        // M^(0, j), j = q + 1: S_GO + (j-1) S_GE - j S_GE, or 0 - j S_GE left of the read
+        hv[h] = real ? go - ge : -(q + 1) * ge;
       }
       Rc[c] = (code[0] | 0x0c00u) | ((code[1] | 0x0c00u) << 16);
       H[c] = pack16(hv[0], hv[1]);
@@ -154,8 +154,10 @@ __global__ __launch_bounds__(kWave) void dp_i16_kernel(DpParams p) {
       asm volatile("" : "+v"(Rc[c]), "+v"(H[c]));
       __builtin_amdgcn_sched_barrier(0);
     }
-    // left boundary M^(i, -pad) = pad * S_MI (true value 0)
-    const uint32_t bnd = pack16(pad[0] * mi, pad[1] * mi);
+    // left boundary M^(i, -pad) = -(i - pad) S_GE (true value 0): row 0 is the
+    // first lane's first diagonal, row 1 its first left neighbour
+    uint32_t bnd = pack16((pad[0] - 1) * ge, (pad[1] - 1) * ge);
+    uint32_t rge = pack16((1 - lg) * ge, (1 - lg) * ge);   // i * S_GE of this lane's row
 
     // window bases, 16 at a time per task, realigned from the base offset
     const uint64_t wlim = p.ref_words - 1;
@@ -168,7 +170,7 @@ __global__ __launch_bounds__(kWave) void dp_i16_kernel(DpParams p) {
     uint32_t hl_out = H[K - 1];
     uint32_t el_out = kNeg16x2;
     uint32_t t_out = 0;
-    uint32_t hl_prev = bnd;
+    uint32_t hl_prev = pack16(pad[0] * ge, pad[1] * ge);
     int32_t best0 = INT32_MIN, best1 = INT32_MIN;
     uint32_t accA[W], accB[W];
 #pragma unroll
@@ -200,14 +202,15 @@ __global__ __launch_bounds__(kWave) void dp_i16_kernel(DpParams p) {
         uint32_t diag = add16(hd, __builtin_amdgcn_perm(tab_hi, tab_lo, Rc[0] ^ T));
 #pragma unroll
         for (int c = 0; c < K; ++c) {
-          const uint32_t ad = add16(H[c], c_god);
-          const uint32_t fe = add16(F[c], c_ged);
+          const uint32_t ad = add16(H[c], c_go);
           uint32_t diag_next = 0;
           if (c + 1 < K) diag_next = add16(H[c], __builtin_amdgcn_perm(tab_hi, tab_lo, Rc[c + 1] ^ T));
-          const uint32_t ai = add16(hl, c_goi);
-          el = max16(ai, add16(el, c_gei));
-          const uint32_t f = max16(ad, fe);
+          const uint32_t ai = add16(hl, c_go);
+          el = max16(ai, el);
+          const uint32_t f = max16(ad, F[c]);
           const uint32_t hv = max16(max16(diag, el), f);
+          // differences against the maxima, so the old I and D die at the max
+          // and the new values take their registers
           const uint32_t tA = __builtin_amdgcn_perm(sub16(ai, el), sub16(ad, f), kSignSel);
           const uint32_t tB = __builtin_amdgcn_perm(sub16(diag, hv), sub16(f, hv), kSignSel);
           const uint32_t msk = 0x01010101u << (c & 7);
@@ -231,11 +234,12 @@ __global__ __launch_bounds__(kWave) void dp_i16_kernel(DpParams p) {
         hl_out = hl;
         el_out = el;
         if (last) {
-          // key = (M^(i, n) << 16) | (0xffff - i): the max is the best score,
-          // then the smallest row
+          // key = ((M^(i, n) + i S_GE) << 16) | (0xffff - i): the max is the
+          // best score M(i, n) - n S_GE, then the smallest row
           const uint32_t inv = 0xffffu - (uint32_t)i;
-          const int32_t k0 = (int32_t)((H[K - 1] << 16) | inv);
-          const int32_t k1 = (int32_t)((H[K - 1] & 0xffff0000u) | inv);
+          const uint32_t v = add16(H[K - 1], rge);
+          const int32_t k0 = (int32_t)((v << 16) | inv);
+          const int32_t k1 = (int32_t)((v & 0xffff0000u) | inv);
           if (i <= mg[0]) best0 = max(best0, k0);
           if (i <= mg[1]) best1 = max(best1, k1);
         }
@@ -243,6 +247,8 @@ __global__ __launch_bounds__(kWave) void dp_i16_kernel(DpParams p) {
 #pragma unroll
       for (int w = 0; w < W; ++w) sp[w * kWave + lane] = make_uint2(accA[w], accB[w]);
       sp += W * kWave;
+      bnd = add16(bnd, c_nge);
+      rge = add16(rge, c_ge);
     }
 
 #pragma unroll
@@ -251,7 +257,7 @@ __global__ __launch_bounds__(kWave) void dp_i16_kernel(DpParams p) {
       if (last) {
         const int32_t b = h ? best1 : best0;
         s_end[u] = 0xffff - (b & 0xffff);
-        s_score[u] = b >> 16;   // M^(end, n); the traceback lane adds n * S_MI
+        s_score[u] = b >> 16;   // M(end, n) - n S_GE; the traceback lane adds n S_GE
       }
     }
     ++r;
@@ -271,7 +277,7 @@ __global__ __launch_bounds__(kWave) void dp_i16_kernel(DpParams p) {
           const int rs = lane / TPW, ui = lane % TPW;
           const int h = ui / G, gq = ui % G;
           const int32_t tn = s_n[lane], tpad = s_pad[lane], tend = s_end[lane];
-          p.score[tk] = s_score[lane] + tn * mi;
+          p.score[tk] = s_score[lane] + tn * ge;
           p.ref_end[tk] = tend;
           p.status[tk] = p.ok_status;
           const uint2 *base =

@@ -9,6 +9,13 @@
 //    result row is read from a fixed register.  Columns left of the read are
 //    "virtual": their delta is 0 and their M stays 0, which reproduces the
 //    boundary M(i,0) = 0 exactly, and I there never beats opening a gap.
+//    (In offset form a virtual column's M^ is -(i+j)*S_GE, kept by its
+//    diagonal constant -2 S_GE.)
+//  * Values are kept in the offset form  X^(i,j) = X(i,j) - (i+j)*S_GE  for
+//    X = M, I, D (exact, and an order-preserving shift within each cell).
+//    Gap extension then adds nothing:  I^(i,j) = max(M^(i,j-1) + S_GO - S_GE,
+//    I^(i,j-1)),  D^(i,j) = max(M^(i-1,j) + S_GO - S_GE, D^(i-1,j)),  and the
+//    diagonal adds delta - 2 S_GE.  The result row compares M^(i,n) + i*S_GE.
 //  * The window (rows i = 1..m) is swept along anti-diagonals: at step t lane
 //    l of a task computes row t + 1 - l for its K columns, left to right.  The
 //    only value crossing lanes is the left neighbour's last column (M and I
@@ -86,6 +93,9 @@ __global__ __launch_bounds__(kWave) void dp_i32_kernel(DpParams p) {
 
     StripWords rw{0, 0, 0, 0};
     if (valid) rw.load(p.read_codes, rwo, n, lg * K - pad);
+    const int32_t ge = p.ge;
+    const int32_t c_go = p.go - ge;          // gap open in offset form
+    const int32_t c_ma = p.ma - 2 * ge;      // diagonal constants in offset form
     int32_t Rc[K], Mi[K], H[K], F[K];
 #pragma unroll
     for (int c = 0; c < K; ++c) {
@@ -93,8 +103,9 @@ __global__ __launch_bounds__(kWave) void dp_i32_kernel(DpParams p) {
       const bool real = valid && q >= 0;
       const uint32_t code = real ? rw.code(q) : 4u;   // 4 never equals a window base
       Rc[c] = (int32_t)code;
-      Mi[c] = real ? p.mi : 0;
-      H[c] = real ? p.go + q * p.ge : 0;   // M(0, q+1), or 0 left of the read
+      Mi[c] = real ? p.mi - 2 * ge : -2 * ge;
+      // M^(0, j), j = q + 1: S_GO + (j-1) S_GE - j S_GE, or 0 - j S_GE left of the read
+      H[c] = real ? c_go : -(q + 1) * ge;
       F[c] = kNeg32;                       // D(0, j)
       // finish each column before the next: bounds live registers in set-up
       asm volatile("" : "+v"(Rc[c]), "+v"(Mi[c]), "+v"(H[c]));
@@ -112,10 +123,14 @@ __global__ __launch_bounds__(kWave) void dp_i32_kernel(DpParams p) {
     uint32_t tn0, tn1, tw = 0;
     load_block(0, tn0, tn1);
 
-    int32_t hl_out = H[K - 1];   // M(0, last column of the strip)
+    int32_t hl_out = H[K - 1];   // M^(0, last column of the strip)
     int32_t el_out = kNeg32;
     int32_t t_out = 0;
-    int32_t hl_prev = 0;
+    // left boundary M^(i, -pad) = -(i - pad) S_GE (true value 0): row 0 is the
+    // first lane's first diagonal, row 1 its first left neighbour
+    int32_t hl_prev = pad * ge;
+    int32_t bnd = (pad - 1) * ge;
+    int32_t rge = (1 - lg) * ge;   // i * S_GE of this lane's current row
     int32_t best = INT32_MIN, endi = 0;
     uint32_t acc[W];
 #pragma unroll
@@ -128,10 +143,10 @@ __global__ __launch_bounds__(kWave) void dp_i32_kernel(DpParams p) {
         load_block((t >> 4) + 1, tn0, tn1);
       }
       const int32_t tfirst = (int32_t)((tw >> ((t & 15) * 2)) & 3u);
-      // the first lane of a task receives the left boundary M = 0, I = -inf
+      // the first lane of a task receives the left boundary (M = 0, I = -inf)
       // and the row's window base; its diagonal is the boundary received one
       // step earlier
-      int32_t hl = group_shr1<L>(hl_out, 0, first);
+      int32_t hl = group_shr1<L>(hl_out, bnd, first);
       int32_t el = group_shr1<L>(el_out, kNeg32, first);
       const int32_t T = group_shr1<L>(t_out, tfirst, first);
       const int32_t hd = hl_prev;
@@ -141,16 +156,15 @@ __global__ __launch_bounds__(kWave) void dp_i32_kernel(DpParams p) {
       if ((uint32_t)(t - lg) < (uint32_t)mg) {   // 1 <= i <= mg
         // The diagonal candidate of column c+1 is formed from the old H[c]
         // before H[c] is overwritten, so every update happens in place.
-        int32_t diag = hd + (Rc[0] == T ? p.ma : Mi[0]);
+        int32_t diag = hd + (Rc[0] == T ? c_ma : Mi[0]);
 #pragma unroll
         for (int c = 0; c < K; ++c) {
-          const int32_t ad = H[c] + p.go;
-          const int32_t fe = F[c] + p.ge;
+          const int32_t ad = H[c] + c_go;
           int32_t diag_next = 0;
-          if (c + 1 < K) diag_next = H[c] + (Rc[c + 1] == T ? p.ma : Mi[c + 1]);
-          const int32_t ai = hl + p.go;
-          el = max(ai, el + p.ge);
-          const int32_t f = max(ad, fe);
+          if (c + 1 < K) diag_next = H[c] + (Rc[c + 1] == T ? c_ma : Mi[c + 1]);
+          const int32_t ai = hl + c_go;
+          el = max(ai, el);
+          const int32_t f = max(ad, F[c]);
           const int32_t h = max(max(diag, el), f);
           uint32_t a = acc[c / 8];
           a = push_sign(a, ai - el);
@@ -171,11 +185,15 @@ __global__ __launch_bounds__(kWave) void dp_i32_kernel(DpParams p) {
         if (K % 8) acc[W - 1] <<= 4 * (8 - K % 8);
         hl_out = hl;
         el_out = el;
-        if (last && H[K - 1] > best) { best = H[K - 1]; endi = i; }
+        // M(i, n) - n S_GE = M^(i, n) + i S_GE
+        const int32_t v = H[K - 1] + rge;
+        if (last && v > best) { best = v; endi = i; }
       }
 #pragma unroll
       for (int w = 0; w < W; ++w) sp[w * kWave + lane] = acc[w];
       sp += W * kWave;
+      bnd -= ge;
+      rge += ge;
     }
 
     if (last) { s_end[u0] = endi; s_score[u0] = best; }
@@ -194,7 +212,7 @@ __global__ __launch_bounds__(kWave) void dp_i32_kernel(DpParams p) {
           p.status[tk] = tst;
         } else {
           const int32_t tn = s_n[lane], tpad = s_pad[lane], tend = s_end[lane];
-          p.score[tk] = s_score[lane];
+          p.score[tk] = s_score[lane] + tn * p.ge;
           p.ref_end[tk] = tend;
           p.status[tk] = p.ok_status;
           const int rs = lane / G, gq = lane % G;

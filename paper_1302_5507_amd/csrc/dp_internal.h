@@ -62,23 +62,26 @@ struct Shape {
   int cells;
 };
 
-// int16 form: a task can run in packed int16 iff every value the kernel
-// forms stays inside int16 (the bound on all maxima, widened by the largest
-// constant added to a value and by the column offset) and the substitution
-// scores fit the byte table.  Evaluated identically on host and device.
-__host__ __device__ inline bool int16_fits(int32_t n, int32_t cols, int32_t ma, int32_t mi,
-                                           int32_t go, int32_t ge) {
-  if (mi > 0 || ma - mi > 255 || -mi > 255) return false;
-  auto iabs = [](int32_t v) { return v < 0 ? -v : v; };
-  int32_t s = ma - mi;
-  s = s > iabs(go - mi) ? s : iabs(go - mi);
-  s = s > iabs(ge - mi) ? s : iabs(ge - mi);
-  s = s > iabs(go) ? s : iabs(go);
+// int16 form: a task (read of n bases, window of m) can run in packed int16
+// iff the diagonal constants of the offset form X - (i+j) S_GE fit a byte
+// table (0 <= S_MI - 2 S_GE, S_MA - 2 S_GE <= 255) and every value the
+// kernel forms stays inside int16: real cells lie between the lowest
+// possible maximum and n S_MA, shifted up by at most (m + n) |S_GE|; virtual
+// columns hold (i+j) |S_GE| with j down to -cols; each bound is widened by
+// twice the largest constant added.  Evaluated identically on host and device.
+__host__ __device__ inline bool int16_fits(int32_t n, int32_t m, int32_t cols, int32_t ma,
+                                           int32_t mi, int32_t go, int32_t ge) {
+  const int64_t d_ma = int64_t(ma) - 2 * int64_t(ge);
+  const int64_t d_mi = int64_t(mi) - 2 * int64_t(ge);
+  const int64_t d_v = -2 * int64_t(ge);
+  if (d_mi < 0 || d_ma > 255 || d_v > 255) return false;
+  auto iabs = [](int64_t v) { return v < 0 ? -v : v; };
+  int64_t s = iabs(int64_t(go) - ge);
+  s = s > d_ma ? s : d_ma;
   s = s > iabs(ge) ? s : iabs(ge);
-  const int64_t lo = 2 * int64_t(go) + int64_t(n - 1) * ge;     // lowest maximum
-  const int64_t hi = int64_t(n) * (ma - mi);                      // highest offset value
-  const int64_t virt = int64_t(cols) * iabs(mi);                  // virtual-column offset
-  return lo - 2 * s > -32000 && hi + 2 * s < 32000 && virt + 2 * s < 32000;
+  const int64_t lo = 2 * int64_t(go) + int64_t(n - 1) * ge - int64_t(cols) * iabs(ge);
+  const int64_t hi = int64_t(n) * ma + (int64_t(m) + n + cols) * iabs(ge);
+  return lo - 2 * s > -32000 && hi + 2 * s < 32000;
 }
 
 // Launch the int32 kernel of shape `s` (must be one of the compiled shapes).

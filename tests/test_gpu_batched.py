@@ -77,15 +77,18 @@ def _int16_class_cols(al, n):
     return None
 
 
-def _int16_fits(n, cols, sc):
+def _int16_fits(n, m, cols, sc):
+    """The int16 range rule of the batched form, restated: the diagonal
+    constants of the offset form X - (i+j) S_GE fit a byte, and the value
+    bounds widened by twice the largest added constant stay inside int16."""
     ma, mi, go, ge = sc
-    if mi > 0 or ma - mi > 255 or -mi > 255:
+    d_ma, d_mi, d_v = ma - 2 * ge, mi - 2 * ge, -2 * ge
+    if d_mi < 0 or d_ma > 255 or d_v > 255:
         return False
-    s = max(ma - mi, abs(go - mi), abs(ge - mi), abs(go), abs(ge))
-    lo = 2 * go + (n - 1) * ge
-    hi = n * (ma - mi)
-    virt = cols * abs(mi)
-    return lo - 2 * s > -32000 and hi + 2 * s < 32000 and virt + 2 * s < 32000
+    s = max(abs(go - ge), d_ma, abs(ge))
+    lo = 2 * go + (n - 1) * ge - cols * abs(ge)
+    hi = n * ma + (m + n + cols) * abs(ge)
+    return lo - 2 * s > -32000 and hi + 2 * s < 32000
 
 
 @pytest.mark.parametrize("k", [50, 100, 128])
@@ -100,7 +103,8 @@ def test_overflow_redo_scaled(al, k):
     assert_same(as_oracle_status(g), ref, label=f"x{k}")
     base = oracle_align(w, CONFIG_SCORING)
     assert np.array_equal(ref.score, k * base.score)
-    want = np.array([not _int16_fits(int(n), _int16_class_cols(al, int(n)), sc) for n in w.read_len])
+    want = np.array([not _int16_fits(int(n), int(m), _int16_class_cols(al, int(n)), sc)
+                     for n, m in zip(w.read_len, w.ref_len)])
     assert np.array_equal(g["status"] == binding.TASK_OK_REDONE_INT32, want)
     assert want.any()
 
