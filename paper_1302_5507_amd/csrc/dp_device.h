@@ -57,10 +57,12 @@ __device__ void traceback_task(const DpParams &p, int64_t task, int32_t n, int32
   int32_t wpos = p.cigar_stride;  // runs are written backward from the row end
   int32_t cur = 3, run = 0;       // current run (3: none yet)
   int32_t i = end, j = n, state = 0;  // 0 = M, 1 = D, 2 = I
-  bool bad = false;
+  // Cells (i, j) with 1 <= i <= max_m and 1 <= j <= n lie inside the task's
+  // decision slot; an end or length outside that range is never walked.
+  bool bad = end < 1 || end > p.max_m || n < 1 || n > p.max_n;
   // Every iteration lowers i or j, so the walk ends within n + end steps.
   // The guard keeps a corrupted decision from reading outside the task.
-  for (int32_t guard = n + end + 1; guard > 0; --guard) {
+  for (int32_t guard = bad ? 0 : n + end + 1; guard > 0; --guard) {
     if (state == 0 && (i == 0 || j == 0)) break;
     if (i < 1 || j < 1) { bad = true; break; }
     const uint32_t nib = nib_at(i, j);
