@@ -21,7 +21,10 @@ using namespace soapdp;
 
 namespace {
 
-constexpr size_t kScratchCap = size_t(8) << 30;   // decision-bit scratch budget
+constexpr size_t kScratchCap = size_t(16) << 30;  // decision-bit scratch budget
+// Small device buffer (int32 units): hist | max_m | offset | cursor |
+// work_counter | defer, then two uint64 tables (slot_dwords, scratch_off).
+constexpr int kSmallInts = 6 * kMaxClasses + 4 * kMaxClasses;
 constexpr int kGraphCacheMax = 16;
 
 struct ClassSpec {
@@ -66,7 +69,7 @@ struct soap_dp_ctx {
   // workspace
   void *scratch = nullptr;
   size_t scratch_bytes = 0;
-  int32_t *small = nullptr;          // hist | offset | cursor | work_counter
+  int32_t *small = nullptr;          // bucketing tables and class plans (kSmallInts)
   uint8_t *task_class = nullptr;
   int32_t *task_list = nullptr;
   int64_t task_cap = 0;
@@ -283,6 +286,22 @@ hipError_t launch_shape(int prec, Shape s, int grid, hipStream_t stream, const D
   return prec == 16 ? launch_dp_i16(s, grid, stream, p) : launch_dp_i32(s, grid, stream, p);
 }
 
+// Device tables of the bucketing and the class plans, carved from `small`.
+BucketBuffers bucket_buffers(const soap_dp_ctx *ctx) {
+  BucketBuffers b{};
+  b.task_class = ctx->task_class;
+  b.task_list = ctx->task_list;
+  b.hist = ctx->small;
+  b.max_m = ctx->small + kMaxClasses;
+  b.offset = ctx->small + 2 * kMaxClasses;
+  b.cursor = ctx->small + 3 * kMaxClasses;
+  b.work_counter = ctx->small + 4 * kMaxClasses;
+  b.defer = ctx->small + 5 * kMaxClasses;
+  b.slot_dwords = reinterpret_cast<uint64_t *>(ctx->small + 6 * kMaxClasses);
+  b.scratch_off = reinterpret_cast<uint64_t *>(ctx->small + 8 * kMaxClasses);
+  return b;
+}
+
 // ------------------------------------------------------------------ plain
 
 size_t plain_scratch_bytes(const soap_dp_ctx *ctx, int64_t n_tasks, int32_t max_n, int32_t max_m) {
@@ -302,7 +321,11 @@ int align_plain(soap_dp_ctx *ctx, const soap_dp_batch *in, const soap_dp_scoring
   p.scratch = static_cast<uint32_t *>(ctx->scratch);
   p.slot_dwords = q.slot_dwords;
   p.defer = q.defer;
-  const hipError_t e = launch_dp_i32(s, q.grid, stream, p);
+  // work queue: waves share SIMDs unevenly, so a static split of the work
+  // items would leave the launch waiting on the most crowded SIMDs
+  p.work_counter = bucket_buffers(ctx).work_counter;
+  hipError_t e = launch_zero(p.work_counter, 1, stream);
+  if (e == hipSuccess) e = launch_dp_i32(s, q.grid, stream, p);
   if (e != hipSuccess) return hip_fail(ctx, e);
   return SOAP_DP_OK;
 }
@@ -343,36 +366,37 @@ std::vector<int> live_classes(const soap_dp_ctx *ctx, int32_t max_n, int32_t max
   return live;
 }
 
-// Launch plans of the live classes, which run concurrently, each in its own
-// scratch region.  The host does not know how the tasks split over the
-// classes, so each class is planned for the whole batch; deferral is then
-// trimmed, largest region first, until the regions fit the scratch budget.
-std::vector<LaunchPlan> batched_plans(const soap_dp_ctx *ctx, int64_t n_tasks, int32_t max_m,
-                                      const std::vector<int> &live) {
-  std::vector<LaunchPlan> plans;
-  size_t total = 0;
+// Scratch of the batched form.  The live classes run concurrently, each in
+// its own region, and their plans (deferral, slot size, region) are made on
+// the device from the actual split of the tasks (the scan kernel).  The host
+// reserves a budget that holds every live class's full grid of slots for
+// the batch's longest window at deferral 1, whatever the split, and
+// otherwise room for every class to reach full deferral as if it held the
+// whole batch, up to the scratch cap; plus slack for region rounding.
+struct BatchedPlan {
+  std::vector<int> grids;
+  uint64_t budget_dwords = 0;
+  size_t bytes() const { return size_t(budget_dwords + 64 * kMaxClasses) * 4; }
+};
+
+BatchedPlan batched_plan(const soap_dp_ctx *ctx, int64_t n_tasks, int32_t max_m,
+                         const std::vector<int> &live) {
+  BatchedPlan bp;
+  uint64_t need = 0, want = 0;
   for (int k : live) {
     const ClassSpec &c = ctx->classes[size_t(k)];
-    plans.push_back(plan_launch(ctx, c.prec, c.shape, n_tasks, max_m, kScratchCap));
-    total += plans.back().bytes();
+    const LaunchPlan q = plan_launch(ctx, c.prec, c.shape, n_tasks, max_m, SIZE_MAX);
+    bp.grids.push_back(q.grid);
+    need += round64(uint64_t(q.grid) * q.slot_dwords);
+    want += round64(uint64_t(q.grid) * uint64_t(q.defer) * q.slot_dwords);
   }
-  while (total > kScratchCap) {
-    size_t worst = 0;
-    for (size_t i = 1; i < plans.size(); ++i)
-      if (plans[i].bytes() > plans[worst].bytes()) worst = i;
-    if (plans.empty() || plans[worst].defer == 1) break;
-    total -= plans[worst].bytes();
-    --plans[worst].defer;
-    total += plans[worst].bytes();
-  }
-  return plans;
+  bp.budget_dwords = std::max<uint64_t>(need, std::min<uint64_t>(want, kScratchCap / 4));
+  return bp;
 }
 
 size_t batched_scratch_bytes(const soap_dp_ctx *ctx, int64_t n_tasks, int32_t max_m,
                              const std::vector<int> &live) {
-  size_t b = 0;
-  for (const LaunchPlan &q : batched_plans(ctx, n_tasks, max_m, live)) b += q.bytes();
-  return b;
+  return batched_plan(ctx, n_tasks, max_m, live).bytes();
 }
 
 int ensure_class_streams(soap_dp_ctx *ctx, size_t n) {
@@ -391,52 +415,58 @@ int ensure_class_streams(soap_dp_ctx *ctx, size_t n) {
   return SOAP_DP_OK;
 }
 
-ClassTable class_table(const soap_dp_ctx *ctx) {
+// Class table of one batched call: classes, and for the live ones the launch
+// fields the device planner needs (dead classes get grid 0 and no tasks).
+ClassTable class_table(const soap_dp_ctx *ctx, const std::vector<int> &live,
+                       const BatchedPlan &bp) {
   ClassTable ct{};
   ct.count = int32_t(ctx->classes.size());
   for (size_t k = 0; k < ctx->classes.size(); ++k) {
-    ct.cap[k] = ctx->classes[k].cap;
-    ct.cols[k] = ctx->classes[k].shape.lanes * ctx->classes[k].shape.cells;
-    ct.prec[k] = ctx->classes[k].prec;
+    const ClassSpec &c = ctx->classes[k];
+    ct.cap[k] = c.cap;
+    ct.cols[k] = c.shape.lanes * c.shape.cells;
+    ct.prec[k] = c.prec;
+    ct.per_item[k] = int32_t(tasks_per_item(c.prec, c.shape));
+    ct.grid[k] = 0;
+    ct.max_defer[k] = kWave / ct.per_item[k];
+    ct.lanes[k] = c.shape.lanes;
+    ct.step_block[k] = step_block(c.shape.cells);
+    ct.step_dwords[k] = int32_t(uint64_t((c.shape.cells + 7) / 8) * kWave * (c.prec == 16 ? 2 : 1));
   }
+  for (size_t li = 0; li < live.size(); ++li) ct.grid[live[li]] = bp.grids[li];
+  ct.budget_dwords = bp.budget_dwords;
   return ct;
 }
+
 
 // Enqueue the whole batched sequence on `stream` (also used under capture,
 // so the launch plans are computed beforehand: no runtime queries in between).
 hipError_t enqueue_batched(soap_dp_ctx *ctx, const soap_dp_batch *in, const soap_dp_scoring *sc,
                            const soap_dp_result *out, const std::vector<int> &live,
-                           const std::vector<LaunchPlan> &plans, hipStream_t stream) {
+                           const BatchedPlan &bp, hipStream_t stream) {
   DpParams p = make_params(in, sc, out);
-  BucketBuffers b{};
-  b.task_class = ctx->task_class;
-  b.task_list = ctx->task_list;
-  b.hist = ctx->small;
-  b.offset = ctx->small + kMaxClasses;
-  b.cursor = ctx->small + 2 * kMaxClasses;
-  b.work_counter = ctx->small + 3 * kMaxClasses;
-  hipError_t e = launch_bucketing(p, class_table(ctx), b, stream);
+  const BucketBuffers b = bucket_buffers(ctx);
+  hipError_t e = launch_bucketing(p, class_table(ctx, live, bp), b, stream);
   if (e != hipSuccess) return e;
   // fork: every class kernel waits for the bucketing only, then they run
   // concurrently; the caller's stream joins them all
   if ((e = hipEventRecord(ctx->fork_event, stream)) != hipSuccess) return e;
   p.task_list = ctx->task_list;
-  size_t scratch_off = 0;
+  p.scratch = static_cast<uint32_t *>(ctx->scratch);
   for (size_t li = 0; li < live.size(); ++li) {
     const int k = live[li];
     const ClassSpec &c = ctx->classes[size_t(k)];
     hipStream_t cs = ctx->class_streams[li];
     if ((e = hipStreamWaitEvent(cs, ctx->fork_event, 0)) != hipSuccess) return e;
     DpParams q = p;
-    q.scratch = reinterpret_cast<uint32_t *>(static_cast<char *>(ctx->scratch) + scratch_off);
-    scratch_off += plans[li].bytes();
     q.task_off = b.offset + k;
     q.task_count = b.hist + k;
     q.work_counter = b.work_counter + k;
-    q.slot_dwords = plans[li].slot_dwords;
-    q.defer = plans[li].defer;
+    q.defer_dev = b.defer + k;
+    q.slot_dwords_dev = b.slot_dwords + k;
+    q.scratch_off_dev = b.scratch_off + k;
     q.ok_status = c.prec == 16 ? kTaskOk : kTaskRedone;
-    if ((e = launch_shape(c.prec, c.shape, plans[li].grid, cs, q)) != hipSuccess) return e;
+    if ((e = launch_shape(c.prec, c.shape, bp.grids[li], cs, q)) != hipSuccess) return e;
     if ((e = hipEventRecord(ctx->join_events[li], cs)) != hipSuccess) return e;
     if ((e = hipStreamWaitEvent(stream, ctx->join_events[li], 0)) != hipSuccess) return e;
   }
@@ -450,13 +480,11 @@ int align_batched(soap_dp_ctx *ctx, const soap_dp_batch *in, const soap_dp_scori
   if (rc) return rc;
   rc = ensure_class_streams(ctx, live.size());
   if (rc) return rc;
-  const std::vector<LaunchPlan> plans = batched_plans(ctx, in->n_tasks, in->max_m, live);
-  size_t need = 0;
-  for (const LaunchPlan &q : plans) need += q.bytes();
-  rc = ensure_scratch(ctx, need);
+  const BatchedPlan bp = batched_plan(ctx, in->n_tasks, in->max_m, live);
+  rc = ensure_scratch(ctx, bp.bytes());
   if (rc) return rc;
   if (!ctx->use_graphs) {
-    const hipError_t e = enqueue_batched(ctx, in, sc, out, live, plans, stream);
+    const hipError_t e = enqueue_batched(ctx, in, sc, out, live, bp, stream);
     return e == hipSuccess ? SOAP_DP_OK : hip_fail(ctx, e);
   }
   GraphKey key;
@@ -474,7 +502,7 @@ int align_batched(soap_dp_ctx *ctx, const soap_dp_batch *in, const soap_dp_scori
       return hip_fail(ctx, hipGetLastError());
     hipError_t e = hipStreamBeginCapture(ctx->capture_stream, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return hip_fail(ctx, e);
-    const hipError_t le = enqueue_batched(ctx, in, sc, out, live, plans, ctx->capture_stream);
+    const hipError_t le = enqueue_batched(ctx, in, sc, out, live, bp, ctx->capture_stream);
     hipGraph_t graph = nullptr;
     e = hipStreamEndCapture(ctx->capture_stream, &graph);
     if (le != hipSuccess || e != hipSuccess) {
@@ -637,7 +665,7 @@ double time_shape(soap_dp_ctx *ctx, int prec, Shape s, const TuneData &d, int32_
   p.defer = q.defer;
   if (ensure_scratch(ctx, q.bytes())) return 0;
   p.scratch = static_cast<uint32_t *>(ctx->scratch);
-  p.work_counter = ctx->small + 3 * kMaxClasses;
+  p.work_counter = bucket_buffers(ctx).work_counter;
   hipEvent_t a, b;
   (void)hipEventCreate(&a);
   (void)hipEventCreate(&b);
@@ -716,7 +744,7 @@ int soap_dp_create(soap_dp_ctx **out, int device_ordinal) {
   ctx->use_graphs = !(ng && ng[0] && ng[0] != '0');
   {
     DeviceGuard dg(device_ordinal);
-    if (hipMalloc(reinterpret_cast<void **>(&ctx->small), 4 * kMaxClasses * sizeof(int32_t)) != hipSuccess) {
+    if (hipMalloc(reinterpret_cast<void **>(&ctx->small), kSmallInts * sizeof(int32_t)) != hipSuccess) {
       (void)hipGetLastError();
       delete ctx;
       return SOAP_DP_ENOMEM;
@@ -763,7 +791,7 @@ size_t soap_dp_workspace_bytes(const soap_dp_ctx *ctx, int64_t n_tasks, int32_t 
   if (!ctx || n_tasks <= 0 || max_n < 1 || max_n > SOAP_DP_MAX_READ || max_m < 1 ||
       max_m > SOAP_DP_MAX_WINDOW)
     return 0;
-  const size_t small = 4 * kMaxClasses * sizeof(int32_t);
+  const size_t small = kSmallInts * sizeof(int32_t);
   if (flags == SOAP_DP_PLAIN) return plain_scratch_bytes(ctx, n_tasks, max_n, max_m) + small;
   // the int32 classes are counted too: the scoring is not known here
   std::vector<int> live;
@@ -783,7 +811,7 @@ int soap_dp_reserve(soap_dp_ctx *ctx, int64_t n_tasks, int32_t max_n, int32_t ma
   const size_t b = soap_dp_workspace_bytes(ctx, n_tasks, max_n, max_m, flags);
   if (b == 0) return SOAP_DP_EINVAL;
   DeviceGuard dg(ctx->device);
-  const size_t small = 4 * kMaxClasses * sizeof(int32_t);
+  const size_t small = kSmallInts * sizeof(int32_t);
   size_t scratch = b - small;
   if (flags != SOAP_DP_PLAIN) {
     scratch -= size_t(n_tasks) * 5;

@@ -9,24 +9,47 @@ constexpr int kMaxClasses = 32;
 // Classes in the order tried: int16 classes by ascending capacity, then
 // int32 classes by ascending capacity.  A class's capacity is its upper
 // bound on read length; `cols` is lanes * cells of its current shape.
+//
+// The launch fields describe each class kernel as the host enqueues it:
+// tasks per work item, grid, the most work items a workgroup may defer
+// before tracing back (64 / tasks per item), lanes per task and decision
+// dwords per sweep step; a slot holds (longest window + lanes - 1) steps
+// rounded up to whole blocks.
+// `budget_dwords` is the scratch the context holds for all class kernels.
 struct ClassTable {
   int32_t count;
   int32_t cap[kMaxClasses];
   int32_t cols[kMaxClasses];
   int32_t prec[kMaxClasses];
+  int32_t per_item[kMaxClasses];
+  int32_t grid[kMaxClasses];
+  int32_t max_defer[kMaxClasses];
+  int32_t lanes[kMaxClasses];
+  int32_t step_dwords[kMaxClasses];   // decision dwords per sweep step
+  int32_t step_block[kMaxClasses];    // slots hold whole blocks of this many steps
+  uint64_t budget_dwords;
 };
 
+// Device buffers of the bucketing and of the class plans; `hist` and
+// `max_m` are adjacent (one fill clears both).
 struct BucketBuffers {
   uint8_t *task_class;    // n_tasks
   int32_t *task_list;     // n_tasks, class segments
   int32_t *hist;          // kMaxClasses: tasks per class
+  int32_t *max_m;         // kMaxClasses: longest window per class
   int32_t *offset;        // kMaxClasses: segment starts
   int32_t *cursor;        // kMaxClasses
   int32_t *work_counter;  // kMaxClasses: persistent-kernel work queues
+  int32_t *defer;         // kMaxClasses: deferral of each class kernel
+  uint64_t *slot_dwords;  // kMaxClasses: decision-slot size of each class
+  uint64_t *scratch_off;  // kMaxClasses: scratch region of each class (dwords)
 };
 
+// Round a region to 64 dwords (256 bytes).
+__host__ __device__ inline uint64_t round64(uint64_t dwords) { return (dwords + 63) & ~uint64_t(63); }
+
 // Enqueue: zero the histogram, classify (invalid tasks get their outputs),
-// scan, scatter.  `p` carries the batch, scoring and outputs.
+// scan and plan, scatter.  `p` carries the batch, scoring and outputs.
 hipError_t launch_bucketing(const DpParams &p, const ClassTable &ct, const BucketBuffers &b,
                             hipStream_t stream);
 hipError_t launch_zero(int32_t *a, int n, hipStream_t stream);

@@ -32,9 +32,10 @@ __global__ void zero_kernel(int32_t *a, int n) {
 }
 
 __global__ __launch_bounds__(kBlock) void classify_kernel(DpParams p, ClassTable ct,
-                                                          uint8_t *task_class, int32_t *hist) {
-  __shared__ int32_t s_hist[kMaxClasses];
-  for (int k = threadIdx.x; k < kMaxClasses; k += kBlock) s_hist[k] = 0;
+                                                          uint8_t *task_class, int32_t *hist,
+                                                          int32_t *max_m) {
+  __shared__ int32_t s_hist[kMaxClasses], s_maxm[kMaxClasses];
+  for (int k = threadIdx.x; k < kMaxClasses; k += kBlock) { s_hist[k] = 0; s_maxm[k] = 0; }
   __syncthreads();
   const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (t < p.n_tasks) {
@@ -59,25 +60,66 @@ __global__ __launch_bounds__(kBlock) void classify_kernel(DpParams p, ClassTable
     } else {
       task_class[t] = (uint8_t)k;
       atomicAdd(&s_hist[k], 1);
+      atomicMax(&s_maxm[k], m);
     }
   }
   __syncthreads();
   for (int k = threadIdx.x; k < ct.count; k += kBlock)
-    if (s_hist[k]) atomicAdd(&hist[k], s_hist[k]);
+    if (s_hist[k]) {
+      atomicAdd(&hist[k], s_hist[k]);
+      atomicMax(&max_m[k], s_maxm[k]);
+    }
 }
 
-// One workgroup: class offsets (exclusive scan of the histogram) and the
-// cursors the scatter advances.
-__global__ void scan_kernel(const int32_t *hist, int32_t *offset, int32_t *cursor,
-                            int32_t *work_counter, int count) {
-  if (threadIdx.x == 0) {
-    int32_t acc = 0;
-    for (int k = 0; k < count; ++k) {
-      offset[k] = acc;
-      cursor[k] = acc;
-      work_counter[k] = 0;
-      acc += hist[k];
-    }
+// One thread: class offsets (exclusive scan of the histogram), the cursors
+// the scatter advances, and the launch plan of every class from its actual
+// tasks.  A class with h tasks has ceil(h / per_item) work items, so
+// g = min(grid, items) workgroups do work, each deferring up to
+// min(max_defer, ceil(items / g)) items into slots sized for the class's
+// longest window.  While the regions g * defer * slot exceed the budget, the
+// largest region's deferral drops by one; with every deferral at 1 the
+// regions fit, because the budget covers every live class's full grid of
+// slots for the batch's longest window.  Regions are laid out back to back,
+// 64-dword aligned.
+__global__ void scan_kernel(ClassTable ct, const int32_t *hist, const int32_t *max_m,
+                            int32_t *offset, int32_t *cursor, int32_t *work_counter,
+                            int32_t *defer, uint64_t *slot_dwords, uint64_t *scratch_off) {
+  if (threadIdx.x != 0) return;
+  int32_t acc = 0;
+  uint64_t region[kMaxClasses];   // dwords per unit of deferral
+  uint64_t total = 0;
+  for (int k = 0; k < ct.count; ++k) {
+    offset[k] = acc;
+    cursor[k] = acc;
+    work_counter[k] = 0;
+    acc += hist[k];
+    const int64_t items = (int64_t(hist[k]) + ct.per_item[k] - 1) / ct.per_item[k];
+    const int64_t g = items < ct.grid[k] ? items : ct.grid[k];
+    int64_t d = g > 0 ? (items + g - 1) / g : 1;
+    d = d < ct.max_defer[k] ? d : ct.max_defer[k];
+    d = d > 1 ? d : 1;
+    const uint64_t B = uint64_t(ct.step_block[k]);
+    const uint64_t steps = (uint64_t(max_m[k] + ct.lanes[k] - 1) + B - 1) / B * B;
+    const uint64_t slot = hist[k] > 0 ? steps * uint64_t(ct.step_dwords[k]) : 0;
+    defer[k] = int32_t(d);
+    slot_dwords[k] = slot;
+    region[k] = uint64_t(g) * slot;
+    total += region[k] * uint64_t(d);
+  }
+  while (total > ct.budget_dwords) {
+    int worst = -1;
+    for (int k = 0; k < ct.count; ++k)
+      if (defer[k] > 1 && (worst < 0 || region[k] * uint64_t(defer[k]) >
+                                             region[worst] * uint64_t(defer[worst])))
+        worst = k;
+    if (worst < 0) break;
+    total -= region[worst];
+    --defer[worst];
+  }
+  uint64_t off = 0;
+  for (int k = 0; k < ct.count; ++k) {
+    scratch_off[k] = off;
+    off += round64(region[k] * uint64_t(defer[k]));
   }
 }
 
@@ -139,11 +181,11 @@ hipError_t launch_compact_cigar(const uint32_t *cigar, int32_t stride, const int
 hipError_t launch_bucketing(const DpParams &p, const ClassTable &ct, const BucketBuffers &b,
                             hipStream_t stream) {
   const int64_t blocks = (p.n_tasks + kBlock - 1) / kBlock;
-  hipLaunchKernelGGL(zero_kernel, dim3(1), dim3(64), 0, stream, b.hist, kMaxClasses);
+  hipLaunchKernelGGL(zero_kernel, dim3(1), dim3(64), 0, stream, b.hist, 2 * kMaxClasses);
   hipLaunchKernelGGL(classify_kernel, dim3((uint32_t)blocks), dim3(kBlock), 0, stream, p, ct,
-                     b.task_class, b.hist);
-  hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(64), 0, stream, b.hist, b.offset, b.cursor,
-                     b.work_counter, ct.count);
+                     b.task_class, b.hist, b.max_m);
+  hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(64), 0, stream, ct, b.hist, b.max_m, b.offset,
+                     b.cursor, b.work_counter, b.defer, b.slot_dwords, b.scratch_off);
   hipLaunchKernelGGL(scatter_kernel, dim3((uint32_t)blocks), dim3(kBlock), 0, stream, b.task_class,
                      p.n_tasks, b.cursor, b.task_list);
   return hipGetLastError();

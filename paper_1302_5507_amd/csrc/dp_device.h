@@ -46,40 +46,54 @@ __device__ __forceinline__ int32_t wave_max(int32_t v) {
 }
 
 // Walk the decision nibbles of one task back from (end, n) and write its
-// CIGAR.  `nib_at(i, j)` returns the decision nibble of cell (i, j):
-// bit3 I extended, bit2 D extended, bit1 M not from the diagonal, bit0 M not
-// from D.  One iteration per emitted operation; the state update is
-// select-based so that lanes tracing different tasks stay converged.
-template <class NibFn>
+// CIGAR.  The decision nibble of cell (i, j) has bit3 I extended, bit2 D
+// extended, bit1 M not from the diagonal, bit0 M not from D.  `tr` serves
+// nibbles from a window of cached decision words: `tr.get(i, j, nib)`
+// returns false when the cell is outside the window, after which
+// `tr.fill()` loads the window that holds it.
+//
+// The walk runs in rounds: every lane advances on cached words until it
+// misses or finishes, then all missing lanes of the wavefront refill at once
+// and wait for memory once.  One iteration per emitted operation; the state
+// update is select-based so that lanes tracing different tasks stay
+// converged.
+template <class Tracer>
 __device__ void traceback_task(const DpParams &p, int64_t task, int32_t n, int32_t end,
-                               NibFn nib_at) {
+                               int32_t slot_rows, Tracer &tr) {
   uint32_t *row = p.cigar + task * (int64_t)p.cigar_stride;
   int32_t wpos = p.cigar_stride;  // runs are written backward from the row end
   int32_t cur = 3, run = 0;       // current run (3: none yet)
   int32_t i = end, j = n, state = 0;  // 0 = M, 1 = D, 2 = I
-  // Cells (i, j) with 1 <= i <= max_m and 1 <= j <= n lie inside the task's
-  // decision slot; an end or length outside that range is never walked.
-  bool bad = end < 1 || end > p.max_m || n < 1 || n > p.max_n;
+  // Cells (i, j) with 1 <= i <= slot_rows and 1 <= j <= n lie inside the
+  // task's decision slot; an end or length outside that range is never walked.
+  bool bad = end < 1 || end > slot_rows || n < 1 || n > p.max_n;
   // Every iteration lowers i or j, so the walk ends within n + end steps.
   // The guard keeps a corrupted decision from reading outside the task.
-  for (int32_t guard = bad ? 0 : n + end + 1; guard > 0; --guard) {
-    if (state == 0 && (i == 0 || j == 0)) break;
-    if (i < 1 || j < 1) { bad = true; break; }
-    const uint32_t nib = nib_at(i, j);
-    const bool in_m = state == 0;
-    const bool diag = in_m && !(nib & 2u);
-    const bool to_d = in_m ? ((nib & 3u) == 2u) : state == 1;   // M from D, or still in D
-    const int32_t op = diag ? 0 : (to_d ? 2 : 1);              // M = 0, I = 1, D = 2
-    const int32_t next = diag ? 0 : (to_d ? ((nib & 4u) ? 1 : 0) : ((nib & 8u) ? 2 : 0));
-    if (op != cur && run > 0) {
-      if (wpos > 0) row[--wpos] = (uint32_t)run << 4 | (uint32_t)cur;
-      else bad = true;
+  int32_t guard = bad ? 0 : n + end + 1;
+  for (;;) {
+    bool miss = false;
+    for (; guard > 0; --guard) {
+      if (state == 0 && (i == 0 || j == 0)) { guard = 0; break; }
+      if (i < 1 || j < 1) { bad = true; guard = 0; break; }
+      uint32_t nib;
+      if (!tr.get(i, j, nib)) { miss = true; break; }
+      const bool in_m = state == 0;
+      const bool diag = in_m && !(nib & 2u);
+      const bool to_d = in_m ? ((nib & 3u) == 2u) : state == 1;   // M from D, or still in D
+      const int32_t op = diag ? 0 : (to_d ? 2 : 1);              // M = 0, I = 1, D = 2
+      const int32_t next = diag ? 0 : (to_d ? ((nib & 4u) ? 1 : 0) : ((nib & 8u) ? 2 : 0));
+      if (op != cur && run > 0) {
+        if (wpos > 0) row[--wpos] = (uint32_t)run << 4 | (uint32_t)cur;
+        else bad = true;
+      }
+      run = op == cur ? run + 1 : 1;
+      cur = op;
+      i -= op != 1;   // M and D consume a region base
+      j -= op != 2;   // M and I consume a read base
+      state = next;
     }
-    run = op == cur ? run + 1 : 1;
-    cur = op;
-    i -= op != 1;   // M and D consume a region base
-    j -= op != 2;   // M and I consume a read base
-    state = next;
+    if (!miss) break;
+    tr.fill();
   }
   int32_t begin = i;
   if (!bad && state == 0 && i == 0 && j > 0) {   // base case M(0, j): j insertions
@@ -106,31 +120,112 @@ __device__ void traceback_task(const DpParams &p, int64_t task, int32_t n, int32
   if (bad) p.status[task] = kTaskInvalidLen;
 }
 
-// Per-lane cache of one (lane, column-group) word over four consecutive
-// sweep steps [top - 3, top], held in LDS (`slots` points at this lane's four
-// entries): a diagonal or vertical move of the traceback usually stays inside
-// it, and a refill issues its four loads at once.
-template <class Word>
-struct StepCache {
-  int32_t lq = -1, w = -1, top = -1;
-  // `base` points at step 0 of this (lq, w); consecutive steps are `stride`
-  // Words apart.  Steps below 0 are clamped to 0 (never used).
-  __device__ __forceinline__ Word get(Word *slots, const Word *base, int32_t ts, int32_t lq_,
-                                      int32_t w_, uint32_t stride) {
-    uint32_t d = (uint32_t)(top - ts);
-    if (lq_ != lq || w_ != w || d > 3u) {
-      lq = lq_;
-      w = w_;
-      top = ts;
-      d = 0;
+// Decision slot layout.  A slot holds ceil(steps / B) blocks of B sweep
+// steps; block b, column group w is a run of 64 lanes x B words, lane-major:
+// word (lane, u) of that run is the decision word of `lane` at step
+// b * B + u.  The sweep writes one step at a time into an LDS staging
+// buffer (`stage`, row stride kStageRow words so that rows start in
+// different banks) and flushes a whole block with coalesced stores.
+constexpr int kStageRow = kWave + 1;
+
+template <class Word, int W, int B>
+__device__ __forceinline__ void stage_step(Word *stage, int lane, int u, const Word (&v)[W]) {
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const int32_t tk = ts - k > 0 ? ts - k : 0;
-        slots[k] = base[(uint64_t)(uint32_t)tk * stride];
-      }
+  for (int w = 0; w < W; ++w) stage[(w * B + u) * kStageRow + lane] = v[w];
+}
+
+// Flush the staged block to `dst` (the block's first word).  Must be called
+// by the whole wavefront; staged writes of all lanes are complete on entry.
+// The run is written in 8-byte chunks, consecutive lanes to consecutive
+// chunks (each store covers 512 contiguous bytes).  Chunk ci = lane + 64 s
+// holds lane ci / CHUNKS's steps from (ci % CHUNKS) * PER on; since 64 is a
+// multiple of CHUNKS, all chunks of a lane are one LDS base plus constant
+// offsets.
+template <class Word, int W, int B>
+__device__ __forceinline__ void flush_block(const Word *stage, int lane, Word *dst) {
+  constexpr int PER = 8 / (int)sizeof(Word);    // words per 8-byte chunk
+  constexpr int CHUNKS = B / PER;              // chunks per lane and group
+  static_assert(B % PER == 0 && kWave % CHUNKS == 0, "whole chunks per lane");
+  const Word *src = stage + (lane % CHUNKS) * PER * kStageRow + lane / CHUNKS;
+  uint2 *out = reinterpret_cast<uint2 *>(dst) + lane;
+#pragma unroll
+  for (int w = 0; w < W; ++w) {
+#pragma unroll
+    for (int s = 0; s < CHUNKS; ++s) {
+      Word v[PER];
+#pragma unroll
+      for (int k = 0; k < PER; ++k) v[k] = src[(w * B + k) * kStageRow + s * (kWave / CHUNKS)];
+      uint2 q;
+      __builtin_memcpy(&q, v, 8);
+      out[(w * CHUNKS + s) * kWave] = q;
+      // one chunk at a time: the flush runs while the sweep's registers are
+      // live, so it must not hold more than one chunk
+      __builtin_amdgcn_sched_barrier(0);
     }
-    return slots[d];
   }
+}
+
+// Decision words of one task as the traceback reads them.  Cell (i, j) (j
+// counted from the read's first base) lies in strip column jp = j + pad - 1,
+// i.e. lane lq = jp / K, column c = jp % K, group w = c / 8, and was computed
+// at step ts = i - 1 + lq.  The block of B steps holding ts for (lq, w) is
+// cached in LDS (`cache`: this lane's B entries); a refill is B contiguous
+// words.  `Decode(word, c)` extracts the nibble of column c.
+template <class Word, int K, int W, int B, class Decode>
+struct BlockTracer {
+  const Word *slot;   // the task's slot
+  Word *cache;        // B LDS entries, 16-byte aligned
+  int32_t lane0;      // first lane of the task in the wavefront
+  int32_t pad;
+  Decode decode;
+  int32_t lq = -1, w = -1, blk = -1;   // cached block
+  int32_t want_lq = 0, want_w = 0, want_blk = 0;
+
+  __device__ __forceinline__ bool get(int32_t i, int32_t j, uint32_t &nib) {
+    const uint32_t jp = (uint32_t)(j + pad - 1);
+    const int32_t lq_ = (int32_t)(jp / K);
+    const uint32_t c = jp - (uint32_t)lq_ * K;
+    const int32_t w_ = (int32_t)(c >> 3);
+    const int32_t ts = i - 1 + lq_;   // >= 0: i >= 1
+    const int32_t blk_ = ts / B;
+    if (lq_ != lq || w_ != w || blk_ != blk) {
+      want_lq = lq_;
+      want_w = w_;
+      want_blk = blk_;
+      return false;
+    }
+    nib = decode(cache[ts & (B - 1)], c);
+    return true;
+  }
+  __device__ __forceinline__ void fill() {
+    constexpr int V = B * (int)sizeof(Word) / 16;
+    const uint4 *src = reinterpret_cast<const uint4 *>(
+        slot + ((uint64_t)(want_blk * W + want_w) * kWave + (uint64_t)(lane0 + want_lq)) * B);
+    uint4 v[V];
+#pragma unroll
+    for (int k = 0; k < V; ++k) v[k] = src[k];
+#pragma unroll
+    for (int k = 0; k < V; ++k) reinterpret_cast<uint4 *>(cache)[k] = v[k];
+    lq = want_lq;
+    w = want_w;
+    blk = want_blk;
+  }
+};
+
+template <class Word, int K, int W, int B, class Decode>
+__device__ __forceinline__ BlockTracer<Word, K, W, B, Decode> make_tracer(
+    const Word *slot, Word *cache, int32_t lane0, int32_t pad, Decode dec) {
+  BlockTracer<Word, K, W, B, Decode> t{slot, cache, lane0, pad, dec};
+  return t;
+}
+
+// LDS of one wavefront shared by the sweep's staging buffer and the
+// traceback's block caches (never live at the same time).
+template <class Word, int W, int B>
+struct StageOrCache {
+  static constexpr int kStageWords = W * B * kStageRow;
+  static constexpr int kCacheWords = kWave * B;
+  static constexpr int kWords = kStageWords > kCacheWords ? kStageWords : kCacheWords;
 };
 
 // Resolve the task order of a work item: entry `tix` of the (segment of the)

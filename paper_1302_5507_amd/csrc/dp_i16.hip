@@ -66,12 +66,18 @@ __global__ __launch_bounds__(kWave) void dp_i16_kernel(DpParams p) {
   __shared__ int64_t s_task[kWave];
   __shared__ int32_t s_n[kWave], s_pad[kWave], s_end[kWave], s_score[kWave];
   __shared__ uint8_t s_st[kWave];
-  __shared__ uint2 s_tbc[kWave][4];   // traceback step caches
+  constexpr int B = step_block(K);   // sweep steps per stored block
+  // staging buffer of the sweep, or the traceback's block caches
+  __shared__ __align__(16) uint2 s_lds[StageOrCache<uint2, W, B>::kWords];
 
   // `defer` work items are swept into consecutive slots before one
   // traceback pass serves all their tasks, one lane per task
-  const int32_t defer = min(max(p.defer, 1), kWave / TPW);
-  uint32_t *const slots = p.scratch + (uint64_t)blockIdx.x * p.slot_dwords * (uint64_t)defer;
+  const int32_t defer = min(max(p.defer_dev ? *p.defer_dev : p.defer, 1), kWave / TPW);
+  const uint64_t slot_dwords = p.slot_dwords_dev ? *p.slot_dwords_dev : p.slot_dwords;
+  uint32_t *const slots = p.scratch + (p.scratch_off_dev ? *p.scratch_off_dev : 0) +
+                          (uint64_t)blockIdx.x * slot_dwords * (uint64_t)defer;
+  // window rows a slot can hold: (rows + L - 1) steps of W * 64 lanes
+  const int64_t slot_rows = (int64_t)(slot_dwords / (uint64_t)(W * kWave * 2)) - (L - 1);
   int32_t r = 0;   // slot of the current work item
   const int64_t n_tasks = p.task_count ? (int64_t)*p.task_count : p.n_tasks;
   const int32_t *const list = (p.task_list && p.task_off) ? p.task_list + *p.task_off : p.task_list;
@@ -103,7 +109,8 @@ __global__ __launch_bounds__(kWave) void dp_i16_kernel(DpParams p) {
         m[h] = p.ref_len[task[h]];
         rwo[h] = p.read_word_off[task[h]];
         rbo[h] = p.ref_base_off[task[h]];
-        if (n[h] < 1 || m[h] < 1 || n[h] > p.max_n || m[h] > p.max_m || n[h] > L * K)
+        if (n[h] < 1 || m[h] < 1 || n[h] > p.max_n || m[h] > p.max_m || n[h] > L * K ||
+            m[h] > slot_rows)
           st[h] = kTaskInvalidLen;
         else if (rwo[h] + (uint64_t)((n[h] + 15) >> 4) > p.read_words ||
                  rbo[h] + (uint64_t)m[h] > p.ref_words * 16)
@@ -176,7 +183,7 @@ __global__ __launch_bounds__(kWave) void dp_i16_kernel(DpParams p) {
 #pragma unroll
     for (int w = 0; w < W; ++w) { accA[w] = 0; accB[w] = 0; }
 
-    uint2 *sp = reinterpret_cast<uint2 *>(slots + (uint64_t)r * p.slot_dwords);
+    uint2 *sp = reinterpret_cast<uint2 *>(slots + (uint64_t)r * slot_dwords);
     for (int32_t t = 0; t < steps; ++t) {
       if ((t & 15) == 0) {
         twa = __builtin_amdgcn_alignbit(a1, a0, wsh0);
@@ -244,9 +251,19 @@ __global__ __launch_bounds__(kWave) void dp_i16_kernel(DpParams p) {
           if (i <= mg[1]) best1 = max(best1, k1);
         }
       }
+      {
+        uint2 v[W];
 #pragma unroll
-      for (int w = 0; w < W; ++w) sp[w * kWave + lane] = make_uint2(accA[w], accB[w]);
-      sp += W * kWave;
+        for (int w = 0; w < W; ++w) v[w] = make_uint2(accA[w], accB[w]);
+        const int u = t & (B - 1);
+        stage_step<uint2, W, B>(s_lds, lane, u, v);
+        if (u == B - 1 || t == steps - 1) {   // block complete (or last step)
+          __syncthreads();
+          flush_block<uint2, W, B>(s_lds, lane, sp);
+          sp += W * kWave * B;
+          __syncthreads();
+        }
+      }
       bnd = add16(bnd, c_nge);
       rge = add16(rge, c_ge);
     }
@@ -280,23 +297,15 @@ __global__ __launch_bounds__(kWave) void dp_i16_kernel(DpParams p) {
           p.score[tk] = s_score[lane] + tn * ge;
           p.ref_end[tk] = tend;
           p.status[tk] = p.ok_status;
-          const uint2 *base =
-              reinterpret_cast<const uint2 *>(slots + (uint64_t)rs * p.slot_dwords) + gq * L;
+          const uint2 *slot = reinterpret_cast<const uint2 *>(slots + (uint64_t)rs * slot_dwords);
           const uint32_t shA = 8u * (2 + h), shD = 8u * h;
-          StepCache<uint2> cache;
-          auto nib_at = [&](int32_t i, int32_t j) -> uint32_t {
-            const uint32_t jp = (uint32_t)(j + tpad - 1);
-            const uint32_t lq = jp / K;
-            const uint32_t c = jp - lq * K;
-            const int32_t ts = i - 1 + (int32_t)lq;
-            const uint32_t w = c >> 3;
-            const uint2 v = cache.get(s_tbc[lane], base + w * kWave + lq, ts, (int32_t)lq, (int32_t)w,
-                                      (uint32_t)(W * kWave));
-            const uint32_t b = (uint32_t)(c & 7);
-            return ((v.x >> (shA + b)) & 1u) << 3 | ((v.x >> (shD + b)) & 1u) << 2 |
-                   ((v.y >> (shA + b)) & 1u) << 1 | ((v.y >> (shD + b)) & 1u);
-          };
-          traceback_task(p, tk, tn, tend, nib_at);
+          auto tr = make_tracer<uint2, K, W, B>(
+              slot, s_lds + lane * B, gq * L, tpad, [shA, shD](uint2 v, uint32_t c) {
+                const uint32_t b = c & 7u;
+                return ((v.x >> (shA + b)) & 1u) << 3 | ((v.x >> (shD + b)) & 1u) << 2 |
+                       ((v.y >> (shA + b)) & 1u) << 1 | ((v.y >> (shD + b)) & 1u);
+              });
+          traceback_task(p, tk, tn, tend, (int32_t)slot_rows, tr);
         }
       }
     }
@@ -324,7 +333,9 @@ const Shape *shapes_i16(int *count) {
 }
 
 uint64_t slot_dwords_i16(Shape s, int32_t max_m) {
-  return (uint64_t(max_m) + uint64_t(s.lanes) - 1) * uint64_t((s.cells + 7) / 8) * kWave * 2;
+  const uint64_t B = uint64_t(step_block(s.cells));
+  const uint64_t steps = (uint64_t(max_m) + uint64_t(s.lanes) - 1 + B - 1) / B * B;
+  return steps * uint64_t((s.cells + 7) / 8) * kWave * 2;
 }
 
 hipError_t launch_dp_i16(Shape s, int grid, hipStream_t stream, const DpParams &p) {

@@ -52,12 +52,18 @@ __global__ __launch_bounds__(kWave) void dp_i32_kernel(DpParams p) {
   __shared__ int64_t s_task[kWave];
   __shared__ int32_t s_n[kWave], s_pad[kWave], s_end[kWave], s_score[kWave];
   __shared__ uint8_t s_st[kWave];
-  __shared__ uint32_t s_tbc[kWave][4];   // traceback step caches
+  constexpr int B = step_block(K);   // sweep steps per stored block
+  // staging buffer of the sweep, or the traceback's block caches
+  __shared__ __align__(16) uint32_t s_lds[StageOrCache<uint32_t, W, B>::kWords];
 
   // `defer` work items are swept into consecutive slots before one
   // traceback pass serves all their tasks, one lane per task
-  const int32_t defer = min(max(p.defer, 1), kWave / G);
-  uint32_t *const slots = p.scratch + (uint64_t)blockIdx.x * p.slot_dwords * (uint64_t)defer;
+  const int32_t defer = min(max(p.defer_dev ? *p.defer_dev : p.defer, 1), kWave / G);
+  const uint64_t slot_dwords = p.slot_dwords_dev ? *p.slot_dwords_dev : p.slot_dwords;
+  uint32_t *const slots = p.scratch + (p.scratch_off_dev ? *p.scratch_off_dev : 0) +
+                          (uint64_t)blockIdx.x * slot_dwords * (uint64_t)defer;
+  // window rows a slot can hold: (rows + L - 1) steps of W * 64 lanes
+  const int64_t slot_rows = (int64_t)(slot_dwords / (uint64_t)(W * kWave * 1)) - (L - 1);
   int32_t r = 0;   // slot of the current work item
   const int64_t n_tasks = p.task_count ? (int64_t)*p.task_count : p.n_tasks;
   const int32_t *const list = (p.task_list && p.task_off) ? p.task_list + *p.task_off : p.task_list;
@@ -77,7 +83,7 @@ __global__ __launch_bounds__(kWave) void dp_i32_kernel(DpParams p) {
       m = p.ref_len[task];
       rwo = p.read_word_off[task];
       rbo = p.ref_base_off[task];
-      if (n < 1 || m < 1 || n > p.max_n || m > p.max_m || n > L * K)
+      if (n < 1 || m < 1 || n > p.max_n || m > p.max_m || n > L * K || m > slot_rows)
         st = kTaskInvalidLen;
       else if (rwo + (uint64_t)((n + 15) >> 4) > p.read_words || rbo + (uint64_t)m > p.ref_words * 16)
         st = kTaskInvalidOffset;
@@ -136,7 +142,7 @@ __global__ __launch_bounds__(kWave) void dp_i32_kernel(DpParams p) {
 #pragma unroll
     for (int w = 0; w < W; ++w) acc[w] = 0;
 
-    uint32_t *sp = slots + (uint64_t)r * p.slot_dwords;
+    uint32_t *sp = slots + (uint64_t)r * slot_dwords;
     for (int32_t t = 0; t < steps; ++t) {
       if ((t & 15) == 0) {
         tw = __builtin_amdgcn_alignbit(tn1, tn0, wsh);
@@ -189,9 +195,16 @@ __global__ __launch_bounds__(kWave) void dp_i32_kernel(DpParams p) {
         const int32_t v = H[K - 1] + rge;
         if (last && v > best) { best = v; endi = i; }
       }
-#pragma unroll
-      for (int w = 0; w < W; ++w) sp[w * kWave + lane] = acc[w];
-      sp += W * kWave;
+      {
+        const int u = t & (B - 1);
+        stage_step<uint32_t, W, B>(s_lds, lane, u, acc);
+        if (u == B - 1 || t == steps - 1) {   // block complete (or last step)
+          __syncthreads();
+          flush_block<uint32_t, W, B>(s_lds, lane, sp);
+          sp += W * kWave * B;
+          __syncthreads();
+        }
+      }
       bnd -= ge;
       rge += ge;
     }
@@ -216,19 +229,11 @@ __global__ __launch_bounds__(kWave) void dp_i32_kernel(DpParams p) {
           p.ref_end[tk] = tend;
           p.status[tk] = p.ok_status;
           const int rs = lane / G, gq = lane % G;
-          const uint32_t *base = slots + (uint64_t)rs * p.slot_dwords + gq * L;
-          StepCache<uint32_t> cache;
-          auto nib_at = [&](int32_t i, int32_t j) -> uint32_t {
-            const uint32_t jp = (uint32_t)(j + tpad - 1);
-            const uint32_t lq = jp / K;
-            const uint32_t c = jp - lq * K;
-            const int32_t ts = i - 1 + (int32_t)lq;
-            const uint32_t w = c >> 3;
-            const uint32_t wd = cache.get(s_tbc[lane], base + w * kWave + lq, ts, (int32_t)lq, (int32_t)w,
-                                          (uint32_t)(W * kWave));
-            return (wd >> (4 * (7 - (c & 7)))) & 15u;
-          };
-          traceback_task(p, tk, tn, tend, nib_at);
+          const uint32_t *slot = slots + (uint64_t)rs * slot_dwords;
+          auto tr = make_tracer<uint32_t, K, W, B>(
+              slot, s_lds + lane * B, gq * L, tpad,
+              [](uint32_t wd, uint32_t c) { return (wd >> (4 * (7 - (c & 7)))) & 15u; });
+          traceback_task(p, tk, tn, tend, (int32_t)slot_rows, tr);
         }
       }
     }
@@ -250,7 +255,9 @@ static const Shape kShapesI32[] = {
 };
 
 uint64_t slot_dwords_i32(Shape s, int32_t max_m) {
-  return (uint64_t(max_m) + uint64_t(s.lanes) - 1) * uint64_t((s.cells + 7) / 8) * kWave;
+  const uint64_t B = uint64_t(step_block(s.cells));
+  const uint64_t steps = (uint64_t(max_m) + uint64_t(s.lanes) - 1 + B - 1) / B * B;
+  return steps * uint64_t((s.cells + 7) / 8) * kWave;
 }
 
 const Shape *shapes_i32(int *count) {

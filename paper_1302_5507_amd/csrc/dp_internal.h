@@ -42,6 +42,12 @@ struct DpParams {
   uint32_t *scratch;
   uint64_t slot_dwords;
   int32_t defer;
+  // Device-planned launch (batched form): when non-null, the deferral, the
+  // slot size and the offset (dwords) of this kernel's scratch region are
+  // read from here instead.
+  const int32_t *defer_dev;
+  const uint64_t *slot_dwords_dev;
+  const uint64_t *scratch_off_dev;
   // Optional task order (nullptr: identity) and its length; work items are
   // groups of (tasks per wave) consecutive entries of that order.
   const int32_t *task_list;
@@ -55,6 +61,13 @@ struct DpParams {
   // when the int32 kernel re-runs tasks outside the int16 range).
   uint8_t ok_status;
 };
+
+// Decision words are stored in blocks of `step_block(K)` sweep steps: within
+// a block each lane's words for consecutive steps are contiguous, so the
+// traceback fetches one lane's block in one piece.  Eight steps while a lane
+// has at most two column groups (W = ceil(K/8) words per step), else four
+// (bounds the LDS staging buffer).  Slots hold whole blocks.
+__host__ __device__ constexpr int step_block(int K) { return (K + 7) / 8 <= 2 ? 8 : 4; }
 
 // A kernel shape: L lanes cooperate on one task, each owning K read columns.
 struct Shape {
