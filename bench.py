@@ -31,6 +31,38 @@ OPS_PER_CELL = 14            # 10 score operations + 4 decision comparisons per 
 PEAK_INT32_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12   # CUs x SIMDs x lanes x clock = 39.3 T lane-ops/s
 PEAK_INT16_TOPS = 2 * PEAK_INT32_TOPS            # packed 2 x int16 per lane
 
+# HBM traffic of the dominant kernel per launch, from two rocprofv3 --pmc
+# runs (FETCH_SIZE, WRITE_SIZE; KiB per dispatch) scaled by what the same
+# counters read for a plain 1 GiB device copy (FETCH x 2.000, WRITE x 1.000).
+# Keyed by (workload, form); valid only for the kernel sources fingerprinted
+# (any change to them makes `traffic` null until the counters are re-taken).
+KERNEL_SOURCES = ("api.cpp", "batch.h", "batch.hip", "dp_device.h", "dp_i16.hip", "dp_i32.hip",
+                  "dp_internal.h")
+TRAFFIC = {
+    ("config2", "plain"): {"fingerprint": "182584a1f026447a", "kernel": "dp_i32_kernel<8,13>",
+                           "fetch_kib": 1848245, "write_kib": 16641869,
+                           "fetch_scale": 2.000, "write_scale": 1.000},
+}
+
+
+def kernel_fingerprint() -> str:
+    import hashlib
+    csrc = os.path.join(ROOT, "paper_1302_5507_amd", "csrc")
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(f.encode())
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_bytes(workload: str, form: str):
+    t = TRAFFIC.get((workload, form))
+    if t is None or t["fingerprint"] != kernel_fingerprint():
+        return None
+    return int(round((t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"]) * 1024))
+
+
 WORKLOADS = {
     "config2": ("mate-rescue: 1,000,000 reads x 100 bp vs 250 bp windows from a 1 Mbp random "
                 "genome (2% subs, 0.5% indels, 10% random reads)", "config2", "plain"),
@@ -240,7 +272,7 @@ def main():
             "peak": round(peak, 1),
             "unit": "TOP/s",
             "frac": round(achieved / peak, 4),
-            "traffic": None,
+            "traffic": traffic_bytes(args.workload, main_form),
             "ops_per_cell": OPS_PER_CELL,
             "kernel_ms": round(k, 3),
         },

@@ -58,7 +58,7 @@ __device__ __forceinline__ int32_t wave_max(int32_t v) {
 // update is select-based so that lanes tracing different tasks stay
 // converged.
 template <class Tracer>
-__device__ void traceback_task(const DpParams &p, int64_t task, int32_t n, int32_t end,
+__device__ __forceinline__ void traceback_task(const DpParams &p, int64_t task, int32_t n, int32_t end,
                                int32_t slot_rows, Tracer &tr) {
   uint32_t *row = p.cigar + task * (int64_t)p.cigar_stride;
   int32_t wpos = p.cigar_stride;  // runs are written backward from the row end
@@ -201,11 +201,9 @@ struct BlockTracer {
     constexpr int V = B * (int)sizeof(Word) / 16;
     const uint4 *src = reinterpret_cast<const uint4 *>(
         slot + ((uint64_t)(want_blk * W + want_w) * kWave + (uint64_t)(lane0 + want_lq)) * B);
-    uint4 v[V];
+    uint4 *dst = reinterpret_cast<uint4 *>(cache);
 #pragma unroll
-    for (int k = 0; k < V; ++k) v[k] = src[k];
-#pragma unroll
-    for (int k = 0; k < V; ++k) reinterpret_cast<uint4 *>(cache)[k] = v[k];
+    for (int k = 0; k < V; ++k) dst[k] = src[k];
     lq = want_lq;
     w = want_w;
     blk = want_blk;
