@@ -250,13 +250,18 @@ typedef struct {
   const int32_t *ref_len;
   int32_t n_tasks;
   soap_dp_host_result out;
-  uint64_t arrival_ns;            /* scheduled arrival, soap_dp_now_ns() clock */
+  uint64_t arrival_ns;            /* arrival time on the soap_dp_now_ns() clock: the
+                                     request is admitted no earlier (0: on submission);
+                                     requests are admitted in submission order */
 } soap_dp_request;
 
 typedef struct {
   uint64_t submitted, completed, rejected, batches;
   uint64_t tasks, cells;
-  double device_busy_s;           /* union of batch intervals on the device */
+  double device_busy_s;   /* sum over batches of upload start .. results copied
+                             (slots overlap, so this can exceed wall time) */
+  double host_launch_s;   /* dispatcher time merging and enqueueing batches */
+  double host_retire_s;   /* dispatcher time handing results to requests */
 } soap_dp_server_stats;
 
 /* Monotonic clock used for arrival and completion times (nanoseconds). */

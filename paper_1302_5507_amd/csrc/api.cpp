@@ -11,6 +11,7 @@
 #include <iterator>
 #include <new>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "../../include/soap_dp.h"
@@ -83,6 +84,9 @@ struct soap_dp_ctx {
   hipEvent_t fork_event = nullptr;
   std::vector<GraphEntry> graphs;
   uint64_t epoch = 1;   // bumped whenever buffers or shapes change
+  // occupancy per kernel shape (key prec << 16 | lanes << 8 | cells), queried
+  // once: launch planning runs on every call
+  mutable std::unordered_map<uint32_t, int> occupancy;
   uint64_t use_clock = 0;
   bool use_graphs = true;
 };
@@ -133,9 +137,14 @@ bool shape_compiled(int prec, Shape s) {
   return false;
 }
 
-int occupancy(int prec, Shape s) {
-  const int o = prec == 16 ? occupancy_dp_i16(s) : occupancy_dp_i32(s);
-  return o < 1 ? 1 : o;
+int occupancy(const soap_dp_ctx *ctx, int prec, Shape s) {
+  const uint32_t key = uint32_t(prec) << 16 | uint32_t(s.lanes) << 8 | uint32_t(s.cells);
+  auto it = ctx->occupancy.find(key);
+  if (it != ctx->occupancy.end()) return it->second;
+  int o = prec == 16 ? occupancy_dp_i16(s) : occupancy_dp_i32(s);
+  o = o < 1 ? 1 : o;
+  ctx->occupancy.emplace(key, o);
+  return o;
 }
 
 uint64_t slot_dwords(int prec, Shape s, int32_t max_m) {
@@ -164,7 +173,7 @@ Shape plain_shape(int32_t max_n, int32_t max_m) {
 int grid_for(const soap_dp_ctx *ctx, int prec, Shape s, int64_t n_tasks, int32_t max_m) {
   const int64_t per_wave = (prec == 16 ? 2 : 1) * kWave / s.lanes;
   const int64_t items = (n_tasks + per_wave - 1) / per_wave;
-  int64_t grid = int64_t(ctx->cu_count) * occupancy(prec, s);
+  int64_t grid = int64_t(ctx->cu_count) * occupancy(ctx, prec, s);
   const uint64_t slot_bytes = slot_dwords(prec, s, max_m) * 4;
   grid = std::min<int64_t>(grid, std::max<int64_t>(int64_t(kScratchCap / slot_bytes), 1));
   grid = std::min<int64_t>(grid, std::max<int64_t>(items, 1));
@@ -695,7 +704,10 @@ int autotune(soap_dp_ctx *ctx, std::vector<double> &gcups) {
   for (size_t k = 0; k < ctx->classes.size() && rc == SOAP_DP_OK; ++k) {
     ClassSpec &c = ctx->classes[k];
     const int32_t n = c.cap, m = n + 160;
-    const int64_t tasks = std::max<int64_t>(2048, std::min<int64_t>(262144, int64_t(6e8 / (double(n) * m))));
+    // about 3e9 cells, and never fewer than 65,536 tasks: enough work items
+    // that the persistent grid runs many rounds, as it does on real batches
+    const int64_t tasks =
+        std::max<int64_t>(65536, std::min<int64_t>(1 << 20, int64_t(3e9 / (double(n) * m))));
     TuneData d;
     if (!make_tune_data(d, n, tasks)) { rc = SOAP_DP_ENOMEM; break; }
     int cnt = 0;

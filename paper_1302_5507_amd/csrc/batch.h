@@ -53,8 +53,11 @@ __host__ __device__ inline uint64_t round64(uint64_t dwords) { return (dwords + 
 hipError_t launch_bucketing(const DpParams &p, const ClassTable &ct, const BucketBuffers &b,
                             hipStream_t stream);
 hipError_t launch_zero(int32_t *a, int n, hipStream_t stream);
-// Pack the CIGAR rows of tasks [0, n) back to back (at most out_cap words).
-hipError_t launch_compact_cigar(const uint32_t *cigar, int32_t stride, const int32_t *cigar_len,
-                                int32_t n, uint32_t *out, int64_t out_cap, hipStream_t stream);
+// First CIGAR words of every task, gathered densely for one small copy back
+// to the host: head[t * kCigarHeadWords + k] = word k of task t's row for
+// k < cigar_len[t], else 0; tasks [0, n).
+constexpr int kCigarHeadWords = 16;
+hipError_t launch_gather_cigar_head(const uint32_t *cigar, int32_t stride, const int32_t *cigar_len,
+                                    int32_t n, uint32_t *head, hipStream_t stream);
 
 }  // namespace soapdp

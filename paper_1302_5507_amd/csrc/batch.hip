@@ -141,40 +141,26 @@ __global__ __launch_bounds__(kBlock) void scatter_kernel(const uint8_t *task_cla
   if (t < n_tasks && k != 0xff) task_list[s_base[k] + rank] = (int32_t)t;
 }
 
-// Pack the CIGARs of tasks [0, n) contiguously: task t's runs go to
-// out[off(t)], off = exclusive prefix sum of cigar_len.  One workgroup; each
-// thread owns a contiguous range of tasks.
-__global__ __launch_bounds__(1024) void compact_cigar_kernel(const uint32_t *cigar, int32_t stride,
-                                                             const int32_t *cigar_len, int32_t n,
-                                                             uint32_t *out, int64_t out_cap) {
-  __shared__ int64_t s_sum[1024];
-  const int tid = threadIdx.x;
-  const int32_t per = (n + 1023) / 1024;
-  const int32_t a = min(n, tid * per), b = min(n, a + per);
-  int64_t sum = 0;
-  for (int32_t t = a; t < b; ++t) sum += max(cigar_len[t], 0);
-  s_sum[tid] = sum;
-  __syncthreads();
-  for (int o = 1; o < 1024; o <<= 1) {   // inclusive scan
-    const int64_t v = tid >= o ? s_sum[tid - o] : 0;
-    __syncthreads();
-    s_sum[tid] += v;
-    __syncthreads();
-  }
-  int64_t off = s_sum[tid] - sum;
-  for (int32_t t = a; t < b; ++t) {
-    const int32_t len = min(max(cigar_len[t], 0), stride);
-    for (int32_t k = 0; k < len && off + k < out_cap; ++k) out[off + k] = cigar[(int64_t)t * stride + k];
-    off += len;
-  }
+__global__ __launch_bounds__(kBlock) void gather_cigar_head_kernel(const uint32_t *cigar,
+                                                                   int32_t stride,
+                                                                   const int32_t *cigar_len,
+                                                                   int32_t n, uint32_t *head) {
+  const int64_t x = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t t = x / kCigarHeadWords;
+  const int32_t k = (int32_t)(x % kCigarHeadWords);
+  if (t >= n) return;
+  const int32_t len = min(cigar_len[t], stride);
+  head[x] = k < len ? cigar[t * stride + k] : 0u;
 }
 
 }  // namespace
 
-hipError_t launch_compact_cigar(const uint32_t *cigar, int32_t stride, const int32_t *cigar_len,
-                                int32_t n, uint32_t *out, int64_t out_cap, hipStream_t stream) {
-  hipLaunchKernelGGL(compact_cigar_kernel, dim3(1), dim3(1024), 0, stream, cigar, stride, cigar_len,
-                     n, out, out_cap);
+hipError_t launch_gather_cigar_head(const uint32_t *cigar, int32_t stride, const int32_t *cigar_len,
+                                    int32_t n, uint32_t *head, hipStream_t stream) {
+  if (n <= 0) return hipSuccess;
+  const int64_t threads = int64_t(n) * kCigarHeadWords;
+  hipLaunchKernelGGL(gather_cigar_head_kernel, dim3((uint32_t)((threads + kBlock - 1) / kBlock)),
+                     dim3(kBlock), 0, stream, cigar, stride, cigar_len, n, head);
   return hipGetLastError();
 }
 

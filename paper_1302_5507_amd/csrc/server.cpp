@@ -1,16 +1,18 @@
 // Continuous-batching server over the batched form (declared in
-// include/soap_dp.h).  One dispatcher thread owns every HIP call: it
-// retires finished batches (copying each request's slice of the results to
-// the caller's buffers) and, for every free slot, merges the queued
-// requests in arrival order into one batch, uploads it, enqueues the
-// batched alignment and the result copies on the slot's stream and records
-// an event.  Slots run concurrently, so batches overlap on the device.
+// include/soap_dp.h).  Every slot has its own worker thread, context,
+// stream and buffers.  A worker takes the requests that have arrived, in
+// submission order, up to its slot's capacity, merges them into one batch,
+// uploads it, enqueues the batched alignment and the result copies on its
+// stream, waits for them and hands each request its slice of the results.
+// Slots work concurrently, so batches overlap on the device and the host
+// work of one slot (staging, result hand-off) overlaps the others.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <atomic>
 #include <chrono>
 #include <condition_variable>
+#include <cstdint>
 #include <cstring>
 #include <deque>
 #include <memory>
@@ -25,9 +27,6 @@
 
 namespace {
 
-// Words of packed CIGAR copied back with every batch, per task; a batch
-// whose alignments need more fetches the rest when it retires.
-constexpr int32_t kCompactWordsPerTask = 8;
 
 uint64_t now_ns() {
   return uint64_t(std::chrono::duration_cast<std::chrono::nanoseconds>(
@@ -73,14 +72,15 @@ struct Slot {
   int32_t *d_rl = nullptr, *d_ml = nullptr;
   int32_t *d_i32 = nullptr;   // score | begin | end | cigar_len
   uint32_t *d_cigar = nullptr;
-  uint32_t *d_packed = nullptr;   // CIGARs packed back to back
+  uint32_t *d_head = nullptr;     // first CIGAR words of every task (dense)
   uint8_t *d_status = nullptr;
   // pinned host staging
   uint32_t *h_reads = nullptr;
   uint64_t *h_rwo = nullptr, *h_rbo = nullptr;
   int32_t *h_rl = nullptr, *h_ml = nullptr;
   int32_t *h_i32 = nullptr;
-  uint32_t *h_cigar = nullptr;    // packed CIGARs
+  uint32_t *h_head = nullptr;     // copy of d_head
+  uint32_t *h_rest = nullptr;     // rest of the CIGARs longer than the head
   uint8_t *h_status = nullptr;
   // batch in flight
   bool busy = false;
@@ -101,7 +101,7 @@ struct soap_dp_server {
   std::unordered_map<uint64_t, TicketState> tickets;
   uint64_t next_ticket = 1;
   bool stopping = false;
-  std::thread worker;
+  std::vector<std::thread> workers;
   soap_dp_server_stats stats{};
   int fatal = SOAP_DP_OK;
 };
@@ -114,10 +114,10 @@ void free_slot(Slot &s) {
   if (s.start) (void)hipEventDestroy(s.start);
   if (s.done) (void)hipEventDestroy(s.done);
   for (void *p : {(void *)s.d_reads, (void *)s.d_rwo, (void *)s.d_rbo, (void *)s.d_rl, (void *)s.d_ml,
-                  (void *)s.d_i32, (void *)s.d_cigar, (void *)s.d_status, (void *)s.d_packed})
+                  (void *)s.d_i32, (void *)s.d_cigar, (void *)s.d_status, (void *)s.d_head})
     if (p) (void)hipFree(p);
   for (void *p : {(void *)s.h_reads, (void *)s.h_rwo, (void *)s.h_rbo, (void *)s.h_rl, (void *)s.h_ml,
-                  (void *)s.h_i32, (void *)s.h_cigar, (void *)s.h_status})
+                  (void *)s.h_i32, (void *)s.h_head, (void *)s.h_rest, (void *)s.h_status})
     if (p) (void)hipHostFree(p);
   s = Slot{};
 }
@@ -133,10 +133,13 @@ int init_slot(soap_dp_server *srv, Slot &s) {
     return SOAP_DP_EHIP;
   const bool ok = dalloc(&s.d_reads, Wd) && dalloc(&s.d_rwo, T) && dalloc(&s.d_rbo, T) &&
                   dalloc(&s.d_rl, T) && dalloc(&s.d_ml, T) && dalloc(&s.d_i32, 4 * T) &&
-                  dalloc(&s.d_cigar, T * S) && dalloc(&s.d_status, T) && dalloc(&s.d_packed, T * S) &&
+                  dalloc(&s.d_cigar, T * S) && dalloc(&s.d_status, T) &&
+                  dalloc(&s.d_head, T * soapdp::kCigarHeadWords) &&
                   halloc(&s.h_reads, Wd) && halloc(&s.h_rwo, T) && halloc(&s.h_rbo, T) &&
                   halloc(&s.h_rl, T) && halloc(&s.h_ml, T) && halloc(&s.h_i32, 4 * T) &&
-                  halloc(&s.h_cigar, T * S) && halloc(&s.h_status, T);
+                  halloc(&s.h_head, T * soapdp::kCigarHeadWords) &&
+                  halloc(&s.h_rest, T * soapdp::kCigarHeadWords) &&
+                  halloc(&s.h_status, T);
   if (!ok) {
     (void)hipGetLastError();
     return SOAP_DP_ENOMEM;
@@ -144,21 +147,32 @@ int init_slot(soap_dp_server *srv, Slot &s) {
   return soap_dp_reserve(s.ctx, c.max_tasks, c.max_n, c.max_m, SOAP_DP_BATCHED);
 }
 
-// Finished batch: copy each request's slice to its caller buffers.
+// Finished batch: copy each request's slice to its caller buffers.  CIGARs
+// come from the dense head copy; the rest of the rare longer rows is
+// fetched with one queued copy per row and a single wait.
 void retire(soap_dp_server *srv, Slot &s, uint64_t t_done) {
   const int32_t T = srv->cfg.max_tasks;
   const int32_t S = srv->stride;
-  (void)S;
+  constexpr int32_t H = soapdp::kCigarHeadWords;
   float ms = 0;
   (void)hipEventElapsedTime(&ms, s.start, s.done);
+  // rows longer than the head: their rest packed into h_rest (T * H words);
+  // in the unlikely case that it fills up, the remaining rows are fetched
+  // one by one below
+  bool fetched = true;
+  std::unordered_map<int32_t, int64_t> rest_at;   // task -> offset in h_rest
+  int64_t rest = 0;
+  for (int32_t t = 0; t < s.tasks; ++t) {
+    const int32_t len = std::min(s.h_i32[3 * T + t], S);
+    if (len <= H || rest + (len - H) > int64_t(T) * H) continue;
+    fetched = fetched && hipMemcpyAsync(s.h_rest + rest, s.d_cigar + int64_t(t) * S + H,
+                                        size_t(len - H) * 4, hipMemcpyDeviceToHost,
+                                        s.stream) == hipSuccess;
+    rest_at.emplace(t, rest);
+    rest += len - H;
+  }
+  if (!rest_at.empty()) fetched = fetched && hipStreamSynchronize(s.stream) == hipSuccess;
   std::vector<std::pair<uint64_t, int>> finished;
-  // packed CIGARs: fetch what did not fit the words copied with the batch
-  int64_t total = 0;
-  for (int32_t t = 0; t < s.tasks; ++t) total += std::max(s.h_i32[3 * T + t], 0);
-  const int64_t have = int64_t(s.tasks) * kCompactWordsPerTask;
-  if (total > have)
-    (void)hipMemcpy(s.h_cigar + have, s.d_packed + have, size_t(total - have) * 4, hipMemcpyDeviceToHost);
-  int64_t off = 0;
   for (size_t r = 0; r < s.reqs.size(); ++r) {
     Request &q = *s.reqs[r];
     const int32_t f = s.first_task[r], n = q.n_tasks;
@@ -169,11 +183,27 @@ void retire(soap_dp_server *srv, Slot &s, uint64_t t_done) {
     std::memcpy(o.cigar_len, s.h_i32 + 3 * T + f, size_t(n) * 4);
     std::memcpy(o.status, s.h_status + f, size_t(n));
     int64_t words = 0;
-    for (int32_t t = 0; t < n; ++t) words += std::max(o.cigar_len[t], 0);
-    const int64_t fit = std::min(words, o.cigar_capacity);
-    std::memcpy(o.cigar, s.h_cigar + off, size_t(std::max<int64_t>(fit, 0)) * 4);
-    off += words;
-    finished.emplace_back(q.ticket, words > o.cigar_capacity ? SOAP_DP_E2BIG : SOAP_DP_OK);
+    int rc = SOAP_DP_OK;
+    for (int32_t t = 0; t < n; ++t) {
+      const int32_t len = std::min(std::max(o.cigar_len[t], 0), S);
+      if (words + len > o.cigar_capacity) {
+        rc = SOAP_DP_E2BIG;   // keeps counting; writes nothing past the buffer
+      } else {
+        std::memcpy(o.cigar + words, s.h_head + int64_t(f + t) * H, size_t(std::min(len, H)) * 4);
+        if (len > H) {
+          auto it = rest_at.find(f + t);
+          uint32_t *dst = o.cigar + words + H;
+          if (it != rest_at.end() && fetched)
+            std::memcpy(dst, s.h_rest + it->second, size_t(len - H) * 4);
+          else if (it != rest_at.end() ||
+                   hipMemcpy(dst, s.d_cigar + int64_t(f + t) * S + H, size_t(len - H) * 4,
+                             hipMemcpyDeviceToHost) != hipSuccess)
+            rc = SOAP_DP_EHIP;
+        }
+      }
+      words += len;
+    }
+    finished.emplace_back(q.ticket, rc);
   }
   {
     std::lock_guard<std::mutex> lk(srv->mu);
@@ -253,13 +283,13 @@ int launch(soap_dp_server *srv, Slot &s, std::vector<std::unique_ptr<Request>> &
   out.status = s.d_status;
   const int rc = soap_dp_align_batch(s.ctx, &in, &c.scoring, &out, st, SOAP_DP_BATCHED);
   if (rc) return rc;
-  ok = soapdp::launch_compact_cigar(s.d_cigar, S, s.d_i32 + 3 * T, nt, s.d_packed, int64_t(T) * S, st) == hipSuccess;
+  ok = soapdp::launch_gather_cigar_head(s.d_cigar, S, s.d_i32 + 3 * T, nt, s.d_head, st) == hipSuccess;
   for (int a = 0; ok && a < 4; ++a)
     ok = hipMemcpyAsync(s.h_i32 + size_t(a) * T, s.d_i32 + size_t(a) * T, size_t(nt) * 4,
                         hipMemcpyDeviceToHost, st) == hipSuccess;
   ok = ok &&
        hipMemcpyAsync(s.h_status, s.d_status, size_t(nt), hipMemcpyDeviceToHost, st) == hipSuccess &&
-       hipMemcpyAsync(s.h_cigar, s.d_packed, size_t(nt) * kCompactWordsPerTask * 4,
+       hipMemcpyAsync(s.h_head, s.d_head, size_t(nt) * soapdp::kCigarHeadWords * 4,
                       hipMemcpyDeviceToHost, st) == hipSuccess &&
        hipEventRecord(s.done, st) == hipSuccess;
   if (!ok) return SOAP_DP_EHIP;
@@ -267,70 +297,90 @@ int launch(soap_dp_server *srv, Slot &s, std::vector<std::unique_ptr<Request>> &
   return SOAP_DP_OK;
 }
 
-void dispatcher(soap_dp_server *srv) {
-  (void)hipSetDevice(srv->cfg.device_ordinal);
+// Fail a slot's requests with `rc` (its batch could not be run).
+void fail_batch(soap_dp_server *srv, Slot &s, int rc) {
+  std::lock_guard<std::mutex> lk(srv->mu);
+  srv->fatal = rc;
+  for (auto &q : s.reqs) {
+    TicketState &ts = srv->tickets[q->ticket];
+    ts.done = true;
+    ts.rc = rc;
+    ts.done_ns = now_ns();
+  }
+  srv->stats.completed += s.reqs.size();
+  s.reqs.clear();
+  s.first_task.clear();
+  s.tasks = 0;
+  s.busy = false;
+  srv->cv_done.notify_all();
+}
+
+// Take the arrived requests at the queue's head that fit one batch (caller
+// holds the lock).
+void take_arrived(soap_dp_server *srv, std::vector<std::unique_ptr<Request>> &take) {
   const auto &c = srv->cfg;
+  int32_t nt = 0;
+  uint64_t nw = 0;
+  const uint64_t now = now_ns();
+  while (!srv->queue.empty()) {
+    Request &q = *srv->queue.front();
+    if (q.arrival_ns > now) break;   // not arrived yet
+    if (nt + q.n_tasks > c.max_tasks || nw + q.reads.size() > uint64_t(c.max_read_words)) break;
+    nt += q.n_tasks;
+    nw += q.reads.size();
+    take.push_back(std::move(srv->queue.front()));
+    srv->queue.pop_front();
+  }
+}
+
+void slot_worker(soap_dp_server *srv, size_t k) {
+  (void)hipSetDevice(srv->cfg.device_ordinal);
+  Slot &s = srv->slots[k];
   std::vector<std::unique_ptr<Request>> take;
+  constexpr uint64_t kSpin = 200000;   // ns: poll closely when an arrival is this near
   for (;;) {
-    bool progressed = false;
-    // retire finished batches
-    for (auto &s : srv->slots) {
-      if (!s.busy) continue;
-      const hipError_t q = hipEventQuery(s.done);
-      if (q == hipSuccess) {
-        retire(srv, s, now_ns());
-        progressed = true;
-      } else if (q != hipErrorNotReady) {
-        std::lock_guard<std::mutex> lk(srv->mu);
-        srv->fatal = SOAP_DP_EHIP;
-      }
-    }
-    // fill free slots
-    bool all_idle = true;
-    for (auto &s : srv->slots) {
-      if (s.busy) { all_idle = false; continue; }
-      {
-        std::lock_guard<std::mutex> lk(srv->mu);
-        int32_t nt = 0;
-        uint64_t nw = 0;
-        while (!srv->queue.empty()) {
-          Request &q = *srv->queue.front();
-          if (nt + q.n_tasks > c.max_tasks || nw + q.reads.size() > uint64_t(c.max_read_words)) break;
-          nt += q.n_tasks;
-          nw += q.reads.size();
-          take.push_back(std::move(srv->queue.front()));
-          srv->queue.pop_front();
+    {
+      std::unique_lock<std::mutex> lk(srv->mu);
+      for (;;) {
+        if (srv->queue.empty()) {
+          if (srv->stopping) return;
+          srv->cv_work.wait_for(lk, std::chrono::milliseconds(5));
+          continue;
+        }
+        const uint64_t now = now_ns(), next = srv->queue.front()->arrival_ns;
+        if (next <= now) break;
+        if (next > now + kSpin) {
+          srv->cv_work.wait_for(lk, std::chrono::nanoseconds(next - now - kSpin / 2));
+        } else {
+          lk.unlock();
+          std::this_thread::yield();
+          lk.lock();
         }
       }
-      if (take.empty()) continue;
-      const int rc = launch(srv, s, take);
-      if (rc) {
-        std::lock_guard<std::mutex> lk(srv->mu);
-        srv->fatal = rc;
-        for (auto &q : s.reqs) {
-          TicketState &ts = srv->tickets[q->ticket];
-          ts.done = true;
-          ts.rc = rc;
-          ts.done_ns = now_ns();
-        }
-        s.reqs.clear();
-        s.first_task.clear();
-        s.busy = false;
-        srv->cv_done.notify_all();
-        continue;
-      }
-      all_idle = false;
-      progressed = true;
+      take_arrived(srv, take);
     }
-    std::unique_lock<std::mutex> lk(srv->mu);
-    if (srv->stopping && srv->queue.empty() && all_idle) break;
-    if (!progressed) {
-      if (all_idle && srv->queue.empty())
-        srv->cv_work.wait_for(lk, std::chrono::milliseconds(5));
-      else {
-        lk.unlock();
-        std::this_thread::sleep_for(std::chrono::microseconds(20));
-      }
+    if (take.empty()) continue;
+    uint64_t t0 = now_ns();
+    const int rc = launch(srv, s, take);
+    {
+      std::lock_guard<std::mutex> lk(srv->mu);
+      srv->stats.host_launch_s += double(now_ns() - t0) * 1e-9;
+    }
+    if (rc) {
+      fail_batch(srv, s, rc);
+      continue;
+    }
+    // another request may have arrived meanwhile: let a free slot take it
+    srv->cv_work.notify_one();
+    if (hipEventSynchronize(s.done) != hipSuccess) {
+      fail_batch(srv, s, SOAP_DP_EHIP);
+      continue;
+    }
+    t0 = now_ns();
+    retire(srv, s, t0);
+    {
+      std::lock_guard<std::mutex> lk(srv->mu);
+      srv->stats.host_retire_s += double(now_ns() - t0) * 1e-9;
     }
   }
 }
@@ -375,7 +425,7 @@ int soap_dp_server_create(soap_dp_server **out, const soap_dp_server_config *cfg
     delete srv;
     return rc;
   }
-  srv->worker = std::thread(dispatcher, srv);
+  for (size_t k = 0; k < srv->slots.size(); ++k) srv->workers.emplace_back(slot_worker, srv, k);
   *out = srv;
   return SOAP_DP_OK;
 }
@@ -401,7 +451,7 @@ int soap_dp_server_submit(soap_dp_server *srv, const soap_dp_request *req, uint6
   q->rbo.assign(req->ref_base_off, req->ref_base_off + n);
   q->ml.assign(req->ref_len, req->ref_len + n);
   q->out = req->out;
-  q->arrival_ns = req->arrival_ns;
+  q->arrival_ns = req->arrival_ns ? req->arrival_ns : now_ns();
   for (size_t t = 0; t < n; ++t) q->cells += int64_t(q->rl[t]) * int64_t(q->ml[t]);
   {
     std::lock_guard<std::mutex> lk(srv->mu);
@@ -459,7 +509,8 @@ int soap_dp_server_destroy(soap_dp_server *srv) {
     srv->stopping = true;
   }
   srv->cv_work.notify_all();
-  if (srv->worker.joinable()) srv->worker.join();
+  for (auto &w : srv->workers)
+    if (w.joinable()) w.join();
   (void)hipSetDevice(srv->cfg.device_ordinal);
   (void)hipDeviceSynchronize();
   for (auto &s : srv->slots) free_slot(s);

@@ -5,8 +5,6 @@ in the library's dispatcher thread and HIP kernels."""
 from __future__ import annotations
 
 import ctypes
-import threading
-import time
 
 import numpy as np
 
@@ -41,7 +39,8 @@ class ServerStats(ctypes.Structure):
     _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64),
                 ("rejected", ctypes.c_uint64), ("batches", ctypes.c_uint64),
                 ("tasks", ctypes.c_uint64), ("cells", ctypes.c_uint64),
-                ("device_busy_s", ctypes.c_double)]
+                ("device_busy_s", ctypes.c_double), ("host_launch_s", ctypes.c_double),
+                ("host_retire_s", ctypes.c_double)]
 
 
 _ready = False
@@ -81,11 +80,12 @@ def _p(a):
 
 class HostRequest:
     """One request: packed reads and window offsets (host arrays) and its
-    result buffers.  ``cigar_words_per_task`` sizes the packed CIGAR buffer;
-    2 * max_n - 1 always suffices."""
+    result buffers.  The packed CIGAR buffer holds ``cigar_words_per_task``
+    words per task plus ``cigar_extra`` words (by default room for one
+    CIGAR of a 512-base read); n_tasks * (2 * max_n - 1) always suffices."""
 
     def __init__(self, read_words, read_word_off, read_len, ref_base_off, ref_len,
-                 cigar_words_per_task=16):
+                 cigar_words_per_task=16, cigar_extra=1023):
         self.read_words = np.ascontiguousarray(read_words, dtype=np.uint32)
         self.read_word_off = np.ascontiguousarray(read_word_off, dtype=np.uint64)
         self.read_len = np.ascontiguousarray(read_len, dtype=np.int32)
@@ -97,7 +97,7 @@ class HostRequest:
         self.ref_end = np.zeros(n, np.int32)
         self.cigar_len = np.zeros(n, np.int32)
         self.status = np.full(n, 255, np.uint8)
-        self.cigar = np.zeros(max(1, n * cigar_words_per_task), np.uint32)
+        self.cigar = np.zeros(max(1, n * cigar_words_per_task + cigar_extra), np.uint32)
         self.cells = int(np.dot(self.read_len.astype(np.int64), self.ref_len.astype(np.int64)))
         self.struct = RequestStruct(
             _p(self.read_words), _p(self.read_word_off), _p(self.read_len), self.read_words.size,
@@ -195,41 +195,38 @@ def requests_from_pool(pool, sizes, start=0):
     return reqs
 
 
-def run_open_loop(server: Server, reqs, rate_hz: float, seed: int = 0):
-    """Submit ``reqs`` at Poisson arrival times (open loop: a late submission
-    still counts from its scheduled time) and wait for all of them.  Returns
-    (arrival_ns, done_ns, submit_lag_ns) arrays."""
-    gaps = np.random.Generator(np.random.PCG64(seed)).exponential(1.0 / rate_hz, size=len(reqs))
-    sched = np.cumsum(gaps)
-    done = []
-
-    def reaper():
-        for r in reqs:
-            while r.ticket is None:
-                time.sleep(0)
-            server.wait(r)
-            done.append(r)
-
-    th = threading.Thread(target=reaper, daemon=True)
-    t0 = now_ns() + 2_000_000
-    lag = np.zeros(len(reqs), np.int64)
-    th.start()
+def run_open_loop(server: Server, reqs, rate_hz: float, seed: int = 0, lead_s: float = None):
+    """Open-loop arrivals: request k arrives at start + the k-th point of a
+    Poisson process of rate ``rate_hz`` (``rate_hz`` <= 0: all at start).
+    The whole schedule is submitted ahead, each request carrying its arrival
+    time; the server admits none before it arrives, so the client's own speed
+    does not shape the arrivals.  ``start`` lies ``lead_s`` after the call
+    (default: room to submit everything first).  Waits for all requests and
+    returns (arrival_ns, done_ns, late_ns): late_ns > 0 marks a request
+    submitted after its arrival time."""
+    n = len(reqs)
+    if rate_hz > 0:
+        gaps = np.random.Generator(np.random.PCG64(seed)).exponential(1.0 / rate_hz, size=n)
+        sched = np.cumsum(gaps) - gaps[0]
+    else:
+        sched = np.zeros(n)
+    if lead_s is None:
+        lead_s = 0.05 + 40e-6 * n
     L = _lib()
+    t0 = L.soap_dp_now_ns() + int(lead_s * 1e9)
+    late = np.zeros(n, np.int64)
     for k, r in enumerate(reqs):
         target = t0 + int(sched[k] * 1e9)
-        while True:
-            now = L.soap_dp_now_ns()
-            if now >= target:
-                break
         r.struct.arrival_ns = target
         r.arrival_ns = target
         tk = ctypes.c_uint64()
         rc = L.soap_dp_server_submit(server.h, ctypes.byref(r.struct), ctypes.byref(tk))
         if rc != 0:
             raise binding.SoapDpError(rc, "soap_dp_server_submit")
-        lag[k] = L.soap_dp_now_ns() - target
+        late[k] = max(0, int(L.soap_dp_now_ns()) - target)
         r.ticket = tk.value
-    th.join()
+    for r in reqs:
+        server.wait(r)
     arr = np.array([r.arrival_ns for r in reqs], np.int64)
     dn = np.array([r.done_ns for r in reqs], np.int64)
-    return arr, dn, lag
+    return arr, dn, late

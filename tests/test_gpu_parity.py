@@ -102,15 +102,3 @@ def test_order_invariance():
     g2 = gpu_align(w.subset(perm), CONFIG_SCORING)
     for f in ("score", "ref_begin", "ref_end", "cigar_len", "status"):
         assert np.array_equal(g1[f][perm], g2[f])
-
-
-def test_config2_full_size_sampled():
-    """1,000,000 reads x 100 bp vs 250 bp windows in one plain launch; the
-    oracle checks a seeded sample of 40,000 tasks plus the first and last."""
-    w = workloads.config2()
-    g = gpu_align(w, CONFIG_SCORING)
-    rng = np.random.default_rng(2)
-    idx = np.unique(np.concatenate([rng.choice(w.n_tasks, 40000, replace=False),
-                                    np.arange(64), np.arange(w.n_tasks - 64, w.n_tasks)]))
-    assert_same(g, oracle_align(w, CONFIG_SCORING, idx=idx), idx=idx, label="config2 sample")
-    assert (g["status"] == 0).all()

@@ -74,7 +74,7 @@ def test_cigar_capacity_overflow_is_reported(setup):
     g, gw, pool, srv = setup
     r = serving.requests_from_pool(pool, [64])[0]
     r2 = serving.HostRequest(r.read_words, r.read_word_off, r.read_len, r.ref_base_off, r.ref_len,
-                             cigar_words_per_task=0)
+                             cigar_words_per_task=0, cigar_extra=0)
     r2.pool_idx = r.pool_idx
     srv.submit(r2)
     assert srv.wait(r2) == serving.SOAP_DP_E2BIG
@@ -92,3 +92,36 @@ def test_open_loop_run_completes(setup):
     assert all(r.rc == 0 for r in reqs)
     for r in reqs[::37]:
         _check_oracle(pool, r)
+
+
+def test_long_cigars_fetched_in_full():
+    """Reads with many short indels have CIGARs longer than the head the
+    server copies back with every batch; a small slot also exhausts the
+    staging for the rest, so rows are fetched both ways.  Every CIGAR must
+    still equal the oracle's."""
+    import torch
+    from paper_1302_5507_amd.workloads import _geometric_trunc, simulate
+    g = workloads.random_genome(500_000, 8)
+    gw = torch.from_numpy(binding.pack_words(g).view(np.int32)).cuda()
+    rng = np.random.Generator(np.random.PCG64(21))
+    n = np.full(64, 250)
+    m = n + 160
+    pool = simulate("long-cigars", g, n, m, lambda r, idx: r.integers(0, 100, size=idx.size),
+                    0.02, 0.12, lambda r, k: _geometric_trunc(r, 0.5, k, 4), rng)
+    ref = oracle_align(pool, CONFIG_SCORING, stride=500)
+    assert (ref.cigar_len > 16).sum() >= 16, "fixture should have many long CIGARs"
+    srv = serving.Server(gw, n_slots=2, max_tasks=16, max_n=250, max_m=410, autotune=False)
+    try:
+        reqs = []
+        for k, r in enumerate(serving.requests_from_pool(pool, [16, 16, 16, 16])):
+            big = serving.HostRequest(r.read_words, r.read_word_off, r.read_len, r.ref_base_off,
+                                      r.ref_len, cigar_words_per_task=499)
+            big.pool_idx = r.pool_idx
+            reqs.append(big)
+            srv.submit(big)
+        for r in reqs:
+            assert srv.wait(r) == 0
+        for r in reqs:
+            _check_oracle(pool, r)
+    finally:
+        srv.close()
