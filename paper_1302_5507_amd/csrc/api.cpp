@@ -137,11 +137,23 @@ bool shape_compiled(int prec, Shape s) {
   return false;
 }
 
-int occupancy(const soap_dp_ctx *ctx, int prec, Shape s) {
-  const uint32_t key = uint32_t(prec) << 16 | uint32_t(s.lanes) << 8 | uint32_t(s.cells);
+// Which int32 kernel variant a launch uses: the byte-table diagonal, the
+// general one, or (for sizing before the scoring is known) whichever holds
+// more workgroups.  int16 kernels have one variant.
+enum Variant { kGeneral = 0, kByte = 1, kEither = 2 };
+
+Variant variant_for(const soap_dp_scoring *sc) {
+  return byte_delta_fits(sc->match, sc->mismatch, sc->gap_extend) ? kByte : kGeneral;
+}
+
+int occupancy(const soap_dp_ctx *ctx, int prec, Shape s, Variant v) {
+  if (prec == 32 && v == kEither)
+    return std::max(occupancy(ctx, prec, s, kGeneral), occupancy(ctx, prec, s, kByte));
+  const uint32_t key = uint32_t(v) << 24 | uint32_t(prec) << 16 | uint32_t(s.lanes) << 8 |
+                       uint32_t(s.cells);
   auto it = ctx->occupancy.find(key);
   if (it != ctx->occupancy.end()) return it->second;
-  int o = prec == 16 ? occupancy_dp_i16(s) : occupancy_dp_i32(s);
+  int o = prec == 16 ? occupancy_dp_i16(s) : occupancy_dp_i32(s, v == kByte);
   o = o < 1 ? 1 : o;
   ctx->occupancy.emplace(key, o);
   return o;
@@ -170,10 +182,10 @@ Shape plain_shape(int32_t max_n, int32_t max_m) {
 
 // Persistent grid of one launch: every resident workgroup slot, limited by
 // the scratch budget and by the work available.
-int grid_for(const soap_dp_ctx *ctx, int prec, Shape s, int64_t n_tasks, int32_t max_m) {
+int grid_for(const soap_dp_ctx *ctx, int prec, Shape s, int64_t n_tasks, int32_t max_m, Variant v) {
   const int64_t per_wave = (prec == 16 ? 2 : 1) * kWave / s.lanes;
   const int64_t items = (n_tasks + per_wave - 1) / per_wave;
-  int64_t grid = int64_t(ctx->cu_count) * occupancy(ctx, prec, s);
+  int64_t grid = int64_t(ctx->cu_count) * occupancy(ctx, prec, s, v);
   const uint64_t slot_bytes = slot_dwords(prec, s, max_m) * 4;
   grid = std::min<int64_t>(grid, std::max<int64_t>(int64_t(kScratchCap / slot_bytes), 1));
   grid = std::min<int64_t>(grid, std::max<int64_t>(items, 1));
@@ -279,9 +291,10 @@ struct LaunchPlan {
 // but no more than the work items a workgroup can expect, and within
 // `budget` bytes of scratch.
 LaunchPlan plan_launch(const soap_dp_ctx *ctx, int prec, Shape s, int64_t n_tasks, int32_t max_m,
+                       Variant v,
                        size_t budget) {
   LaunchPlan q;
-  q.grid = grid_for(ctx, prec, s, n_tasks, max_m);
+  q.grid = grid_for(ctx, prec, s, n_tasks, max_m, v);
   q.slot_dwords = slot_dwords(prec, s, max_m);
   const int64_t per = tasks_per_item(prec, s);
   const int64_t items = (n_tasks + per - 1) / per;
@@ -313,17 +326,18 @@ BucketBuffers bucket_buffers(const soap_dp_ctx *ctx) {
 
 // ------------------------------------------------------------------ plain
 
-size_t plain_scratch_bytes(const soap_dp_ctx *ctx, int64_t n_tasks, int32_t max_n, int32_t max_m) {
+size_t plain_scratch_bytes(const soap_dp_ctx *ctx, int64_t n_tasks, int32_t max_n, int32_t max_m,
+                           Variant v) {
   const Shape s = plain_shape(max_n, max_m);
   if (s.lanes == 0) return 0;
-  return plan_launch(ctx, 32, s, n_tasks, max_m, kScratchCap).bytes();
+  return plan_launch(ctx, 32, s, n_tasks, max_m, v, kScratchCap).bytes();
 }
 
 int align_plain(soap_dp_ctx *ctx, const soap_dp_batch *in, const soap_dp_scoring *sc,
                 const soap_dp_result *out, hipStream_t stream) {
   const Shape s = plain_shape(in->max_n, in->max_m);
   if (s.lanes == 0) return SOAP_DP_EINVAL;
-  const LaunchPlan q = plan_launch(ctx, 32, s, in->n_tasks, in->max_m, kScratchCap);
+  const LaunchPlan q = plan_launch(ctx, 32, s, in->n_tasks, in->max_m, variant_for(sc), kScratchCap);
   const int rc = ensure_scratch(ctx, q.bytes());
   if (rc) return rc;
   DpParams p = make_params(in, sc, out);
@@ -388,13 +402,13 @@ struct BatchedPlan {
   size_t bytes() const { return size_t(budget_dwords + 64 * kMaxClasses) * 4; }
 };
 
-BatchedPlan batched_plan(const soap_dp_ctx *ctx, int64_t n_tasks, int32_t max_m,
+BatchedPlan batched_plan(const soap_dp_ctx *ctx, int64_t n_tasks, int32_t max_m, Variant v,
                          const std::vector<int> &live) {
   BatchedPlan bp;
   uint64_t need = 0, want = 0;
   for (int k : live) {
     const ClassSpec &c = ctx->classes[size_t(k)];
-    const LaunchPlan q = plan_launch(ctx, c.prec, c.shape, n_tasks, max_m, SIZE_MAX);
+    const LaunchPlan q = plan_launch(ctx, c.prec, c.shape, n_tasks, max_m, v, SIZE_MAX);
     bp.grids.push_back(q.grid);
     need += round64(uint64_t(q.grid) * q.slot_dwords);
     want += round64(uint64_t(q.grid) * uint64_t(q.defer) * q.slot_dwords);
@@ -403,9 +417,9 @@ BatchedPlan batched_plan(const soap_dp_ctx *ctx, int64_t n_tasks, int32_t max_m,
   return bp;
 }
 
-size_t batched_scratch_bytes(const soap_dp_ctx *ctx, int64_t n_tasks, int32_t max_m,
+size_t batched_scratch_bytes(const soap_dp_ctx *ctx, int64_t n_tasks, int32_t max_m, Variant v,
                              const std::vector<int> &live) {
-  return batched_plan(ctx, n_tasks, max_m, live).bytes();
+  return batched_plan(ctx, n_tasks, max_m, v, live).bytes();
 }
 
 int ensure_class_streams(soap_dp_ctx *ctx, size_t n) {
@@ -489,7 +503,7 @@ int align_batched(soap_dp_ctx *ctx, const soap_dp_batch *in, const soap_dp_scori
   if (rc) return rc;
   rc = ensure_class_streams(ctx, live.size());
   if (rc) return rc;
-  const BatchedPlan bp = batched_plan(ctx, in->n_tasks, in->max_m, live);
+  const BatchedPlan bp = batched_plan(ctx, in->n_tasks, in->max_m, variant_for(sc), live);
   rc = ensure_scratch(ctx, bp.bytes());
   if (rc) return rc;
   if (!ctx->use_graphs) {
@@ -668,7 +682,7 @@ double time_shape(soap_dp_ctx *ctx, int prec, Shape s, const TuneData &d, int32_
   p.cigar_len = d.i32 + 3 * d.tasks; p.cigar = d.cigar; p.cigar_stride = 2 * n;
   p.status = d.status;
   p.ok_status = kTaskOk;
-  const LaunchPlan q = plan_launch(ctx, prec, s, d.tasks, m, kScratchCap);
+  const LaunchPlan q = plan_launch(ctx, prec, s, d.tasks, m, variant_for(&sc), kScratchCap);
   const int grid = q.grid;
   p.slot_dwords = q.slot_dwords;
   p.defer = q.defer;
@@ -804,7 +818,7 @@ size_t soap_dp_workspace_bytes(const soap_dp_ctx *ctx, int64_t n_tasks, int32_t 
       max_m > SOAP_DP_MAX_WINDOW)
     return 0;
   const size_t small = kSmallInts * sizeof(int32_t);
-  if (flags == SOAP_DP_PLAIN) return plain_scratch_bytes(ctx, n_tasks, max_n, max_m) + small;
+  if (flags == SOAP_DP_PLAIN) return plain_scratch_bytes(ctx, n_tasks, max_n, max_m, kEither) + small;
   // the int32 classes are counted too: the scoring is not known here
   std::vector<int> live;
   int prev16 = 0, prev32 = 0;
@@ -814,7 +828,7 @@ size_t soap_dp_workspace_bytes(const soap_dp_ctx *ctx, int64_t n_tasks, int32_t 
     if (prev < max_n) live.push_back(int(k));
     prev = c.cap;
   }
-  return batched_scratch_bytes(ctx, n_tasks, max_m, live) + size_t(n_tasks) * 5 + small;
+  return batched_scratch_bytes(ctx, n_tasks, max_m, kEither, live) + size_t(n_tasks) * 5 + small;
 }
 
 int soap_dp_reserve(soap_dp_ctx *ctx, int64_t n_tasks, int32_t max_n, int32_t max_m,

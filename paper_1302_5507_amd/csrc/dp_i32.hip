@@ -37,7 +37,7 @@
 
 namespace soapdp {
 
-template <int L, int K>
+template <int L, int K, bool kByte>
 __global__ __launch_bounds__(kWave) void dp_i32_kernel(DpParams p) {
   static_assert(kWave % L == 0, "lanes per task must divide the wavefront");
   constexpr int G = kWave / L;       // tasks per wavefront
@@ -102,21 +102,43 @@ __global__ __launch_bounds__(kWave) void dp_i32_kernel(DpParams p) {
     const int32_t ge = p.ge;
     const int32_t c_go = p.go - ge;          // gap open in offset form
     const int32_t c_ma = p.ma - 2 * ge;      // diagonal constants in offset form
-    int32_t Rc[K], Mi[K], H[K], F[K];
+    // Read codes (4 left of the read, never a window base).  General
+    // variant: one register per column plus its mismatch constant.  Byte
+    // variant: four columns' codes per register, one byte each.
+    constexpr int Q = (K + 3) / 4;
+    int32_t Rc[kByte ? 1 : K], Mi[kByte ? 1 : K], H[K], F[K];
+    uint32_t R4[kByte ? Q : 1];
+#pragma unroll
+    for (int q = 0; q < (kByte ? Q : 1); ++q) R4[q] = 0;
 #pragma unroll
     for (int c = 0; c < K; ++c) {
       const int32_t q = lg * K + c - pad;  // 0-based read index of this column
       const bool real = valid && q >= 0;
-      const uint32_t code = real ? rw.code(q) : 4u;   // 4 never equals a window base
-      Rc[c] = (int32_t)code;
-      Mi[c] = real ? p.mi - 2 * ge : -2 * ge;
+      const uint32_t code = real ? rw.code(q) : 4u;
+      if constexpr (kByte) {
+        R4[c / 4] |= code << (8 * (c % 4));
+      } else {
+        Rc[c] = (int32_t)code;
+        Mi[c] = real ? p.mi - 2 * ge : -2 * ge;
+      }
       // M^(0, j), j = q + 1: S_GO + (j-1) S_GE - j S_GE, or 0 - j S_GE left of the read
       H[c] = real ? c_go : -(q + 1) * ge;
       F[c] = kNeg32;                       // D(0, j)
       // finish each column before the next: bounds live registers in set-up
-      asm volatile("" : "+v"(Rc[c]), "+v"(Mi[c]), "+v"(H[c]));
+      if constexpr (kByte)
+        asm volatile("" : "+v"(R4[c / 4]), "+v"(H[c]));
+      else
+        asm volatile("" : "+v"(Rc[c]), "+v"(Mi[c]), "+v"(H[c]));
       __builtin_amdgcn_sched_barrier(0);
     }
+    // Byte variant: the diagonal constant of code x at window base b is byte
+    // x of the table (tab_hi:tab_lo) with byte b of tab_lo holding the match
+    // value, the other bytes of tab_lo the mismatch value and tab_hi (codes
+    // 4..7) the value left of the read.
+    const uint32_t d_mi = (uint32_t)(p.mi - 2 * ge) & 0xffu;
+    const uint32_t tab_mis = d_mi * 0x01010101u;
+    const uint32_t tab_flip = ((uint32_t)c_ma & 0xffu) ^ d_mi;
+    const uint32_t tab_hi = ((uint32_t)(-2 * ge) & 0xffu) * 0x01010101u;
 
     // window bases, 16 at a time, realigned from the base offset
     const uint64_t wlim = p.ref_words - 1;
@@ -160,14 +182,27 @@ __global__ __launch_bounds__(kWave) void dp_i32_kernel(DpParams p) {
       t_out = T;
       const int32_t i = t + 1 - lg;
       if ((uint32_t)(t - lg) < (uint32_t)mg) {   // 1 <= i <= mg
+        uint32_t d4[kByte ? Q : 1];
+        if constexpr (kByte) {
+          // this row's table, then four columns' constants per byte permute
+          const uint32_t tab_lo = tab_mis ^ (tab_flip << (8 * T));
+#pragma unroll
+          for (int q = 0; q < Q; ++q) d4[q] = __builtin_amdgcn_perm(tab_hi, tab_lo, R4[q]);
+        }
+        auto delta = [&](int c) -> int32_t {
+          if constexpr (kByte)
+            return (int32_t)((d4[c / 4] >> (8 * (c % 4))) & 0xffu);
+          else
+            return Rc[c] == T ? c_ma : Mi[c];
+        };
         // The diagonal candidate of column c+1 is formed from the old H[c]
         // before H[c] is overwritten, so every update happens in place.
-        int32_t diag = hd + (Rc[0] == T ? c_ma : Mi[0]);
+        int32_t diag = hd + delta(0);
 #pragma unroll
         for (int c = 0; c < K; ++c) {
           const int32_t ad = H[c] + c_go;
           int32_t diag_next = 0;
-          if (c + 1 < K) diag_next = H[c] + (Rc[c + 1] == T ? c_ma : Mi[c + 1]);
+          if (c + 1 < K) diag_next = H[c] + delta(c + 1);
           const int32_t ai = hl + c_go;
           el = max(ai, el);
           const int32_t f = max(ad, F[c]);
@@ -266,24 +301,30 @@ const Shape *shapes_i32(int *count) {
 }
 
 hipError_t launch_dp_i32(Shape s, int grid, hipStream_t stream, const DpParams &p) {
-#define X(l, k)                                                                 \
-  if (s.lanes == l && s.cells == k) {                                           \
-    hipLaunchKernelGGL((dp_i32_kernel<l, k>), dim3(grid), dim3(kWave), 0, stream, p); \
-    return hipGetLastError();                                                   \
+  const bool byte = byte_delta_fits(p.ma, p.mi, p.ge);
+#define X(l, k)                                                                      \
+  if (s.lanes == l && s.cells == k) {                                                \
+    if (byte)                                                                        \
+      hipLaunchKernelGGL((dp_i32_kernel<l, k, true>), dim3(grid), dim3(kWave), 0, stream, p); \
+    else                                                                             \
+      hipLaunchKernelGGL((dp_i32_kernel<l, k, false>), dim3(grid), dim3(kWave), 0, stream, p); \
+    return hipGetLastError();                                                        \
   }
   SOAPDP_I32_SHAPES(X)
 #undef X
   return hipErrorInvalidValue;
 }
 
-int occupancy_dp_i32(Shape s) {
+int occupancy_dp_i32(Shape s, bool byte_delta) {
   int blocks = 0;
-#define X(l, k)                                                                               \
-  if (s.lanes == l && s.cells == k) {                                                         \
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, dp_i32_kernel<l, k>, kWave, 0) \
-        != hipSuccess)                                                                        \
-      blocks = 0;                                                                             \
-    return blocks;                                                                            \
+  hipError_t e = hipErrorInvalidValue;
+#define X(l, k)                                                                            \
+  if (s.lanes == l && s.cells == k) {                                                      \
+    e = byte_delta ? hipOccupancyMaxActiveBlocksPerMultiprocessor(                         \
+                         &blocks, dp_i32_kernel<l, k, true>, kWave, 0)                     \
+                   : hipOccupancyMaxActiveBlocksPerMultiprocessor(                         \
+                         &blocks, dp_i32_kernel<l, k, false>, kWave, 0);                   \
+    return e == hipSuccess ? blocks : 0;                                                   \
   }
   SOAPDP_I32_SHAPES(X)
 #undef X

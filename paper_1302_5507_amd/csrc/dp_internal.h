@@ -82,12 +82,20 @@ struct Shape {
 // possible maximum and n S_MA, shifted up by at most (m + n) |S_GE|; virtual
 // columns hold (i+j) |S_GE| with j down to -cols; each bound is widened by
 // twice the largest constant added.  Evaluated identically on host and device.
-__host__ __device__ inline bool int16_fits(int32_t n, int32_t m, int32_t cols, int32_t ma,
-                                           int32_t mi, int32_t go, int32_t ge) {
+// The diagonal constants of the offset form X - (i+j) S_GE (S_MA - 2 S_GE on
+// a match, S_MI - 2 S_GE on a mismatch, -2 S_GE left of the read) fit an
+// unsigned byte, so one byte permute looks them up.
+__host__ __device__ inline bool byte_delta_fits(int32_t ma, int32_t mi, int32_t ge) {
   const int64_t d_ma = int64_t(ma) - 2 * int64_t(ge);
   const int64_t d_mi = int64_t(mi) - 2 * int64_t(ge);
   const int64_t d_v = -2 * int64_t(ge);
-  if (d_mi < 0 || d_ma > 255 || d_v > 255) return false;
+  return d_mi >= 0 && d_ma <= 255 && d_v <= 255;
+}
+
+__host__ __device__ inline bool int16_fits(int32_t n, int32_t m, int32_t cols, int32_t ma,
+                                           int32_t mi, int32_t go, int32_t ge) {
+  if (!byte_delta_fits(ma, mi, ge)) return false;
+  const int64_t d_ma = int64_t(ma) - 2 * int64_t(ge);
   auto iabs = [](int64_t v) { return v < 0 ? -v : v; };
   int64_t s = iabs(int64_t(go) - ge);
   s = s > d_ma ? s : d_ma;
@@ -97,10 +105,13 @@ __host__ __device__ inline bool int16_fits(int32_t n, int32_t m, int32_t cols, i
   return lo - 2 * s > -32000 && hi + 2 * s < 32000;
 }
 
-// Launch the int32 kernel of shape `s` (must be one of the compiled shapes).
+// Launch the int32 kernel of shape `s` (must be one of the compiled shapes);
+// the variant with the byte-table diagonal runs when the scoring allows it
+// (byte_delta_fits).
 hipError_t launch_dp_i32(Shape s, int grid, hipStream_t stream, const DpParams &p);
-// Occupancy (workgroups of one wave per CU) of the int32 kernel of shape `s`.
-int occupancy_dp_i32(Shape s);
+// Occupancy (workgroups of one wave per CU) of the int32 kernel of shape `s`,
+// byte-table variant or general one.
+int occupancy_dp_i32(Shape s, bool byte_delta);
 // The compiled int32 shapes.
 const Shape *shapes_i32(int *count);
 
