@@ -49,8 +49,12 @@ constexpr uint32_t kSignSel = 0x0b0a0908u;   // v_perm: replicate the four sign 
 
 }  // namespace
 
+// Shapes with at most 8 columns per lane fit five wavefronts per SIMD (96
+// VGPRs) without spilling once the compiler is asked to; wider ones would
+// spill and keep the default.
 template <int L, int K>
-__global__ __launch_bounds__(kWave) void dp_i16_kernel(DpParams p) {
+__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(K <= 8 ? 5 : 1)))
+void dp_i16_kernel(DpParams p) {
   static_assert(kWave % L == 0, "lanes per task must divide the wavefront");
   constexpr int G = kWave / L;       // lane groups per wavefront
   constexpr int TPW = 2 * G;         // tasks per wavefront (low and high halves)

@@ -37,8 +37,11 @@
 
 namespace soapdp {
 
+// The byte-table variant fits five wavefronts per SIMD (96 VGPRs) up to 16
+// columns per lane without spilling once the compiler is asked to.
 template <int L, int K, bool kByte>
-__global__ __launch_bounds__(kWave) void dp_i32_kernel(DpParams p) {
+__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(kByte && K <= 16 ? 5 : 1)))
+void dp_i32_kernel(DpParams p) {
   static_assert(kWave % L == 0, "lanes per task must divide the wavefront");
   constexpr int G = kWave / L;       // tasks per wavefront
   constexpr int W = (K + 7) / 8;     // decision dwords per lane per step
