@@ -39,8 +39,8 @@ PEAK_INT16_TOPS = 2 * PEAK_INT32_TOPS            # packed 2 x int16 per lane
 KERNEL_SOURCES = ("api.cpp", "batch.h", "batch.hip", "dp_device.h", "dp_i16.hip", "dp_i32.hip",
                   "dp_internal.h")
 TRAFFIC = {
-    ("config2", "plain"): {"fingerprint": "182584a1f026447a", "kernel": "dp_i32_kernel<8,13>",
-                           "fetch_kib": 1848245, "write_kib": 16641869,
+    ("config2", "plain"): {"fingerprint": "a68ec3b0c49a2c05", "kernel": "dp_i32_kernel<8,13,byte>",
+                           "fetch_kib": 1851808, "write_kib": 16642528,
                            "fetch_scale": 2.000, "write_scale": 1.000},
 }
 
