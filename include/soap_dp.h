@@ -66,6 +66,9 @@ extern "C" {
 #define SOAP_DP_BATCHED 1u  /* device-side length bucketing, packed int16 with int32 redo of
                                tasks outside the int16 range, persistent kernels with a
                                work queue, autotuned shapes, replayed as a hipGraph */
+#define SOAP_DP_SCORE_ONLY 2u  /* OR-ed with either form: score and ref_end only (same values
+                                  as the full call); no traceback: ref_begin is -1, cigar_len
+                                  0, `cigar` untouched and may be NULL with any stride */
 
 /*
  * Scores, all signed and added.  A gap of k bases scores
@@ -142,7 +145,8 @@ int soap_dp_destroy(soap_dp_ctx *ctx);
 /*
  * Enqueue the alignment of `in` on `stream` (a hipStream_t; NULL is the null
  * stream) and return.  Results are valid once the stream has synchronised.
- * `flags` is SOAP_DP_PLAIN or SOAP_DP_BATCHED; both give identical outputs.
+ * `flags` is SOAP_DP_PLAIN or SOAP_DP_BATCHED (both give identical outputs),
+ * optionally OR-ed with SOAP_DP_SCORE_ONLY; other bits are SOAP_DP_EINVAL.
  * The library keeps no pointer to caller buffers after the work completes.
  * One context serves one stream at a time: calls on a context must not
  * overlap in time on different streams (use one context per stream).

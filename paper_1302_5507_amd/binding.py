@@ -31,6 +31,7 @@ MAX_WINDOW = 8192
 
 PLAIN = 0
 BATCHED = 1
+SCORE_ONLY = 2   # OR-ed with either form: score and end only
 
 EXPORTED = [
     "soap_dp_create", "soap_dp_destroy", "soap_dp_align_batch", "soap_dp_workspace_bytes",
@@ -272,7 +273,8 @@ class DeviceResult:
             "score": self.score.cpu().numpy()[:T],
             "ref_begin": self.ref_begin.cpu().numpy()[:T],
             "ref_end": self.ref_end.cpu().numpy()[:T],
-            "cigar": self.cigar.cpu().numpy().view(np.uint32).reshape(-1, self.cigar_stride)[:T],
+            "cigar": (self.cigar.cpu().numpy().view(np.uint32).reshape(-1, self.cigar_stride)[:T]
+                      if self.cigar_stride else np.zeros((T, 0), np.uint32)),
             "cigar_len": self.cigar_len.cpu().numpy()[:T],
             "status": self.status.cpu().numpy()[:T],
         }

@@ -50,6 +50,7 @@ struct GraphKey {
   soap_dp_scoring sc;
   soap_dp_result out;
   uint64_t epoch;
+  uint32_t flags;
 };
 
 struct GraphEntry {
@@ -113,18 +114,18 @@ bool scoring_ok(const soap_dp_scoring *sc) {
          sc->gap_open <= sc->gap_extend && sc->gap_extend <= 0;
 }
 
-int batch_ok(const soap_dp_batch *in, const soap_dp_result *out) {
+int batch_ok(const soap_dp_batch *in, const soap_dp_result *out, bool score_only) {
   if (!in || !out) return SOAP_DP_EINVAL;
   if (in->n_tasks < 0 || in->n_tasks > (int64_t(1) << 31) - 1) return SOAP_DP_EINVAL;
   if (in->max_n < 1 || in->max_n > SOAP_DP_MAX_READ) return SOAP_DP_EINVAL;
   if (in->max_m < 1 || in->max_m > SOAP_DP_MAX_WINDOW) return SOAP_DP_EINVAL;
-  if (out->cigar_stride < 2 * in->max_n - 1) return SOAP_DP_EINVAL;
+  if (!score_only && out->cigar_stride < 2 * in->max_n - 1) return SOAP_DP_EINVAL;
   if (in->n_tasks == 0) return SOAP_DP_OK;
   if (!in->read_codes || !in->read_word_off || !in->read_len || !in->ref_codes ||
       !in->ref_base_off || !in->ref_len || in->read_words == 0 || in->ref_words == 0)
     return SOAP_DP_EINVAL;
-  if (!out->score || !out->ref_begin || !out->ref_end || !out->cigar || !out->cigar_len ||
-      !out->status)
+  if (!out->score || !out->ref_begin || !out->ref_end || !out->cigar_len || !out->status ||
+      (!score_only && !out->cigar))
     return SOAP_DP_EINVAL;
   return SOAP_DP_OK;
 }
@@ -137,23 +138,29 @@ bool shape_compiled(int prec, Shape s) {
   return false;
 }
 
-// Which int32 kernel variant a launch uses: the byte-table diagonal, the
-// general one, or (for sizing before the scoring is known) whichever holds
-// more workgroups.  int16 kernels have one variant.
+// Kernel kind of a launch: which int32 diagonal variant (byte table,
+// general, or -- for sizing before the scoring is known -- whichever holds
+// more workgroups; int16 kernels have one) and whether only scores are
+// computed.
 enum Variant { kGeneral = 0, kByte = 1, kEither = 2 };
+struct Kind {
+  Variant v;
+  bool score;
+};
 
-Variant variant_for(const soap_dp_scoring *sc) {
-  return byte_delta_fits(sc->match, sc->mismatch, sc->gap_extend) ? kByte : kGeneral;
+Kind kind_for(const soap_dp_scoring *sc, bool score) {
+  return Kind{byte_delta_fits(sc->match, sc->mismatch, sc->gap_extend) ? kByte : kGeneral, score};
 }
 
-int occupancy(const soap_dp_ctx *ctx, int prec, Shape s, Variant v) {
-  if (prec == 32 && v == kEither)
-    return std::max(occupancy(ctx, prec, s, kGeneral), occupancy(ctx, prec, s, kByte));
-  const uint32_t key = uint32_t(v) << 24 | uint32_t(prec) << 16 | uint32_t(s.lanes) << 8 |
-                       uint32_t(s.cells);
+int occupancy(const soap_dp_ctx *ctx, int prec, Shape s, Kind k) {
+  if (prec == 32 && k.v == kEither)
+    return std::max(occupancy(ctx, prec, s, Kind{kGeneral, k.score}),
+                    occupancy(ctx, prec, s, Kind{kByte, k.score}));
+  const uint32_t key = uint32_t(k.score) << 26 | uint32_t(k.v) << 24 | uint32_t(prec) << 16 |
+                       uint32_t(s.lanes) << 8 | uint32_t(s.cells);
   auto it = ctx->occupancy.find(key);
   if (it != ctx->occupancy.end()) return it->second;
-  int o = prec == 16 ? occupancy_dp_i16(s) : occupancy_dp_i32(s, v == kByte);
+  int o = prec == 16 ? occupancy_dp_i16(s, k.score) : occupancy_dp_i32(s, k.v == kByte, k.score);
   o = o < 1 ? 1 : o;
   ctx->occupancy.emplace(key, o);
   return o;
@@ -182,10 +189,10 @@ Shape plain_shape(int32_t max_n, int32_t max_m) {
 
 // Persistent grid of one launch: every resident workgroup slot, limited by
 // the scratch budget and by the work available.
-int grid_for(const soap_dp_ctx *ctx, int prec, Shape s, int64_t n_tasks, int32_t max_m, Variant v) {
+int grid_for(const soap_dp_ctx *ctx, int prec, Shape s, int64_t n_tasks, int32_t max_m, Kind k) {
   const int64_t per_wave = (prec == 16 ? 2 : 1) * kWave / s.lanes;
   const int64_t items = (n_tasks + per_wave - 1) / per_wave;
-  int64_t grid = int64_t(ctx->cu_count) * occupancy(ctx, prec, s, v);
+  int64_t grid = int64_t(ctx->cu_count) * occupancy(ctx, prec, s, k);
   const uint64_t slot_bytes = slot_dwords(prec, s, max_m) * 4;
   grid = std::min<int64_t>(grid, std::max<int64_t>(int64_t(kScratchCap / slot_bytes), 1));
   grid = std::min<int64_t>(grid, std::max<int64_t>(items, 1));
@@ -291,10 +298,14 @@ struct LaunchPlan {
 // but no more than the work items a workgroup can expect, and within
 // `budget` bytes of scratch.
 LaunchPlan plan_launch(const soap_dp_ctx *ctx, int prec, Shape s, int64_t n_tasks, int32_t max_m,
-                       Variant v,
-                       size_t budget) {
+                       Kind k, size_t budget) {
   LaunchPlan q;
-  q.grid = grid_for(ctx, prec, s, n_tasks, max_m, v);
+  q.grid = grid_for(ctx, prec, s, n_tasks, max_m, k);
+  if (k.score) {   // no decision scratch
+    q.slot_dwords = 0;
+    q.defer = 1;
+    return q;
+  }
   q.slot_dwords = slot_dwords(prec, s, max_m);
   const int64_t per = tasks_per_item(prec, s);
   const int64_t items = (n_tasks + per - 1) / per;
@@ -327,20 +338,21 @@ BucketBuffers bucket_buffers(const soap_dp_ctx *ctx) {
 // ------------------------------------------------------------------ plain
 
 size_t plain_scratch_bytes(const soap_dp_ctx *ctx, int64_t n_tasks, int32_t max_n, int32_t max_m,
-                           Variant v) {
+                           Kind k) {
   const Shape s = plain_shape(max_n, max_m);
   if (s.lanes == 0) return 0;
-  return plan_launch(ctx, 32, s, n_tasks, max_m, v, kScratchCap).bytes();
+  return plan_launch(ctx, 32, s, n_tasks, max_m, k, kScratchCap).bytes();
 }
 
 int align_plain(soap_dp_ctx *ctx, const soap_dp_batch *in, const soap_dp_scoring *sc,
-                const soap_dp_result *out, hipStream_t stream) {
+                const soap_dp_result *out, hipStream_t stream, bool score) {
   const Shape s = plain_shape(in->max_n, in->max_m);
   if (s.lanes == 0) return SOAP_DP_EINVAL;
-  const LaunchPlan q = plan_launch(ctx, 32, s, in->n_tasks, in->max_m, variant_for(sc), kScratchCap);
+  const LaunchPlan q = plan_launch(ctx, 32, s, in->n_tasks, in->max_m, kind_for(sc, score), kScratchCap);
   const int rc = ensure_scratch(ctx, q.bytes());
   if (rc) return rc;
   DpParams p = make_params(in, sc, out);
+  p.score_only = score;
   p.scratch = static_cast<uint32_t *>(ctx->scratch);
   p.slot_dwords = q.slot_dwords;
   p.defer = q.defer;
@@ -397,18 +409,20 @@ std::vector<int> live_classes(const soap_dp_ctx *ctx, int32_t max_n, int32_t max
 // otherwise room for every class to reach full deferral as if it held the
 // whole batch, up to the scratch cap; plus slack for region rounding.
 struct BatchedPlan {
+  bool score = false;   // score-only kernels: no decision scratch
   std::vector<int> grids;
   uint64_t budget_dwords = 0;
   size_t bytes() const { return size_t(budget_dwords + 64 * kMaxClasses) * 4; }
 };
 
-BatchedPlan batched_plan(const soap_dp_ctx *ctx, int64_t n_tasks, int32_t max_m, Variant v,
+BatchedPlan batched_plan(const soap_dp_ctx *ctx, int64_t n_tasks, int32_t max_m, Kind k,
                          const std::vector<int> &live) {
   BatchedPlan bp;
+  bp.score = k.score;
   uint64_t need = 0, want = 0;
-  for (int k : live) {
-    const ClassSpec &c = ctx->classes[size_t(k)];
-    const LaunchPlan q = plan_launch(ctx, c.prec, c.shape, n_tasks, max_m, v, SIZE_MAX);
+  for (int cls : live) {
+    const ClassSpec &c = ctx->classes[size_t(cls)];
+    const LaunchPlan q = plan_launch(ctx, c.prec, c.shape, n_tasks, max_m, k, SIZE_MAX);
     bp.grids.push_back(q.grid);
     need += round64(uint64_t(q.grid) * q.slot_dwords);
     want += round64(uint64_t(q.grid) * uint64_t(q.defer) * q.slot_dwords);
@@ -417,9 +431,9 @@ BatchedPlan batched_plan(const soap_dp_ctx *ctx, int64_t n_tasks, int32_t max_m,
   return bp;
 }
 
-size_t batched_scratch_bytes(const soap_dp_ctx *ctx, int64_t n_tasks, int32_t max_m, Variant v,
+size_t batched_scratch_bytes(const soap_dp_ctx *ctx, int64_t n_tasks, int32_t max_m, Kind k,
                              const std::vector<int> &live) {
-  return batched_plan(ctx, n_tasks, max_m, v, live).bytes();
+  return batched_plan(ctx, n_tasks, max_m, k, live).bytes();
 }
 
 int ensure_class_streams(soap_dp_ctx *ctx, size_t n) {
@@ -454,7 +468,9 @@ ClassTable class_table(const soap_dp_ctx *ctx, const std::vector<int> &live,
     ct.max_defer[k] = kWave / ct.per_item[k];
     ct.lanes[k] = c.shape.lanes;
     ct.step_block[k] = step_block(c.shape.cells);
-    ct.step_dwords[k] = int32_t(uint64_t((c.shape.cells + 7) / 8) * kWave * (c.prec == 16 ? 2 : 1));
+    ct.step_dwords[k] =
+        bp.score ? 0 : int32_t(uint64_t((c.shape.cells + 7) / 8) * kWave * (c.prec == 16 ? 2 : 1));
+    if (bp.score) ct.max_defer[k] = 1;
   }
   for (size_t li = 0; li < live.size(); ++li) ct.grid[live[li]] = bp.grids[li];
   ct.budget_dwords = bp.budget_dwords;
@@ -489,6 +505,7 @@ hipError_t enqueue_batched(soap_dp_ctx *ctx, const soap_dp_batch *in, const soap
     q.slot_dwords_dev = b.slot_dwords + k;
     q.scratch_off_dev = b.scratch_off + k;
     q.ok_status = c.prec == 16 ? kTaskOk : kTaskRedone;
+    q.score_only = bp.score;
     if ((e = launch_shape(c.prec, c.shape, bp.grids[li], cs, q)) != hipSuccess) return e;
     if ((e = hipEventRecord(ctx->join_events[li], cs)) != hipSuccess) return e;
     if ((e = hipStreamWaitEvent(stream, ctx->join_events[li], 0)) != hipSuccess) return e;
@@ -497,13 +514,13 @@ hipError_t enqueue_batched(soap_dp_ctx *ctx, const soap_dp_batch *in, const soap
 }
 
 int align_batched(soap_dp_ctx *ctx, const soap_dp_batch *in, const soap_dp_scoring *sc,
-                  const soap_dp_result *out, hipStream_t stream) {
+                  const soap_dp_result *out, hipStream_t stream, bool score) {
   const std::vector<int> live = live_classes(ctx, in->max_n, in->max_m, sc);
   int rc = ensure_task_buffers(ctx, in->n_tasks);
   if (rc) return rc;
   rc = ensure_class_streams(ctx, live.size());
   if (rc) return rc;
-  const BatchedPlan bp = batched_plan(ctx, in->n_tasks, in->max_m, variant_for(sc), live);
+  const BatchedPlan bp = batched_plan(ctx, in->n_tasks, in->max_m, kind_for(sc, score), live);
   rc = ensure_scratch(ctx, bp.bytes());
   if (rc) return rc;
   if (!ctx->use_graphs) {
@@ -516,6 +533,7 @@ int align_batched(soap_dp_ctx *ctx, const soap_dp_batch *in, const soap_dp_scori
   key.sc = *sc;
   key.out = *out;
   key.epoch = ctx->epoch;
+  key.flags = score ? SOAP_DP_SCORE_ONLY : 0u;
   GraphEntry *hit = nullptr;
   for (auto &g : ctx->graphs)
     if (same_key(g.key, key)) { hit = &g; break; }
@@ -682,7 +700,7 @@ double time_shape(soap_dp_ctx *ctx, int prec, Shape s, const TuneData &d, int32_
   p.cigar_len = d.i32 + 3 * d.tasks; p.cigar = d.cigar; p.cigar_stride = 2 * n;
   p.status = d.status;
   p.ok_status = kTaskOk;
-  const LaunchPlan q = plan_launch(ctx, prec, s, d.tasks, m, variant_for(&sc), kScratchCap);
+  const LaunchPlan q = plan_launch(ctx, prec, s, d.tasks, m, kind_for(&sc, false), kScratchCap);
   const int grid = q.grid;
   p.slot_dwords = q.slot_dwords;
   p.defer = q.defer;
@@ -803,13 +821,15 @@ int soap_dp_align_batch(soap_dp_ctx *ctx, const soap_dp_batch *in, const soap_dp
                         const soap_dp_result *out, void *stream, uint32_t flags) {
   if (!ctx) return SOAP_DP_EINVAL;
   if (!scoring_ok(sc)) return SOAP_DP_EINVAL;
-  const int rc = batch_ok(in, out);
+  if (flags & ~(SOAP_DP_BATCHED | SOAP_DP_SCORE_ONLY)) return SOAP_DP_EINVAL;
+  const bool score = (flags & SOAP_DP_SCORE_ONLY) != 0;
+  const int rc = batch_ok(in, out, score);
   if (rc) return rc;
-  if (flags != SOAP_DP_PLAIN && flags != SOAP_DP_BATCHED) return SOAP_DP_EINVAL;
   if (in->n_tasks == 0) return SOAP_DP_OK;
   DeviceGuard dg(ctx->device);
   const hipStream_t st = static_cast<hipStream_t>(stream);
-  return flags == SOAP_DP_PLAIN ? align_plain(ctx, in, sc, out, st) : align_batched(ctx, in, sc, out, st);
+  return (flags & SOAP_DP_BATCHED) ? align_batched(ctx, in, sc, out, st, score)
+                                   : align_plain(ctx, in, sc, out, st, score);
 }
 
 size_t soap_dp_workspace_bytes(const soap_dp_ctx *ctx, int64_t n_tasks, int32_t max_n,
@@ -818,7 +838,8 @@ size_t soap_dp_workspace_bytes(const soap_dp_ctx *ctx, int64_t n_tasks, int32_t 
       max_m > SOAP_DP_MAX_WINDOW)
     return 0;
   const size_t small = kSmallInts * sizeof(int32_t);
-  if (flags == SOAP_DP_PLAIN) return plain_scratch_bytes(ctx, n_tasks, max_n, max_m, kEither) + small;
+  const Kind k{kEither, (flags & SOAP_DP_SCORE_ONLY) != 0};
+  if ((flags & SOAP_DP_BATCHED) == 0) return plain_scratch_bytes(ctx, n_tasks, max_n, max_m, k) + small;
   // the int32 classes are counted too: the scoring is not known here
   std::vector<int> live;
   int prev16 = 0, prev32 = 0;
@@ -828,7 +849,7 @@ size_t soap_dp_workspace_bytes(const soap_dp_ctx *ctx, int64_t n_tasks, int32_t 
     if (prev < max_n) live.push_back(int(k));
     prev = c.cap;
   }
-  return batched_scratch_bytes(ctx, n_tasks, max_m, kEither, live) + size_t(n_tasks) * 5 + small;
+  return batched_scratch_bytes(ctx, n_tasks, max_m, k, live) + size_t(n_tasks) * 5 + small;
 }
 
 int soap_dp_reserve(soap_dp_ctx *ctx, int64_t n_tasks, int32_t max_n, int32_t max_m,

@@ -52,7 +52,8 @@ constexpr uint32_t kSignSel = 0x0b0a0908u;   // v_perm: replicate the four sign 
 // Shapes with at most 8 columns per lane fit five wavefronts per SIMD (96
 // VGPRs) without spilling once the compiler is asked to; wider ones would
 // spill and keep the default.
-template <int L, int K>
+// kScore: score and end only -- no decision bits, no scratch, no traceback.
+template <int L, int K, bool kScore>
 __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(K <= 8 ? 5 : 1)))
 void dp_i16_kernel(DpParams p) {
   static_assert(kWave % L == 0, "lanes per task must divide the wavefront");
@@ -72,16 +73,17 @@ void dp_i16_kernel(DpParams p) {
   __shared__ uint8_t s_st[kWave];
   constexpr int B = step_block(K);   // sweep steps per stored block
   // staging buffer of the sweep, or the traceback's block caches
-  __shared__ __align__(16) uint2 s_lds[StageOrCache<uint2, W, B>::kWords];
+  __shared__ __align__(16) uint2 s_lds[kScore ? 2 : StageOrCache<uint2, W, B>::kWords];
 
   // `defer` work items are swept into consecutive slots before one
   // traceback pass serves all their tasks, one lane per task
-  const int32_t defer = min(max(p.defer_dev ? *p.defer_dev : p.defer, 1), kWave / TPW);
+  const int32_t defer = kScore ? 1 : min(max(p.defer_dev ? *p.defer_dev : p.defer, 1), kWave / TPW);
   const uint64_t slot_dwords = p.slot_dwords_dev ? *p.slot_dwords_dev : p.slot_dwords;
   uint32_t *const slots = p.scratch + (p.scratch_off_dev ? *p.scratch_off_dev : 0) +
                           (uint64_t)blockIdx.x * slot_dwords * (uint64_t)defer;
   // window rows a slot can hold: (rows + L - 1) steps of W * 64 lanes
-  const int64_t slot_rows = (int64_t)(slot_dwords / (uint64_t)(W * kWave * 2)) - (L - 1);
+  const int64_t slot_rows =
+      kScore ? INT64_MAX : (int64_t)(slot_dwords / (uint64_t)(W * kWave * 2)) - (L - 1);
   int32_t r = 0;   // slot of the current work item
   const int64_t n_tasks = p.task_count ? (int64_t)*p.task_count : p.n_tasks;
   const int32_t *const list = (p.task_list && p.task_off) ? p.task_list + *p.task_off : p.task_list;
@@ -222,15 +224,17 @@ void dp_i16_kernel(DpParams p) {
           const uint32_t hv = max16(max16(diag, el), f);
           // differences against the maxima, so the old I and D die at the max
           // and the new values take their registers
-          const uint32_t tA = __builtin_amdgcn_perm(sub16(ai, el), sub16(ad, f), kSignSel);
-          const uint32_t tB = __builtin_amdgcn_perm(sub16(diag, hv), sub16(f, hv), kSignSel);
-          const uint32_t msk = 0x01010101u << (c & 7);
-          if ((c & 7) == 0) {
-            accA[c / 8] = tA & msk;
-            accB[c / 8] = tB & msk;
-          } else {
-            accA[c / 8] |= tA & msk;
-            accB[c / 8] |= tB & msk;
+          if constexpr (!kScore) {
+            const uint32_t tA = __builtin_amdgcn_perm(sub16(ai, el), sub16(ad, f), kSignSel);
+            const uint32_t tB = __builtin_amdgcn_perm(sub16(diag, hv), sub16(f, hv), kSignSel);
+            const uint32_t msk = 0x01010101u << (c & 7);
+            if ((c & 7) == 0) {
+              accA[c / 8] = tA & msk;
+              accB[c / 8] = tB & msk;
+            } else {
+              accA[c / 8] |= tA & msk;
+              accB[c / 8] |= tB & msk;
+            }
           }
           H[c] = hv;
           F[c] = f;
@@ -239,7 +243,8 @@ void dp_i16_kernel(DpParams p) {
           // keep each column's decisions next to its scores: without this the
           // optimiser sinks them below all columns and every column's
           // candidates stay live (bounds live registers)
-          asm volatile("" : "+v"(accA[c / 8]), "+v"(accB[c / 8]));
+          if constexpr (!kScore) asm volatile("" : "+v"(accA[c / 8]), "+v"(accB[c / 8]));
+          else asm volatile("" : "+v"(H[c]));
           __builtin_amdgcn_sched_barrier(0);
         }
         hl_out = hl;
@@ -255,7 +260,7 @@ void dp_i16_kernel(DpParams p) {
           if (i <= mg[1]) best1 = max(best1, k1);
         }
       }
-      {
+      if constexpr (!kScore) {
         uint2 v[W];
 #pragma unroll
         for (int w = 0; w < W; ++w) v[w] = make_uint2(accA[w], accB[w]);
@@ -301,15 +306,21 @@ void dp_i16_kernel(DpParams p) {
           p.score[tk] = s_score[lane] + tn * ge;
           p.ref_end[tk] = tend;
           p.status[tk] = p.ok_status;
-          const uint2 *slot = reinterpret_cast<const uint2 *>(slots + (uint64_t)rs * slot_dwords);
-          const uint32_t shA = 8u * (2 + h), shD = 8u * h;
-          auto tr = make_tracer<uint2, K, W, B>(
-              slot, s_lds + lane * B, gq * L, tpad, [shA, shD](uint2 v, uint32_t c) {
-                const uint32_t b = c & 7u;
-                return ((v.x >> (shA + b)) & 1u) << 3 | ((v.x >> (shD + b)) & 1u) << 2 |
-                       ((v.y >> (shA + b)) & 1u) << 1 | ((v.y >> (shD + b)) & 1u);
-              });
-          traceback_task(p, tk, tn, tend, (int32_t)slot_rows, tr);
+          if constexpr (kScore) {   // begin and CIGAR are not computed
+            (void)rs; (void)h; (void)gq; (void)tpad;
+            p.ref_begin[tk] = -1;
+            p.cigar_len[tk] = 0;
+          } else {
+            const uint2 *slot = reinterpret_cast<const uint2 *>(slots + (uint64_t)rs * slot_dwords);
+            const uint32_t shA = 8u * (2 + h), shD = 8u * h;
+            auto tr = make_tracer<uint2, K, W, B>(
+                slot, s_lds + lane * B, gq * L, tpad, [shA, shD](uint2 v, uint32_t c) {
+                  const uint32_t b = c & 7u;
+                  return ((v.x >> (shA + b)) & 1u) << 3 | ((v.x >> (shD + b)) & 1u) << 2 |
+                         ((v.y >> (shA + b)) & 1u) << 1 | ((v.y >> (shD + b)) & 1u);
+                });
+            traceback_task(p, tk, tn, tend, (int32_t)slot_rows, tr);
+          }
         }
       }
     }
@@ -343,24 +354,29 @@ uint64_t slot_dwords_i16(Shape s, int32_t max_m) {
 }
 
 hipError_t launch_dp_i16(Shape s, int grid, hipStream_t stream, const DpParams &p) {
-#define X(l, k)                                                                 \
-  if (s.lanes == l && s.cells == k) {                                           \
-    hipLaunchKernelGGL((dp_i16_kernel<l, k>), dim3(grid), dim3(kWave), 0, stream, p); \
-    return hipGetLastError();                                                   \
+#define X(l, k)                                                                                \
+  if (s.lanes == l && s.cells == k) {                                                          \
+    if (p.score_only)                                                                          \
+      hipLaunchKernelGGL((dp_i16_kernel<l, k, true>), dim3(grid), dim3(kWave), 0, stream, p);  \
+    else                                                                                       \
+      hipLaunchKernelGGL((dp_i16_kernel<l, k, false>), dim3(grid), dim3(kWave), 0, stream, p); \
+    return hipGetLastError();                                                                  \
   }
   SOAPDP_I16_SHAPES(X)
 #undef X
   return hipErrorInvalidValue;
 }
 
-int occupancy_dp_i16(Shape s) {
+int occupancy_dp_i16(Shape s, bool score_only) {
   int blocks = 0;
-#define X(l, k)                                                                               \
-  if (s.lanes == l && s.cells == k) {                                                         \
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, dp_i16_kernel<l, k>, kWave, 0) \
-        != hipSuccess)                                                                        \
-      blocks = 0;                                                                             \
-    return blocks;                                                                            \
+  hipError_t e = hipErrorInvalidValue;
+#define X(l, k)                                                                          \
+  if (s.lanes == l && s.cells == k) {                                                    \
+    e = score_only ? hipOccupancyMaxActiveBlocksPerMultiprocessor(                       \
+                         &blocks, dp_i16_kernel<l, k, true>, kWave, 0)                   \
+                   : hipOccupancyMaxActiveBlocksPerMultiprocessor(                       \
+                         &blocks, dp_i16_kernel<l, k, false>, kWave, 0);                 \
+    return e == hipSuccess ? blocks : 0;                                                 \
   }
   SOAPDP_I16_SHAPES(X)
 #undef X

@@ -39,8 +39,10 @@ namespace soapdp {
 
 // The byte-table variant fits five wavefronts per SIMD (96 VGPRs) up to 16
 // columns per lane without spilling once the compiler is asked to.
-template <int L, int K, bool kByte>
-__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(kByte && K <= 16 ? 5 : 1)))
+// kScore: score and end only -- no decision bits, no scratch, no traceback.
+template <int L, int K, bool kByte, bool kScore>
+__global__ __launch_bounds__(kWave)
+__attribute__((amdgpu_waves_per_eu((kByte || kScore) && K <= 16 ? 5 : 1)))
 void dp_i32_kernel(DpParams p) {
   static_assert(kWave % L == 0, "lanes per task must divide the wavefront");
   constexpr int G = kWave / L;       // tasks per wavefront
@@ -57,16 +59,17 @@ void dp_i32_kernel(DpParams p) {
   __shared__ uint8_t s_st[kWave];
   constexpr int B = step_block(K);   // sweep steps per stored block
   // staging buffer of the sweep, or the traceback's block caches
-  __shared__ __align__(16) uint32_t s_lds[StageOrCache<uint32_t, W, B>::kWords];
+  __shared__ __align__(16) uint32_t s_lds[kScore ? 4 : StageOrCache<uint32_t, W, B>::kWords];
 
   // `defer` work items are swept into consecutive slots before one
   // traceback pass serves all their tasks, one lane per task
-  const int32_t defer = min(max(p.defer_dev ? *p.defer_dev : p.defer, 1), kWave / G);
+  const int32_t defer = kScore ? 1 : min(max(p.defer_dev ? *p.defer_dev : p.defer, 1), kWave / G);
   const uint64_t slot_dwords = p.slot_dwords_dev ? *p.slot_dwords_dev : p.slot_dwords;
   uint32_t *const slots = p.scratch + (p.scratch_off_dev ? *p.scratch_off_dev : 0) +
                           (uint64_t)blockIdx.x * slot_dwords * (uint64_t)defer;
   // window rows a slot can hold: (rows + L - 1) steps of W * 64 lanes
-  const int64_t slot_rows = (int64_t)(slot_dwords / (uint64_t)(W * kWave * 1)) - (L - 1);
+  const int64_t slot_rows =
+      kScore ? INT64_MAX : (int64_t)(slot_dwords / (uint64_t)(W * kWave * 1)) - (L - 1);
   int32_t r = 0;   // slot of the current work item
   const int64_t n_tasks = p.task_count ? (int64_t)*p.task_count : p.n_tasks;
   const int32_t *const list = (p.task_list && p.task_off) ? p.task_list + *p.task_off : p.task_list;
@@ -210,12 +213,14 @@ void dp_i32_kernel(DpParams p) {
           el = max(ai, el);
           const int32_t f = max(ad, F[c]);
           const int32_t h = max(max(diag, el), f);
-          uint32_t a = acc[c / 8];
-          a = push_sign(a, ai - el);
-          a = push_sign(a, ad - f);
-          a = push_sign(a, diag - h);
-          a = push_sign(a, f - h);
-          acc[c / 8] = a;
+          if constexpr (!kScore) {
+            uint32_t a = acc[c / 8];
+            a = push_sign(a, ai - el);
+            a = push_sign(a, ad - f);
+            a = push_sign(a, diag - h);
+            a = push_sign(a, f - h);
+            acc[c / 8] = a;
+          }
           H[c] = h;
           F[c] = f;
           hl = h;
@@ -223,17 +228,19 @@ void dp_i32_kernel(DpParams p) {
           // keep each column's decisions next to its scores: without this the
           // optimiser sinks them below all columns and every column's
           // candidates stay live (bounds live registers)
-          asm volatile("" : "+v"(acc[c / 8]));
+          if constexpr (!kScore) asm volatile("" : "+v"(acc[c / 8]));
+          else asm volatile("" : "+v"(H[c]));
           __builtin_amdgcn_sched_barrier(0);
         }
-        if (K % 8) acc[W - 1] <<= 4 * (8 - K % 8);
+        if constexpr (!kScore)
+          if (K % 8) acc[W - 1] <<= 4 * (8 - K % 8);
         hl_out = hl;
         el_out = el;
         // M(i, n) - n S_GE = M^(i, n) + i S_GE
         const int32_t v = H[K - 1] + rge;
         if (last && v > best) { best = v; endi = i; }
       }
-      {
+      if constexpr (!kScore) {
         const int u = t & (B - 1);
         stage_step<uint32_t, W, B>(s_lds, lane, u, acc);
         if (u == B - 1 || t == steps - 1) {   // block complete (or last step)
@@ -266,12 +273,18 @@ void dp_i32_kernel(DpParams p) {
           p.score[tk] = s_score[lane] + tn * p.ge;
           p.ref_end[tk] = tend;
           p.status[tk] = p.ok_status;
-          const int rs = lane / G, gq = lane % G;
-          const uint32_t *slot = slots + (uint64_t)rs * slot_dwords;
-          auto tr = make_tracer<uint32_t, K, W, B>(
-              slot, s_lds + lane * B, gq * L, tpad,
-              [](uint32_t wd, uint32_t c) { return (wd >> (4 * (7 - (c & 7)))) & 15u; });
-          traceback_task(p, tk, tn, tend, (int32_t)slot_rows, tr);
+          if constexpr (kScore) {   // begin and CIGAR are not computed
+            (void)tpad;
+            p.ref_begin[tk] = -1;
+            p.cigar_len[tk] = 0;
+          } else {
+            const int rs = lane / G, gq = lane % G;
+            const uint32_t *slot = slots + (uint64_t)rs * slot_dwords;
+            auto tr = make_tracer<uint32_t, K, W, B>(
+                slot, s_lds + lane * B, gq * L, tpad,
+                [](uint32_t wd, uint32_t c) { return (wd >> (4 * (7 - (c & 7)))) & 15u; });
+            traceback_task(p, tk, tn, tend, (int32_t)slot_rows, tr);
+          }
         }
       }
     }
@@ -303,32 +316,46 @@ const Shape *shapes_i32(int *count) {
   return kShapesI32;
 }
 
+template <int L, int K>
+hipError_t launch_i32(int grid, hipStream_t stream, const DpParams &p, bool byte, bool score) {
+  if (byte && score)
+    hipLaunchKernelGGL((dp_i32_kernel<L, K, true, true>), dim3(grid), dim3(kWave), 0, stream, p);
+  else if (byte)
+    hipLaunchKernelGGL((dp_i32_kernel<L, K, true, false>), dim3(grid), dim3(kWave), 0, stream, p);
+  else if (score)
+    hipLaunchKernelGGL((dp_i32_kernel<L, K, false, true>), dim3(grid), dim3(kWave), 0, stream, p);
+  else
+    hipLaunchKernelGGL((dp_i32_kernel<L, K, false, false>), dim3(grid), dim3(kWave), 0, stream, p);
+  return hipGetLastError();
+}
+
+template <int L, int K>
+int occupancy_i32(bool byte, bool score) {
+  int blocks = 0;
+  hipError_t e;
+  if (byte && score)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, dp_i32_kernel<L, K, true, true>, kWave, 0);
+  else if (byte)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, dp_i32_kernel<L, K, true, false>, kWave, 0);
+  else if (score)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, dp_i32_kernel<L, K, false, true>, kWave, 0);
+  else
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, dp_i32_kernel<L, K, false, false>, kWave, 0);
+  return e == hipSuccess ? blocks : 0;
+}
+
 hipError_t launch_dp_i32(Shape s, int grid, hipStream_t stream, const DpParams &p) {
   const bool byte = byte_delta_fits(p.ma, p.mi, p.ge);
-#define X(l, k)                                                                      \
-  if (s.lanes == l && s.cells == k) {                                                \
-    if (byte)                                                                        \
-      hipLaunchKernelGGL((dp_i32_kernel<l, k, true>), dim3(grid), dim3(kWave), 0, stream, p); \
-    else                                                                             \
-      hipLaunchKernelGGL((dp_i32_kernel<l, k, false>), dim3(grid), dim3(kWave), 0, stream, p); \
-    return hipGetLastError();                                                        \
-  }
+#define X(l, k) \
+  if (s.lanes == l && s.cells == k) return launch_i32<l, k>(grid, stream, p, byte, p.score_only != 0);
   SOAPDP_I32_SHAPES(X)
 #undef X
   return hipErrorInvalidValue;
 }
 
-int occupancy_dp_i32(Shape s, bool byte_delta) {
-  int blocks = 0;
-  hipError_t e = hipErrorInvalidValue;
-#define X(l, k)                                                                            \
-  if (s.lanes == l && s.cells == k) {                                                      \
-    e = byte_delta ? hipOccupancyMaxActiveBlocksPerMultiprocessor(                         \
-                         &blocks, dp_i32_kernel<l, k, true>, kWave, 0)                     \
-                   : hipOccupancyMaxActiveBlocksPerMultiprocessor(                         \
-                         &blocks, dp_i32_kernel<l, k, false>, kWave, 0);                   \
-    return e == hipSuccess ? blocks : 0;                                                   \
-  }
+int occupancy_dp_i32(Shape s, bool byte_delta, bool score_only) {
+#define X(l, k) \
+  if (s.lanes == l && s.cells == k) return occupancy_i32<l, k>(byte_delta, score_only);
   SOAPDP_I32_SHAPES(X)
 #undef X
   return 0;

@@ -60,6 +60,9 @@ struct DpParams {
   // Status written for a task this kernel completes (kTaskOk, or kTaskRedone
   // when the int32 kernel re-runs tasks outside the int16 range).
   uint8_t ok_status;
+  // Nonzero: score and end only (ref_begin -1, cigar_len 0, no CIGAR, no
+  // decision scratch).
+  uint8_t score_only;
 };
 
 // Decision words are stored in blocks of `step_block(K)` sweep steps: within
@@ -110,14 +113,14 @@ __host__ __device__ inline bool int16_fits(int32_t n, int32_t m, int32_t cols, i
 // (byte_delta_fits).
 hipError_t launch_dp_i32(Shape s, int grid, hipStream_t stream, const DpParams &p);
 // Occupancy (workgroups of one wave per CU) of the int32 kernel of shape `s`,
-// byte-table variant or general one.
-int occupancy_dp_i32(Shape s, bool byte_delta);
+// byte-table variant or general one, full or score-only.
+int occupancy_dp_i32(Shape s, bool byte_delta, bool score_only);
 // The compiled int32 shapes.
 const Shape *shapes_i32(int *count);
 
 // Same for the packed int16 kernel (two tasks per lane, lo and hi halves).
 hipError_t launch_dp_i16(Shape s, int grid, hipStream_t stream, const DpParams &p);
-int occupancy_dp_i16(Shape s);
+int occupancy_dp_i16(Shape s, bool score_only);
 const Shape *shapes_i16(int *count);
 // Decision-scratch dwords of one workgroup slot.
 uint64_t slot_dwords_i32(Shape s, int32_t max_m);
