@@ -55,6 +55,8 @@ extern "C" {
 #define SOAP_DP_TASK_OK_REDONE_INT32 2 /* OK; the int16 form's range did not cover this task,
                                           so it was computed by the exact int32 kernel */
 #define SOAP_DP_TASK_INVALID_OFFSET 3  /* read or window lies outside its buffer */
+#define SOAP_DP_TASK_NO_CANDIDATE 4    /* multi-candidate call: the read has no valid
+                                          candidate region */
 
 /* ---- limits ---- */
 #define SOAP_DP_MAX_READ 512      /* n; the paper does not recommend reads over 500 bp */
@@ -196,6 +198,67 @@ int soap_dp_set_class_shape(soap_dp_ctx *ctx, int32_t precision, int32_t capacit
 /* The compiled shapes of a precision (capacity = lanes * cells); returns the
  * count, writes up to n_max. */
 int soap_dp_list_shapes(int32_t precision, soap_dp_class_info *out, int32_t n_max);
+
+/* ------------------------------------------------------------------------
+ * Multi-candidate alignment with an effort limit (paper, Methods section 4:
+ * candidate regions are ranked by their number of supporting seeds and only
+ * the best `ceiling` of them are aligned by dynamic programming).
+ *
+ * Read r owns candidates [cand_start[r], cand_start[r+1]).  A candidate is
+ * valid if 1 <= cand_len <= max_m and its window lies inside ref_codes;
+ * invalid candidates are skipped before ranking.  The valid ones are ranked
+ * by cand_support, highest first, ties by lower candidate index, and the
+ * first min(count, ceiling) are aligned: strand 0 aligns the read, strand 1
+ * its reverse complement (codes 3 - c, reversed), against the window as
+ * stored.  The result is the best of them -- highest score, ties to the
+ * earlier rank -- with its begin, end (window coordinates of that
+ * candidate) and CIGAR, plus the best score among the other aligned
+ * candidates.  Statuses: SOAP_DP_TASK_OK (or OK_REDONE_INT32),
+ * INVALID_LEN / INVALID_OFFSET for the read itself, NO_CANDIDATE.
+ * ------------------------------------------------------------------------ */
+#define SOAP_DP_MAX_CEILING 64
+
+typedef struct {
+  /* reads, DEVICE pointers, caller-owned, as in soap_dp_batch */
+  const uint32_t *read_codes;
+  const uint64_t *read_word_off;
+  const int32_t *read_len;
+  uint64_t read_words;
+  /* candidate regions, DEVICE pointers, caller-owned */
+  const int64_t *cand_start;       /* n_reads + 1 entries, non-decreasing, last = n_cands */
+  const uint64_t *cand_base_off;   /* window start, in bases into ref_codes */
+  const int32_t *cand_len;         /* window length m */
+  const int32_t *cand_support;     /* ranking key (e.g. supporting seeds) */
+  const uint8_t *cand_strand;      /* 0: the read, 1: its reverse complement */
+  const uint32_t *ref_codes;       /* packed sequence the windows index */
+  uint64_t ref_words;
+  int64_t n_reads;
+  int64_t n_cands;
+  int32_t max_n, max_m;            /* bounds on read and window lengths */
+  int32_t ceiling;                 /* 1 .. SOAP_DP_MAX_CEILING */
+} soap_dp_multi_batch;
+
+/* Outputs, DEVICE pointers, caller-owned, n_reads entries each (cigar:
+ * n_reads * cigar_stride words, cigar_stride >= 2 * max_n - 1). */
+typedef struct {
+  int32_t *score;
+  int32_t *ref_begin;
+  int32_t *ref_end;
+  int64_t *best_cand;      /* candidate index of the result, -1 if none */
+  int32_t *second_score;   /* best score of the other aligned candidates, INT32_MIN if none */
+  int32_t *n_aligned;      /* candidates aligned for the read */
+  uint32_t *cigar;
+  int32_t cigar_stride;
+  int32_t *cigar_len;
+  uint8_t *status;
+} soap_dp_multi_result;
+
+/* Enqueue on `stream` like soap_dp_align_batch: all candidates are first
+ * scored (score-only batched form), then each read's best one is aligned
+ * again with traceback.  Same error codes; the context's workspace grows
+ * with n_reads * ceiling. */
+int soap_dp_align_multi(soap_dp_ctx *ctx, const soap_dp_multi_batch *in, const soap_dp_scoring *sc,
+                        const soap_dp_multi_result *out, void *stream);
 
 /* ------------------------------------------------------------------------
  * Serving: continuous batching over a device-resident genome.

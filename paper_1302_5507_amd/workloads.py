@@ -279,6 +279,83 @@ def config5(seed: int = 105, genome_seed: int = 1, n_reads: int = 500_000) -> Wo
     return w
 
 
+@dataclasses.dataclass
+class MultiWorkload:
+    """Reads with lists of candidate regions (the multi-candidate call).
+
+    read_codes, read_off, read_len   the reads (base codes, one per byte)
+    cand_start int64[R+1]  read r owns candidates [cand_start[r], cand_start[r+1])
+    cand_off   int64[C]    window start in ``genome`` (bases)
+    cand_len   int32[C]    window length
+    cand_support int32[C]  ranking key (supporting seeds)
+    cand_strand uint8[C]   1: the read's reverse complement aligns to the window
+    true_cand  int64[R]    the candidate the read was simulated from
+    """
+
+    name: str
+    genome: np.ndarray
+    read_codes: np.ndarray
+    read_off: np.ndarray
+    read_len: np.ndarray
+    cand_start: np.ndarray
+    cand_off: np.ndarray
+    cand_len: np.ndarray
+    cand_support: np.ndarray
+    cand_strand: np.ndarray
+    true_cand: np.ndarray
+    seed: int = 0
+    params: dict = dataclasses.field(default_factory=dict)
+
+    @property
+    def n_reads(self) -> int:
+        return int(self.read_len.size)
+
+    @property
+    def n_cands(self) -> int:
+        return int(self.cand_len.size)
+
+
+def multi_candidate(n_reads: int = 200_000, seed: int = 106, genome_seed: int = 1,
+                    lengths=(100, 150), flank: int = 30, mean_cands: float = 12.0,
+                    max_cands: int = 40, max_support: int = 20) -> MultiWorkload:
+    """Candidate lists per read (stand-in for step 3's seed hits): each read
+    is simulated from a window of n + 2*flank bases with config3's error
+    model and is reverse-complemented with probability 1/2 (its candidate
+    then has strand 1).  A read has 1 + Poisson(mean_cands - 1) candidates
+    (at most max_cands): the true window and random decoy windows of the
+    same length and random strand, in random order; supports are uniform
+    over 1..max_support for all of them, so with a ceiling below the count
+    the true window is sometimes not aligned."""
+    g = random_genome(1_000_000, genome_seed)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    n = rng.choice(np.asarray(lengths), size=n_reads).astype(np.int64)
+    m = n + 2 * flank
+    law = lambda r, idx: r.integers(0, 2 * flank + 1, size=idx.size)
+    w = simulate("multi-true", g, n, m, law, 0.03, 0.005,
+                 lambda r, k: _geometric_trunc(r, 0.25, k, 30), rng)
+    rc = rng.random(n_reads) < 0.5
+    codes = w.read_codes.copy()
+    for r in np.nonzero(rc)[0]:
+        a, b = int(w.read_off[r]), int(w.read_off[r] + w.read_len[r])
+        codes[a:b] = 3 - codes[a:b][::-1]
+    k = np.minimum(1 + rng.poisson(mean_cands - 1.0, size=n_reads), max_cands).astype(np.int64)
+    start = np.concatenate([[0], np.cumsum(k)]).astype(np.int64)
+    C = int(start[-1])
+    owner = np.repeat(np.arange(n_reads), k)
+    cm = m[owner].astype(np.int32)
+    coff = rng.integers(0, len(g) - cm + 1).astype(np.int64)
+    strand = (rng.random(C) < 0.5).astype(np.uint8)
+    support = rng.integers(1, max_support + 1, size=C).astype(np.int32)
+    true_pos = start[:-1] + rng.integers(0, k)          # a random slot of each read's list
+    coff[true_pos] = w.ref_off
+    strand[true_pos] = rc.astype(np.uint8)
+    return MultiWorkload("multi", g, codes, w.read_off.copy(), w.read_len.copy(), start, coff, cm,
+                         support, strand, true_pos.astype(np.int64), seed,
+                         dict(lengths=list(lengths), flank=flank, mean_cands=mean_cands,
+                              max_cands=max_cands, max_support=max_support, p_sub=0.03,
+                              p_ind=0.005, rc_frac=0.5))
+
+
 SERVE_LENGTHS = (50, 75, 100, 150, 250)
 
 
