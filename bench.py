@@ -1,7 +1,7 @@
 """Benchmark: GCUPS with traceback of batched read-vs-window affine-gap
 alignment on one MI355X (seeded synthetic data).
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload config2|config3|config5]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload config2|config3|config5|config4|multi]
 
 Default workload: the mate-rescue batch, 1,000,000 reads x 100 bp against
 250 bp windows, aligned by the plain one-launch int32 kernel (`value`); the
@@ -28,6 +28,7 @@ if ROOT not in sys.path:
 METRIC = "GCUPS w/ traceback, batched vs plain kernel; p50/p99 latency at fixed QPS"
 SCORING = (1, -3, -5, -2)
 OPS_PER_CELL = 14            # 10 score operations + 4 decision comparisons per cell
+OPS_PER_CELL_SCORE = 10      # score-only pass: no decision comparisons
 PEAK_INT32_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12   # CUs x SIMDs x lanes x clock = 39.3 T lane-ops/s
 PEAK_INT16_TOPS = 2 * PEAK_INT32_TOPS            # packed 2 x int16 per lane
 
@@ -170,6 +171,93 @@ def serve_bench(args):
     print(json.dumps(line), flush=True)
 
 
+MULTI_DESC = ("multi-candidate: 200,000 reads of 100 or 150 bp, 1 + Poisson(11) candidate "
+              "windows each (at most 40; n + 60 bp, random strand, support uniform 1..20) "
+              "from a 1 Mbp random genome, the best `ceiling` by support aligned, best and "
+              "second best with the best's CIGAR")
+
+
+def multi_cells(mw, ceiling):
+    """Cells of the aligned (read, candidate) pairs and of the final pass
+    (every candidate of the generated lists is valid)."""
+    k = np.minimum(np.diff(mw.cand_start), ceiling)
+    n = mw.read_len.astype(np.int64)
+    m = n + 2 * int(mw.params["flank"])
+    return int(np.sum(k * n * m)), int(np.sum(np.where(k > 0, n * m, 0)))
+
+
+def multi_bench(args):
+    import torch
+    from paper_1302_5507_amd import binding, workloads
+    mw = workloads.multi_candidate()
+    C = args.ceiling
+    al = binding.Aligner(0)
+    al.autotune(args.tune_cache)
+    dm = binding.DeviceMultiWorkload(mw)
+    res = binding.DeviceMultiResult(mw.n_reads, 2 * dm.max_n)
+    stream = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        al.align_multi(dm, C, SCORING, res=res)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        ev[k][0].record(stream)
+        al.align_multi(dm, C, SCORING, res=res)
+        ev[k][1].record(stream)
+    torch.cuda.synchronize()
+    s = (time.perf_counter() - t0) / args.steps
+    dev_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+    out = res.to_host()
+    assert np.isin(out["status"], (0, 2)).all(), "unaligned reads in bench"
+    cand_cells, final_cells = multi_cells(mw, C)
+    ops = OPS_PER_CELL_SCORE * cand_cells + OPS_PER_CELL * final_cells
+    achieved = ops / (dev_ms * 1e-3) / 1e12
+    line = {
+        "metric": "GCUPS over aligned candidate windows (multi-candidate call, effort limit)",
+        "value": round(cand_cells / s / 1e9, 2),
+        "unit": "GCUPS",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(s * 1e3, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "int16+int32", "data": "synthetic",
+        "config": {"workload": MULTI_DESC, "ceiling": C, "n_reads": mw.n_reads,
+                   "n_cands": mw.n_cands, "candidate_cells": cand_cells,
+                   "final_cells": final_cells, "scoring": list(SCORING)},
+        "reads_per_s": round(mw.n_reads / s, 1),
+        "true_window_found": round(float(np.mean(out["best_cand"] == mw.true_cand)), 5),
+        "roofline": {
+            "bound": "alu", "achieved": round(achieved, 3), "peak": round(PEAK_INT16_TOPS, 1),
+            "unit": "TOP/s", "frac": round(achieved / PEAK_INT16_TOPS, 4), "traffic": None,
+            "ops": f"{OPS_PER_CELL_SCORE}/cell score pass + {OPS_PER_CELL}/cell final pass",
+            "kernel_ms": round(dev_ms, 3),
+        },
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        from oracle import multi as omulti
+        R = min(args.cpu_reads, mw.n_reads)
+        e = int(mw.cand_start[R])
+        threads = oracle.default_threads()
+        t0 = time.perf_counter()
+        omulti.align_multi(mw.read_codes, mw.read_off[:R], mw.read_len[:R], mw.genome,
+                           mw.cand_start[:R + 1], mw.cand_off[:e], mw.cand_len[:e],
+                           mw.cand_support[:e], mw.cand_strand[:e], oracle.scoring(*SCORING),
+                           dm.max_n, dm.max_m, C, n_threads=threads)
+        dt = time.perf_counter() - t0
+        k = np.minimum(np.diff(mw.cand_start[:R + 1]), C)
+        n = mw.read_len[:R].astype(np.int64)
+        cells = int(np.sum(k * n * (n + 2 * int(mw.params["flank"]))))
+        line["cpu_baseline"] = {
+            "value": round(cells / dt / 1e9, 4), "unit": "GCUPS", "cores": threads,
+            "kind": "oracle",
+            "sample": f"first {R:,} reads of the same workload ({cells:.3g} candidate cells), "
+                      f"multi-candidate oracle, {threads} threads, {dt:.1f} s"}
+    print(json.dumps(line), flush=True)
+    al.close()
+
+
 def time_form(al, dw, res, flags, steps, warmup):
     import torch
     stream = torch.cuda.current_stream()
@@ -196,7 +284,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", choices=sorted(WORKLOADS) + ["config4"], default="config2")
+    ap.add_argument("--workload", choices=sorted(WORKLOADS) + ["config4", "multi"],
+                    default="config2")
+    ap.add_argument("--ceiling", type=int, default=30, help="multi workload: candidates aligned per read")
+    ap.add_argument("--cpu-reads", type=int, default=40_000, help="multi workload: oracle sample")
     ap.add_argument("--qps", type=float, default=None, help="served workload: arrival rate (0: saturate)")
     ap.add_argument("--slots", type=int, default=3)
     ap.add_argument("--slot-tasks", type=int, default=131072, help="served workload: reads per slot")
@@ -232,6 +323,9 @@ def main():
 
     if args.workload == "config4":
         serve_bench(args)
+        return
+    if args.workload == "multi":
+        multi_bench(args)
         return
     desc, gen, headline = WORKLOADS[args.workload]
     w = getattr(workloads, gen)()

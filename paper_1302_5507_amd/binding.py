@@ -25,6 +25,9 @@ TASK_OK = 0
 TASK_INVALID_LEN = 1
 TASK_OK_REDONE_INT32 = 2
 TASK_INVALID_OFFSET = 3
+TASK_NO_CANDIDATE = 4
+
+MAX_CEILING = 64
 
 MAX_READ = 512
 MAX_WINDOW = 8192
@@ -37,6 +40,7 @@ EXPORTED = [
     "soap_dp_create", "soap_dp_destroy", "soap_dp_align_batch", "soap_dp_workspace_bytes",
     "soap_dp_reserve", "soap_dp_strerror", "soap_dp_last_hip_error", "soap_dp_autotune",
     "soap_dp_get_classes", "soap_dp_set_class_shape", "soap_dp_list_shapes",
+    "soap_dp_align_multi",
 ]
 
 
@@ -58,6 +62,25 @@ class Result(ctypes.Structure):
                 ("ref_end", ctypes.c_void_p), ("cigar", ctypes.c_void_p),
                 ("cigar_stride", ctypes.c_int32), ("cigar_len", ctypes.c_void_p),
                 ("status", ctypes.c_void_p)]
+
+
+class MultiBatch(ctypes.Structure):
+    _fields_ = [("read_codes", ctypes.c_void_p), ("read_word_off", ctypes.c_void_p),
+                ("read_len", ctypes.c_void_p), ("read_words", ctypes.c_uint64),
+                ("cand_start", ctypes.c_void_p), ("cand_base_off", ctypes.c_void_p),
+                ("cand_len", ctypes.c_void_p), ("cand_support", ctypes.c_void_p),
+                ("cand_strand", ctypes.c_void_p), ("ref_codes", ctypes.c_void_p),
+                ("ref_words", ctypes.c_uint64), ("n_reads", ctypes.c_int64),
+                ("n_cands", ctypes.c_int64), ("max_n", ctypes.c_int32), ("max_m", ctypes.c_int32),
+                ("ceiling", ctypes.c_int32)]
+
+
+class MultiResultABI(ctypes.Structure):
+    _fields_ = [("score", ctypes.c_void_p), ("ref_begin", ctypes.c_void_p),
+                ("ref_end", ctypes.c_void_p), ("best_cand", ctypes.c_void_p),
+                ("second_score", ctypes.c_void_p), ("n_aligned", ctypes.c_void_p),
+                ("cigar", ctypes.c_void_p), ("cigar_stride", ctypes.c_int32),
+                ("cigar_len", ctypes.c_void_p), ("status", ctypes.c_void_p)]
 
 
 class ClassInfo(ctypes.Structure):
@@ -117,6 +140,9 @@ def lib():
         L.soap_dp_set_class_shape.restype = ctypes.c_int
         L.soap_dp_list_shapes.argtypes = [ctypes.c_int32, ctypes.POINTER(ClassInfo), ctypes.c_int32]
         L.soap_dp_list_shapes.restype = ctypes.c_int
+        L.soap_dp_align_multi.argtypes = [vp, ctypes.POINTER(MultiBatch), ctypes.POINTER(Scoring),
+                                          ctypes.POINTER(MultiResultABI), vp]
+        L.soap_dp_align_multi.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -182,6 +208,12 @@ def soap_dp_list_shapes(precision):
     lib().soap_dp_list_shapes(int(precision), arr, n)
     return [arr[k].as_tuple() for k in range(n)]
 
+
+
+def soap_dp_align_multi(ctx, batch: MultiBatch, sc: Scoring, res: MultiResultABI,
+                        stream: int) -> int:
+    return lib().soap_dp_align_multi(ctx, ctypes.byref(batch), ctypes.byref(sc),
+                                     ctypes.byref(res), ctypes.c_void_p(stream))
 
 # ---------------------------------------------------------------- packing
 
@@ -281,6 +313,71 @@ class DeviceResult:
         return out
 
 
+class DeviceMultiWorkload:
+    """Reads and candidate lists resident in device memory (the
+    multi-candidate call's input format)."""
+
+    def __init__(self, w, device="cuda", genome_words=None, max_n=None, max_m=None):
+        import torch
+        dev = torch.device(device)
+        t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+        self.n_reads = w.n_reads
+        self.n_cands = w.n_cands
+        rw, rwo = pack_reads(w.read_codes, w.read_off, w.read_len)
+        self.read_words = t(rw.view(np.int32))
+        self.read_word_off = t(rwo.view(np.int64))
+        self.read_len = t(np.asarray(w.read_len, np.int32))
+        self.cand_start = t(np.asarray(w.cand_start, np.int64))
+        C = max(w.n_cands, 1)
+        pad = lambda a, dt: np.concatenate([np.asarray(a, dt), np.zeros(C - w.n_cands, dt)])
+        self.cand_base_off = t(pad(w.cand_off, np.int64))
+        self.cand_len = t(pad(w.cand_len, np.int32))
+        self.cand_support = t(pad(w.cand_support, np.int32))
+        self.cand_strand = t(pad(w.cand_strand, np.uint8))
+        if genome_words is None:
+            genome_words = t(pack_words(w.genome).view(np.int32))
+        self.ref_words = genome_words
+        nmax = int(np.max(w.read_len)) if w.n_reads else 1
+        mmax = int(np.max(w.cand_len)) if w.n_cands else 1
+        self.max_n = int(max_n or max(1, min(MAX_READ, nmax)))
+        self.max_m = int(max_m or max(1, min(MAX_WINDOW, mmax)))
+
+    def batch(self, ceiling) -> MultiBatch:
+        return MultiBatch(self.read_words.data_ptr(), self.read_word_off.data_ptr(),
+                          self.read_len.data_ptr(), int(self.read_words.numel()),
+                          self.cand_start.data_ptr(), self.cand_base_off.data_ptr(),
+                          self.cand_len.data_ptr(), self.cand_support.data_ptr(),
+                          self.cand_strand.data_ptr(), self.ref_words.data_ptr(),
+                          int(self.ref_words.numel()), self.n_reads, self.n_cands, self.max_n,
+                          self.max_m, int(ceiling))
+
+
+class DeviceMultiResult(DeviceResult):
+    def __init__(self, n_reads, cigar_stride, device="cuda"):
+        import torch
+        super().__init__(n_reads, cigar_stride, device)
+        T = max(int(n_reads), 1)
+        dev = torch.device(device)
+        self.best_cand = torch.full((T,), -2, dtype=torch.int64, device=dev)
+        self.second_score = torch.zeros(T, dtype=torch.int32, device=dev)
+        self.n_aligned = torch.full((T,), -1, dtype=torch.int32, device=dev)
+
+    def abi(self) -> MultiResultABI:
+        return MultiResultABI(self.score.data_ptr(), self.ref_begin.data_ptr(),
+                              self.ref_end.data_ptr(), self.best_cand.data_ptr(),
+                              self.second_score.data_ptr(), self.n_aligned.data_ptr(),
+                              self.cigar.data_ptr(), self.cigar_stride, self.cigar_len.data_ptr(),
+                              self.status.data_ptr())
+
+    def to_host(self):
+        out = super().to_host()
+        T = self.n_tasks
+        out["best_cand"] = self.best_cand.cpu().numpy()[:T]
+        out["second_score"] = self.second_score.cpu().numpy()[:T]
+        out["n_aligned"] = self.n_aligned.cpu().numpy()[:T]
+        return out
+
+
 class Aligner:
     """Owns a library context on one device."""
 
@@ -324,4 +421,16 @@ class Aligner:
                                  stream, flags)
         if rc != SOAP_DP_OK:
             raise SoapDpError(rc, "soap_dp_align_batch")
+        return res
+
+    def align_multi(self, dm: DeviceMultiWorkload, ceiling, scoring=(1, -3, -5, -2), res=None,
+                    stream=None) -> DeviceMultiResult:
+        import torch
+        if res is None:
+            res = DeviceMultiResult(dm.n_reads, 2 * dm.max_n)
+        if stream is None:
+            stream = torch.cuda.current_stream().cuda_stream
+        rc = soap_dp_align_multi(self.ctx, dm.batch(ceiling), Scoring(*scoring), res.abi(), stream)
+        if rc != SOAP_DP_OK:
+            raise SoapDpError(rc, "soap_dp_align_multi")
         return res

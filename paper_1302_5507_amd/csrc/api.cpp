@@ -17,6 +17,7 @@
 #include "../../include/soap_dp.h"
 #include "batch.h"
 #include "dp_internal.h"
+#include "multi.h"
 
 using namespace soapdp;
 
@@ -90,6 +91,9 @@ struct soap_dp_ctx {
   mutable std::unordered_map<uint32_t, int> occupancy;
   uint64_t use_clock = 0;
   bool use_graphs = true;
+  // multi-candidate work arrays (task slots, reverse complements)
+  void *multi = nullptr;
+  size_t multi_bytes = 0;
 };
 
 namespace {
@@ -762,6 +766,56 @@ int autotune(soap_dp_ctx *ctx, std::vector<double> &gcups) {
   return rc;
 }
 
+// Work arrays of a multi-candidate call with R reads, ceiling C and W read
+// words, laid out 256-byte aligned from `base`; returns the bytes needed
+// (with base == nullptr only the size is computed).
+size_t multi_layout(int64_t R, int32_t C, uint64_t W, char *base, MultiWork *w) {
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    char *p = base ? base + off : nullptr;
+    off += (bytes + 255) & ~size_t(255);
+    return p;
+  };
+  const size_t T = size_t(R) * size_t(C);
+  MultiWork m{};
+  m.reads2 = reinterpret_cast<uint32_t *>(take(2 * W * 4));
+  m.t_rwo = reinterpret_cast<uint64_t *>(take(T * 8));
+  m.t_rbo = reinterpret_cast<uint64_t *>(take(T * 8));
+  m.t_rl = reinterpret_cast<int32_t *>(take(T * 4));
+  m.t_ml = reinterpret_cast<int32_t *>(take(T * 4));
+  m.t_cand = reinterpret_cast<int64_t *>(take(T * 8));
+  m.p_score = reinterpret_cast<int32_t *>(take(T * 4));
+  m.p_begin = reinterpret_cast<int32_t *>(take(T * 4));
+  m.p_end = reinterpret_cast<int32_t *>(take(T * 4));
+  m.p_clen = reinterpret_cast<int32_t *>(take(T * 4));
+  m.p_status = reinterpret_cast<uint8_t *>(take(T));
+  m.f_rwo = reinterpret_cast<uint64_t *>(take(size_t(R) * 8));
+  m.f_rbo = reinterpret_cast<uint64_t *>(take(size_t(R) * 8));
+  m.f_rl = reinterpret_cast<int32_t *>(take(size_t(R) * 4));
+  m.f_ml = reinterpret_cast<int32_t *>(take(size_t(R) * 4));
+  m.flag = reinterpret_cast<uint8_t *>(take(size_t(R)));
+  if (w) *w = m;
+  return off;
+}
+
+int ensure_multi(soap_dp_ctx *ctx, size_t bytes) {
+  if (bytes <= ctx->multi_bytes) return SOAP_DP_OK;
+  if (ctx->multi) {
+    if (hipDeviceSynchronize() != hipSuccess) return SOAP_DP_EHIP;
+    (void)hipFree(ctx->multi);
+    ctx->multi = nullptr;
+    ctx->multi_bytes = 0;
+  }
+  clear_graphs(ctx);   // graphs hold pointers into the old arrays
+  if (hipMalloc(&ctx->multi, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    ctx->multi = nullptr;
+    return SOAP_DP_ENOMEM;
+  }
+  ctx->multi_bytes = bytes;
+  return SOAP_DP_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -812,8 +866,63 @@ int soap_dp_destroy(soap_dp_ctx *ctx) {
     if (ctx->small) (void)hipFree(ctx->small);
     if (ctx->task_list) (void)hipFree(ctx->task_list);
     if (ctx->task_class) (void)hipFree(ctx->task_class);
+    if (ctx->multi) (void)hipFree(ctx->multi);
   }
   delete ctx;
+  return SOAP_DP_OK;
+}
+
+int soap_dp_align_multi(soap_dp_ctx *ctx, const soap_dp_multi_batch *in, const soap_dp_scoring *sc,
+                        const soap_dp_multi_result *out, void *stream) {
+  if (!ctx || !in || !out || !scoring_ok(sc)) return SOAP_DP_EINVAL;
+  if (in->n_reads < 0 || in->n_cands < 0 || in->ceiling < 1 || in->ceiling > SOAP_DP_MAX_CEILING)
+    return SOAP_DP_EINVAL;
+  if (in->max_n < 1 || in->max_n > SOAP_DP_MAX_READ || in->max_m < 1 || in->max_m > SOAP_DP_MAX_WINDOW)
+    return SOAP_DP_EINVAL;
+  if (out->cigar_stride < 2 * in->max_n - 1) return SOAP_DP_EINVAL;
+  if (in->n_reads * int64_t(in->ceiling) > (int64_t(1) << 31) - 1) return SOAP_DP_EINVAL;
+  if (in->n_reads == 0) return SOAP_DP_OK;
+  if (!in->read_codes || !in->read_word_off || !in->read_len || !in->cand_start ||
+      (in->n_cands > 0 && (!in->cand_base_off || !in->cand_len || !in->cand_support ||
+                           !in->cand_strand)) ||
+      !in->ref_codes || in->read_words == 0 || in->ref_words == 0)
+    return SOAP_DP_EINVAL;
+  if (!out->score || !out->ref_begin || !out->ref_end || !out->best_cand || !out->second_score ||
+      !out->n_aligned || !out->cigar || !out->cigar_len || !out->status)
+    return SOAP_DP_EINVAL;
+  DeviceGuard dg(ctx->device);
+  const hipStream_t st = static_cast<hipStream_t>(stream);
+  const int32_t C = in->ceiling;
+  int rc = ensure_multi(ctx, multi_layout(in->n_reads, C, in->read_words, nullptr, nullptr));
+  if (rc) return rc;
+  MultiWork w{};
+  multi_layout(in->n_reads, C, in->read_words, static_cast<char *>(ctx->multi), &w);
+  const MultiIn mi{in->read_codes, in->read_word_off, in->read_len, in->read_words, in->cand_start,
+                   in->cand_base_off, in->cand_len, in->cand_support, in->cand_strand,
+                   in->ref_words, in->n_reads, in->n_cands, in->max_n, in->max_m, C};
+  const MultiOut mo{out->score, out->ref_begin, out->ref_end, out->cigar_len, out->status,
+                    out->best_cand, out->second_score, out->n_aligned};
+  // reads and their reverse complements, candidate ranking into task slots
+  hipError_t e = hipMemcpyAsync(w.reads2, in->read_codes, in->read_words * 4,
+                                hipMemcpyDeviceToDevice, st);
+  if (e == hipSuccess) e = launch_revcomp(mi, w, st);
+  if (e == hipSuccess) e = launch_select(mi, w, mo, st);
+  if (e != hipSuccess) return hip_fail(ctx, e);
+  // every ranked (read, candidate) pair, score only
+  const soap_dp_batch b1{w.reads2, w.t_rwo, w.t_rl, in->ref_codes, w.t_rbo, w.t_ml,
+                         in->n_reads * C, in->max_n, in->max_m, 2 * in->read_words, in->ref_words};
+  const soap_dp_result r1{w.p_score, w.p_begin, w.p_end, nullptr, 0, w.p_clen, w.p_status};
+  rc = align_batched(ctx, &b1, sc, &r1, st, true);
+  if (rc) return rc;
+  if ((e = launch_reduce(mi, w, mo, st)) != hipSuccess) return hip_fail(ctx, e);
+  // each read's best pair again, with traceback, into the caller's outputs
+  const soap_dp_batch b2{w.reads2, w.f_rwo, w.f_rl, in->ref_codes, w.f_rbo, w.f_ml,
+                         in->n_reads, in->max_n, in->max_m, 2 * in->read_words, in->ref_words};
+  const soap_dp_result r2{out->score, out->ref_begin, out->ref_end, out->cigar, out->cigar_stride,
+                          out->cigar_len, out->status};
+  rc = align_batched(ctx, &b2, sc, &r2, st, false);
+  if (rc) return rc;
+  if ((e = launch_fixup(mi, w, mo, st)) != hipSuccess) return hip_fail(ctx, e);
   return SOAP_DP_OK;
 }
 

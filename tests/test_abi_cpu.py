@@ -84,3 +84,36 @@ def test_pack_reads_word_aligned():
     for t in range(len(lens)):
         got = _unpack(words[int(woff[t]):], int(lens[t]))
         assert np.array_equal(got, codes[offs[t]:offs[t] + lens[t]])
+
+
+def test_ctypes_structs_match_header_layout(tmp_path):
+    """Every ctypes mirror has the size and field offsets the C compiler gives
+    the header's struct."""
+    from paper_1302_5507_amd import serving
+    pairs = {
+        "soap_dp_scoring": binding.Scoring, "soap_dp_batch": binding.Batch,
+        "soap_dp_result": binding.Result, "soap_dp_class_info": binding.ClassInfo,
+        "soap_dp_multi_batch": binding.MultiBatch, "soap_dp_multi_result": binding.MultiResultABI,
+        "soap_dp_server_config": serving.ServerConfig, "soap_dp_host_result": serving.HostResult,
+        "soap_dp_request": serving.RequestStruct, "soap_dp_server_stats": serving.ServerStats,
+    }
+    lines = ["#include <stddef.h>", "#include <stdio.h>", '#include "soap_dp.h"', "int main(void) {"]
+    for cname, py in pairs.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f in py._fields_:
+            lines.append(f'printf("{cname} {f[0]} %zu\\n", offsetof({cname}, {f[0]}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True, capture_output=True)
+    got = {}
+    for line in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n"):
+        if line:
+            c, f, v = line.split()
+            got[(c, f)] = int(v)
+    for cname, py in pairs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for f in py._fields_:
+            assert got[(cname, f[0])] == getattr(py, f[0]).offset, (cname, f[0])

@@ -1,0 +1,168 @@
+"""GPU: the multi-candidate call (effort limit, paper Methods section 4)
+through the C ABI against the multi-candidate oracle, every output of every
+read: ranking and ceiling, both strands, best with its CIGAR, second best,
+counts, and the statuses of reads without a result."""
+import numpy as np
+import pytest
+
+from oracle import multi as omulti
+import oracle
+from paper_1302_5507_amd import binding, workloads
+from tests.conftest import CONFIG_SCORING
+from tests.gpu_util import aligner
+
+pytestmark = pytest.mark.gpu
+
+
+def _gpu(mw, ceiling, sc=CONFIG_SCORING, max_n=None, max_m=None):
+    import torch
+    dm = binding.DeviceMultiWorkload(mw, max_n=max_n, max_m=max_m)
+    res = aligner().align_multi(dm, ceiling, sc)
+    torch.cuda.synchronize()
+    return res.to_host(), dm
+
+
+def _oracle(mw, ceiling, sc, max_n, max_m):
+    return omulti.align_multi(mw.read_codes, mw.read_off, mw.read_len, mw.genome, mw.cand_start,
+                              mw.cand_off, mw.cand_len, mw.cand_support, mw.cand_strand,
+                              oracle.scoring(*sc), max_n, max_m, ceiling)
+
+
+def _compare(g, ref, label=""):
+    status = np.where(g["status"] == binding.TASK_OK_REDONE_INT32, 0, g["status"])
+    fields = {"status": status, "score": g["score"], "ref_begin": g["ref_begin"],
+              "ref_end": g["ref_end"], "cigar_len": g["cigar_len"], "best_cand": g["best_cand"],
+              "second_score": g["second_score"], "n_aligned": g["n_aligned"]}
+    for f, got in fields.items():
+        r = np.asarray(getattr(ref, f)).astype(np.int64)
+        got = np.asarray(got).astype(np.int64)
+        bad = np.nonzero(got != r)[0]
+        assert bad.size == 0, (f"{label}: {f} differs on {bad.size} reads, first {bad[:5].tolist()} "
+                               f"gpu={got[bad[:5]].tolist()} oracle={r[bad[:5]].tolist()}")
+    cig = g["cigar"].view(np.uint32)
+    for r in range(len(ref.score)):
+        L = int(ref.cigar_len[r])
+        assert np.array_equal(cig[r, :L], ref.cigar_of(r)[:L]), f"{label}: cigar of read {r}"
+
+
+def _run_and_compare(mw, ceiling, sc=CONFIG_SCORING, max_n=None, max_m=None, label=""):
+    g, dm = _gpu(mw, ceiling, sc, max_n, max_m)
+    ref = _oracle(mw, ceiling, sc, dm.max_n, dm.max_m)
+    _compare(g, ref, label)
+    return g, ref
+
+
+@pytest.mark.parametrize("ceiling", [1, 6, 30, 64])
+def test_multi_matches_oracle(ceiling):
+    mw = workloads.multi_candidate(3000, seed=40 + ceiling)
+    g, ref = _run_and_compare(mw, ceiling, label=f"ceiling {ceiling}")
+    assert (ref.status == 0).all()
+    assert ref.n_aligned.max() == min(ceiling, int(np.diff(mw.cand_start).max()))
+
+
+@pytest.mark.parametrize("sc", [(2, -1, -3, -3), (5, -4, -10, 0), tuple(60 * x for x in CONFIG_SCORING)])
+def test_multi_other_scorings(sc):
+    mw = workloads.multi_candidate(1500, seed=51)
+    _run_and_compare(mw, 30, sc, label=f"scoring {sc}")
+
+
+def test_multi_long_candidate_lists():
+    """Reads with hundreds of candidates: the ranking keeps the first 64 of
+    hundreds, with many support ties."""
+    mw = workloads.multi_candidate(400, seed=52, mean_cands=150, max_cands=400, max_support=6)
+    assert np.diff(mw.cand_start).min() > binding.MAX_CEILING
+    for ceiling in (64, 17):
+        _run_and_compare(mw, ceiling, label=f"ceiling {ceiling}")
+
+
+def test_multi_edge_cases():
+    """Reads without candidates, with only invalid candidates (empty, longer
+    than max_m, past the end of the sequence), invalid read lengths (0 and
+    above max_n), all on one strand, in one call."""
+    mw = workloads.multi_candidate(1200, seed=53)
+    rng = np.random.default_rng(53)
+    glen = mw.genome.size
+    cand_len = mw.cand_len.copy()
+    cand_off = mw.cand_off.copy()
+    strand = mw.cand_strand.copy()
+    pick = rng.choice(mw.n_cands, mw.n_cands // 5, replace=False)
+    kind = rng.integers(0, 3, pick.size)
+    cand_len[pick[kind == 0]] = 0
+    cand_len[pick[kind == 1]] = 400                        # above max_m = 260
+    cand_off[pick[kind == 2]] = glen - cand_len[pick[kind == 2]] + 1
+    # every candidate of reads 10..19 invalid; reads 20..29 without candidates
+    for r in range(10, 20):
+        cand_len[mw.cand_start[r]:mw.cand_start[r + 1]] = 0
+    counts = np.diff(mw.cand_start)
+    counts[20:30] = 0
+    keep = np.concatenate([np.arange(mw.cand_start[r], mw.cand_start[r] + counts[r])
+                           for r in range(mw.n_reads)]).astype(np.int64)
+    start = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
+    strand[:] = 1                                          # every candidate on the reverse strand
+    read_len = mw.read_len.copy()
+    read_len[30:40] = 0
+    mw2 = workloads.MultiWorkload("edge", mw.genome, mw.read_codes, mw.read_off, read_len, start,
+                                  cand_off[keep], cand_len[keep], mw.cand_support[keep],
+                                  strand[keep], mw.true_cand)
+    g, ref = _run_and_compare(mw2, 30, max_n=130, max_m=260, label="edge cases")
+    assert (ref.status[10:30] == omulti.NO_CANDIDATE).all()
+    assert (ref.status[30:40] == oracle.INVALID_LEN).all()
+    assert (ref.status[mw2.read_len > 130] == oracle.INVALID_LEN).all()
+    assert (ref.status == 0).sum() > 500
+
+
+def test_multi_workspace_reuse_and_shrink():
+    """Back-to-back calls of different sizes on one context give the same
+    result as the oracle each time (the workspace grows, then is reused)."""
+    big = workloads.multi_candidate(2500, seed=54)
+    small = workloads.multi_candidate(300, seed=55)
+    _run_and_compare(big, 64, label="big")
+    _run_and_compare(small, 8, label="small after big")
+    _run_and_compare(big, 30, label="big again")
+
+
+def test_multi_empty_and_rejected():
+    import torch
+    mw = workloads.multi_candidate(50, seed=56)
+    dm = binding.DeviceMultiWorkload(mw)
+    res = binding.DeviceMultiResult(mw.n_reads, 2 * dm.max_n)
+    ctx = aligner().ctx
+    stream = torch.cuda.current_stream().cuda_stream
+    for bad in (0, binding.MAX_CEILING + 1):
+        rc = binding.soap_dp_align_multi(ctx, dm.batch(bad), binding.Scoring(*CONFIG_SCORING),
+                                         res.abi(), stream)
+        assert rc == binding.SOAP_DP_EINVAL
+    short = binding.DeviceMultiResult(mw.n_reads, 2 * dm.max_n - 2)
+    rc = binding.soap_dp_align_multi(ctx, dm.batch(8), binding.Scoring(*CONFIG_SCORING),
+                                     short.abi(), stream)
+    assert rc == binding.SOAP_DP_EINVAL
+    b = dm.batch(8)
+    b.n_reads = 0
+    rc = binding.soap_dp_align_multi(ctx, b, binding.Scoring(*CONFIG_SCORING), res.abi(), stream)
+    assert rc == binding.SOAP_DP_OK
+    torch.cuda.synchronize()
+    assert (res.status.cpu().numpy() == 255).all()   # nothing written
+
+
+def test_multi_full_size_sampled():
+    """The default 200,000-read candidate workload at ceiling 30, as timed:
+    400 sampled reads recomputed by the oracle."""
+    mw = workloads.multi_candidate()
+    g, dm = _gpu(mw, 30)
+    rng = np.random.default_rng(57)
+    idx = np.sort(rng.choice(mw.n_reads, 400, replace=False))
+    counts = np.diff(mw.cand_start)[idx]
+    keep = np.concatenate([np.arange(mw.cand_start[r], mw.cand_start[r + 1]) for r in idx])
+    sub = workloads.MultiWorkload("sample", mw.genome, mw.read_codes, mw.read_off[idx],
+                                  mw.read_len[idx], np.concatenate([[0], np.cumsum(counts)]),
+                                  mw.cand_off[keep], mw.cand_len[keep], mw.cand_support[keep],
+                                  mw.cand_strand[keep], mw.true_cand[idx])
+    ref = _oracle(sub, 30, CONFIG_SCORING, dm.max_n, dm.max_m)
+    gs = {k: v[idx] for k, v in g.items()}
+    # candidate indices of the sample are local to it
+    local = np.where(ref.best_cand >= 0, keep[np.maximum(ref.best_cand, 0)], -1)
+    ref.best_cand = local
+    _compare(gs, ref, "full size sample")
+    status = np.where(g["status"] == binding.TASK_OK_REDONE_INT32, 0, g["status"])
+    assert (status == 0).all()
+    assert np.mean(g["best_cand"] == mw.true_cand) > 0.97
