@@ -40,8 +40,8 @@ PEAK_INT16_TOPS = 2 * PEAK_INT32_TOPS            # packed 2 x int16 per lane
 KERNEL_SOURCES = ("api.cpp", "batch.h", "batch.hip", "dp_device.h", "dp_i16.hip", "dp_i32.hip",
                   "dp_internal.h")
 TRAFFIC = {
-    ("config2", "plain"): {"fingerprint": "a68ec3b0c49a2c05", "kernel": "dp_i32_kernel<8,13,byte>",
-                           "fetch_kib": 1851808, "write_kib": 16642528,
+    ("config2", "plain"): {"fingerprint": "4c8d088297c63b74", "kernel": "dp_i32_kernel<8,13,byte>",
+                           "fetch_kib": 1850941, "write_kib": 16642495,
                            "fetch_scale": 2.000, "write_scale": 1.000},
 }
 
@@ -302,7 +302,7 @@ def main():
                     help="only run device-to-device copies of BYTES (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build measures one GPU; the tasks are independent and would be "
+        print("bench.py: measures one GPU only; the tasks are independent and would be "
               "split across GPUs by task range with no communication, but no multi-GPU run is "
               "made here", file=sys.stderr)
         sys.exit(2)
