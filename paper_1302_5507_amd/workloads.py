@@ -455,3 +455,100 @@ def from_strings(pairs, pad: int = 0) -> Workload:
     codes = np.concatenate(reads) if reads and n.sum() else np.zeros(0, dtype=np.uint8)
     return Workload("strings", g, codes, roff, n.astype(np.int32), woff, m.astype(np.int32),
                     np.full(len(pairs), -1, dtype=np.int32))
+
+
+# --------------------------------------------------------------------------
+# Read pairs for mate rescue.
+
+ORIENT_SAME = {0: False, 1: True, 2: False, 3: True}   # FR, FF, RF, FF with the mate upstream
+ORIENT_UP = {0: False, 1: False, 2: True, 3: True}
+
+
+@dataclasses.dataclass
+class MateWorkload:
+    """Pairs with one end aligned, for the mate-rescue call.
+
+    read_codes, read_off, read_len   the unaligned ends (as sequenced)
+    mate_pos   int64[R]  leftmost forward-strand base of the aligned end
+    mate_len   int32[R]  its length
+    mate_strand uint8[R] its strand (0 forward, 1 reverse)
+    v, u, orientation    fragment length range and orientation code
+    true_pos   int64[R]  leftmost forward-strand base of the unaligned end
+                         before sequencing errors (-1 for random reads)
+    true_strand uint8[R] its strand
+    frag       int64[R]  simulated fragment length
+    """
+
+    name: str
+    genome: np.ndarray
+    read_codes: np.ndarray
+    read_off: np.ndarray
+    read_len: np.ndarray
+    mate_pos: np.ndarray
+    mate_len: np.ndarray
+    mate_strand: np.ndarray
+    v: int
+    u: int
+    orientation: int
+    true_pos: np.ndarray
+    true_strand: np.ndarray
+    frag: np.ndarray
+    seed: int = 0
+    params: dict = dataclasses.field(default_factory=dict)
+
+    @property
+    def n_reads(self) -> int:
+        return int(self.read_len.size)
+
+
+def mate_pairs(n_pairs: int = 1_000_000, seed: int = 107, genome_seed: int = 1, n: int = 100,
+               n_mapped: int = 100, frag_mean: float = 500.0, frag_sd: float = 50.0,
+               v: int = 425, u: int = 575, orientation: int = 0, p_sub: float = 0.02,
+               p_ind: float = 0.005, random_frac: float = 0.10, genome=None) -> MateWorkload:
+    """Simulated pairs: fragments of length rint(N(frag_mean, frag_sd^2))
+    (at least max(n, n_mapped)) at uniform genome positions.  The aligned
+    end has a random strand and sits at one outer end of its fragment, the
+    unaligned end at the other, as the orientation code says (0 FR: opposite
+    strand, downstream; 1 FF: same strand, downstream; 2 RF: opposite,
+    upstream; 3: same strand, upstream).  The unaligned end is walked from
+    the genome with config2's error model and reverse-complemented when it
+    lies on the reverse strand; random_frac of them are uniform random.
+    The default (1,000,000 pairs of 100 bp, v = 425, u = 575) gives
+    250 bp regions, the mate-rescue batch's shape."""
+    g = random_genome(1_000_000, genome_seed) if genome is None else genome
+    G = len(g)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    R = n_pairs
+    frag = np.rint(rng.normal(frag_mean, frag_sd, size=R)).astype(np.int64)
+    frag = np.maximum(frag, max(n, n_mapped))
+    a = rng.integers(0, G - frag + 1)
+    s = (rng.random(R) < 0.5).astype(np.int64)
+    up = ORIENT_UP[orientation]
+    higher = (s == 0) != up                  # the unaligned end lies toward higher coordinates
+    mate_pos = np.where(higher, a, a + frag - n_mapped)
+    true_pos = np.where(higher, a + frag - n, a)
+    true_strand = s if ORIENT_SAME[orientation] else 1 - s
+    nn = np.full(R, n, dtype=np.int64)
+    # walk each unaligned end forward from its true start (slack for deletions)
+    slack = np.minimum(G - true_pos, n + 64)
+    reads, ok = _walk(rng, g, true_pos, slack, nn, np.zeros(R, np.int64), np.full(R, p_sub),
+                      np.full(R, p_ind), lambda r, k: _geometric_trunc(r, 0.5, k, 0))
+    bad = ~ok
+    if bad.any():   # ran past the slack: redraw those without indels
+        idx = np.nonzero(bad)[0]
+        r2, _ = _walk(rng, g, true_pos[idx], np.full(idx.size, n), nn[idx],
+                      np.zeros(idx.size, np.int64), np.full(idx.size, p_sub),
+                      np.zeros(idx.size), lambda r, k: _geometric_trunc(r, 0.5, k, 0))
+        reads[idx] = r2
+    rev = true_strand == 1
+    reads[rev] = 3 - reads[rev][:, ::-1]
+    rnd = rng.random(R) < random_frac
+    reads[rnd] = rng.integers(0, 4, size=(int(rnd.sum()), n), dtype=np.uint8)
+    tp = np.where(rnd, -1, true_pos)
+    return MateWorkload("mate", g, reads.reshape(-1).astype(np.uint8),
+                        np.arange(R, dtype=np.int64) * n, nn.astype(np.int32),
+                        mate_pos.astype(np.int64), np.full(R, n_mapped, np.int32),
+                        s.astype(np.uint8), v, u, orientation, tp.astype(np.int64),
+                        true_strand.astype(np.uint8), frag, seed,
+                        dict(frag_mean=frag_mean, frag_sd=frag_sd, p_sub=p_sub, p_ind=p_ind,
+                             random_frac=random_frac))
