@@ -1,7 +1,7 @@
 """Benchmark: GCUPS with traceback of batched read-vs-window affine-gap
 alignment on one MI355X (seeded synthetic data).
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload config2|config3|config5|config4|multi]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload config2|config3|config5|config4|multi|mate]
 
 Default workload: the mate-rescue batch, 1,000,000 reads x 100 bp against
 250 bp windows, aligned by the plain one-launch int32 kernel (`value`); the
@@ -258,6 +258,78 @@ def multi_bench(args):
     al.close()
 
 
+MATE_DESC = ("mate rescue: 1,000,000 pairs of 100 bp ends from a 1 Mbp random genome, "
+             "fragments N(500, 50^2), FR orientation, regions for fragments of 425..575 bp "
+             "generated on the device (250 bp), unaligned end with 2% subs, 0.5% indels, 10% "
+             "random")
+
+
+def mate_bench(args):
+    import torch
+    from paper_1302_5507_amd import binding, workloads
+    mw = workloads.mate_pairs()
+    al = binding.Aligner(0)
+    al.autotune(args.tune_cache)
+    dm = binding.DeviceMateWorkload(mw)
+    res = binding.DeviceMateResult(mw.n_reads, 2 * dm.max_n)
+    stream = torch.cuda.current_stream()
+    forms = {}
+    for name, flags in (("batched", binding.BATCHED), ("plain", binding.PLAIN)):
+        for _ in range(args.warmup):
+            al.mate_rescue(dm, SCORING, flags=flags, res=res)
+        torch.cuda.synchronize()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(args.steps)]
+        t0 = time.perf_counter()
+        for k in range(args.steps):
+            ev[k][0].record(stream)
+            al.mate_rescue(dm, SCORING, flags=flags, res=res)
+            ev[k][1].record(stream)
+        torch.cuda.synchronize()
+        s = (time.perf_counter() - t0) / args.steps
+        out = res.to_host()
+        assert np.isin(out["status"], (0, 2)).all(), "unaligned pairs in bench"
+        cells = int(np.dot(mw.read_len.astype(np.int64), out["window_len"].astype(np.int64)))
+        forms[name] = (s, float(np.mean([a.elapsed_time(b) for a, b in ev])), cells, out)
+    s, dev_ms, cells, out = forms["batched"]
+    achieved = OPS_PER_CELL * cells / (dev_ms * 1e-3) / 1e12
+    line = {
+        "metric": "GCUPS w/ traceback, mate rescue with device-side regions",
+        "value": round(cells / s / 1e9, 2), "unit": "GCUPS",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(s * 1e3, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "int16+int32", "data": "synthetic",
+        "config": {"workload": MATE_DESC, "form": "batched", "n_pairs": mw.n_reads, "cells": cells,
+                   "min_frag": mw.v, "max_frag": mw.u, "scoring": list(SCORING)},
+        "mate_found": round(float(np.mean(out["window_off"].astype(np.int64) + out["ref_begin"]
+                                          == mw.true_pos)), 5),
+        "roofline": {"bound": "alu", "achieved": round(achieved, 3),
+                     "peak": round(PEAK_INT16_TOPS, 1), "unit": "TOP/s",
+                     "frac": round(achieved / PEAK_INT16_TOPS, 4), "traffic": None,
+                     "ops_per_cell": OPS_PER_CELL, "kernel_ms": round(dev_ms, 3)},
+        "forms": {f: {"gcups": round(c / fs / 1e9, 2), "ms_per_step": round(fs * 1e3, 3),
+                      "device_ms": round(fk, 3)} for f, (fs, fk, c, _) in forms.items()},
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        from oracle import mate as omate
+        R = min(args.cpu_pairs, mw.n_reads)
+        threads = oracle.default_threads()
+        t0 = time.perf_counter()
+        ref = omate.rescue(mw.read_codes, mw.read_off[:R], mw.read_len[:R], mw.genome,
+                           mw.mate_pos[:R], mw.mate_len[:R], mw.mate_strand[:R], mw.v, mw.u,
+                           mw.orientation, oracle.scoring(*SCORING), dm.max_n, n_threads=threads)
+        dt = time.perf_counter() - t0
+        c = int(np.dot(mw.read_len[:R].astype(np.int64), ref.window_len.astype(np.int64)))
+        line["cpu_baseline"] = {
+            "value": round(c / dt / 1e9, 4), "unit": "GCUPS", "cores": threads, "kind": "oracle",
+            "sample": f"first {R:,} pairs of the same workload ({c:.3g} cells), mate-rescue "
+                      f"oracle (regions in Python, C three-table DP), {threads} threads, {dt:.1f} s"}
+    print(json.dumps(line), flush=True)
+    al.close()
+
+
 def time_form(al, dw, res, flags, steps, warmup):
     import torch
     stream = torch.cuda.current_stream()
@@ -284,10 +356,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", choices=sorted(WORKLOADS) + ["config4", "multi"],
+    ap.add_argument("--workload", choices=sorted(WORKLOADS) + ["config4", "multi", "mate"],
                     default="config2")
     ap.add_argument("--ceiling", type=int, default=30, help="multi workload: candidates aligned per read")
     ap.add_argument("--cpu-reads", type=int, default=160_000, help="multi workload: oracle sample")
+    ap.add_argument("--cpu-pairs", type=int, default=400_000, help="mate workload: oracle sample")
     ap.add_argument("--qps", type=float, default=None, help="served workload: arrival rate (0: saturate)")
     ap.add_argument("--slots", type=int, default=3)
     ap.add_argument("--slot-tasks", type=int, default=131072, help="served workload: reads per slot")
@@ -326,6 +399,9 @@ def main():
         return
     if args.workload == "multi":
         multi_bench(args)
+        return
+    if args.workload == "mate":
+        mate_bench(args)
         return
     desc, gen, headline = WORKLOADS[args.workload]
     w = getattr(workloads, gen)()

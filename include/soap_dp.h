@@ -56,7 +56,8 @@ extern "C" {
                                           so it was computed by the exact int32 kernel */
 #define SOAP_DP_TASK_INVALID_OFFSET 3  /* read or window lies outside its buffer */
 #define SOAP_DP_TASK_NO_CANDIDATE 4    /* multi-candidate call: the read has no valid
-                                          candidate region */
+                                          candidate region; mate rescue: the region
+                                          lies outside the sequence */
 
 /* ---- limits ---- */
 #define SOAP_DP_MAX_READ 512      /* n; the paper does not recommend reads over 500 bp */
@@ -259,6 +260,82 @@ typedef struct {
  * with n_reads * ceiling. */
 int soap_dp_align_multi(soap_dp_ctx *ctx, const soap_dp_multi_batch *in, const soap_dp_scoring *sc,
                         const soap_dp_multi_result *out, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Mate rescue (paper, Results: step 2 of the three-step pipeline; Methods:
+ * paired-end alignment).  For a pair with one end aligned, the other end
+ * is aligned against the region where the expected fragment length range
+ * [min_frag, max_frag] (the -v / -u settings) and the orientation of the
+ * ends place it.  The regions are computed on the device.
+ *
+ * Pair r's aligned end covers forward-strand bases [mate_pos, mate_pos +
+ * mate_len) of ref_codes, on strand mate_strand (0 forward, 1 reverse).  A
+ * fragment runs from the outer end of one read to the outer end of the
+ * other; its length L satisfies min_frag <= L <= max_frag.  The
+ * orientation says where the unaligned end (the mate, length n) lies,
+ * relative to the aligned end: on the same or the opposite strand, and
+ * downstream (further along the aligned end's own strand) or upstream.
+ * The mate lies toward higher coordinates when it is downstream of a
+ * forward end or upstream of a reverse one.  The region is the union of
+ * the mate's placements over all L:
+ *   toward higher coordinates: [mate_pos + min_frag - n, mate_pos + max_frag)
+ *   toward lower coordinates:  [mate_pos + mate_len - max_frag,
+ *                               mate_pos + mate_len - min_frag + n)
+ * clipped to [0, ref_len).  A mate on the reverse strand is aligned as its
+ * reverse complement (codes 3 - c, reversed) against the region as stored.
+ * Outputs: the region's start, length and the mate's strand, and the
+ * alignment in region coordinates (score, begin, end, CIGAR), as from
+ * soap_dp_align_batch.  Statuses: SOAP_DP_TASK_OK (or OK_REDONE_INT32);
+ * INVALID_LEN for n outside 1..max_n or mate_len < 1; INVALID_OFFSET for a
+ * read outside read_codes; NO_CANDIDATE when the clipped region is empty.
+ * Pairs with a non-OK status have zero outputs.
+ * ------------------------------------------------------------------------ */
+#define SOAP_DP_ORIENT_FR 0     /* opposite strand, downstream (Illumina paired ends) */
+#define SOAP_DP_ORIENT_FF 1     /* same strand, downstream (SOLiD) */
+#define SOAP_DP_ORIENT_RF 2     /* opposite strand, upstream (outward-facing) */
+#define SOAP_DP_ORIENT_FF_UP 3  /* same strand, upstream */
+
+typedef struct {
+  /* unaligned ends, DEVICE pointers, caller-owned, as in soap_dp_batch */
+  const uint32_t *read_codes;
+  const uint64_t *read_word_off;
+  const int32_t *read_len;
+  uint64_t read_words;
+  /* aligned ends, DEVICE pointers, caller-owned, n_reads entries each */
+  const uint64_t *mate_pos;     /* leftmost forward-strand base */
+  const int32_t *mate_len;
+  const uint8_t *mate_strand;   /* 0 forward, 1 reverse */
+  /* packed sequence, DEVICE pointer, caller-owned, (ref_len + 15) / 16 words */
+  const uint32_t *ref_codes;
+  uint64_t ref_len;             /* in bases, at most 2^40 */
+  int64_t n_reads;
+  int32_t max_n;                /* bound on the unaligned ends' lengths */
+  int32_t min_frag, max_frag;   /* 1 <= min_frag <= max_frag, and
+                                   max_frag - min_frag + max_n <= SOAP_DP_MAX_WINDOW */
+  int32_t orientation;          /* SOAP_DP_ORIENT_* */
+} soap_dp_mate_batch;
+
+/* Outputs, DEVICE pointers, caller-owned, n_reads entries each (cigar:
+ * n_reads * cigar_stride words, cigar_stride >= 2 * max_n - 1, or NULL with
+ * stride 0 under SOAP_DP_SCORE_ONLY). */
+typedef struct {
+  int32_t *score;
+  int32_t *ref_begin;
+  int32_t *ref_end;
+  uint32_t *cigar;
+  int32_t cigar_stride;
+  int32_t *cigar_len;
+  uint8_t *status;
+  uint64_t *window_off;         /* region start in ref_codes */
+  int32_t *window_len;
+  uint8_t *strand;              /* 1: the read's reverse complement was aligned */
+} soap_dp_mate_result;
+
+/* Enqueue on `stream`.  flags as for soap_dp_align_batch (SOAP_DP_PLAIN or
+ * SOAP_DP_BATCHED, optionally | SOAP_DP_SCORE_ONLY).  Same error codes; the
+ * context's workspace grows with the reads. */
+int soap_dp_mate_rescue(soap_dp_ctx *ctx, const soap_dp_mate_batch *in, const soap_dp_scoring *sc,
+                        const soap_dp_mate_result *out, void *stream, uint32_t flags);
 
 /* ------------------------------------------------------------------------
  * Serving: continuous batching over a device-resident genome.

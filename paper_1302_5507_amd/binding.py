@@ -29,6 +29,8 @@ TASK_NO_CANDIDATE = 4
 
 MAX_CEILING = 64
 
+ORIENT_FR, ORIENT_FF, ORIENT_RF, ORIENT_FF_UP = 0, 1, 2, 3
+
 MAX_READ = 512
 MAX_WINDOW = 8192
 
@@ -40,7 +42,7 @@ EXPORTED = [
     "soap_dp_create", "soap_dp_destroy", "soap_dp_align_batch", "soap_dp_workspace_bytes",
     "soap_dp_reserve", "soap_dp_strerror", "soap_dp_last_hip_error", "soap_dp_autotune",
     "soap_dp_get_classes", "soap_dp_set_class_shape", "soap_dp_list_shapes",
-    "soap_dp_align_multi",
+    "soap_dp_align_multi", "soap_dp_mate_rescue",
 ]
 
 
@@ -81,6 +83,24 @@ class MultiResultABI(ctypes.Structure):
                 ("second_score", ctypes.c_void_p), ("n_aligned", ctypes.c_void_p),
                 ("cigar", ctypes.c_void_p), ("cigar_stride", ctypes.c_int32),
                 ("cigar_len", ctypes.c_void_p), ("status", ctypes.c_void_p)]
+
+
+class MateBatch(ctypes.Structure):
+    _fields_ = [("read_codes", ctypes.c_void_p), ("read_word_off", ctypes.c_void_p),
+                ("read_len", ctypes.c_void_p), ("read_words", ctypes.c_uint64),
+                ("mate_pos", ctypes.c_void_p), ("mate_len", ctypes.c_void_p),
+                ("mate_strand", ctypes.c_void_p), ("ref_codes", ctypes.c_void_p),
+                ("ref_len", ctypes.c_uint64), ("n_reads", ctypes.c_int64),
+                ("max_n", ctypes.c_int32), ("min_frag", ctypes.c_int32),
+                ("max_frag", ctypes.c_int32), ("orientation", ctypes.c_int32)]
+
+
+class MateResultABI(ctypes.Structure):
+    _fields_ = [("score", ctypes.c_void_p), ("ref_begin", ctypes.c_void_p),
+                ("ref_end", ctypes.c_void_p), ("cigar", ctypes.c_void_p),
+                ("cigar_stride", ctypes.c_int32), ("cigar_len", ctypes.c_void_p),
+                ("status", ctypes.c_void_p), ("window_off", ctypes.c_void_p),
+                ("window_len", ctypes.c_void_p), ("strand", ctypes.c_void_p)]
 
 
 class ClassInfo(ctypes.Structure):
@@ -143,6 +163,9 @@ def lib():
         L.soap_dp_align_multi.argtypes = [vp, ctypes.POINTER(MultiBatch), ctypes.POINTER(Scoring),
                                           ctypes.POINTER(MultiResultABI), vp]
         L.soap_dp_align_multi.restype = ctypes.c_int
+        L.soap_dp_mate_rescue.argtypes = [vp, ctypes.POINTER(MateBatch), ctypes.POINTER(Scoring),
+                                          ctypes.POINTER(MateResultABI), vp, ctypes.c_uint32]
+        L.soap_dp_mate_rescue.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -214,6 +237,12 @@ def soap_dp_align_multi(ctx, batch: MultiBatch, sc: Scoring, res: MultiResultABI
                         stream: int) -> int:
     return lib().soap_dp_align_multi(ctx, ctypes.byref(batch), ctypes.byref(sc),
                                      ctypes.byref(res), ctypes.c_void_p(stream))
+
+
+def soap_dp_mate_rescue(ctx, batch: MateBatch, sc: Scoring, res: MateResultABI, stream: int,
+                        flags: int) -> int:
+    return lib().soap_dp_mate_rescue(ctx, ctypes.byref(batch), ctypes.byref(sc),
+                                     ctypes.byref(res), ctypes.c_void_p(stream), int(flags))
 
 # ---------------------------------------------------------------- packing
 
@@ -378,6 +407,65 @@ class DeviceMultiResult(DeviceResult):
         return out
 
 
+class DeviceMateWorkload:
+    """Pairs with one end aligned, resident in device memory (the
+    mate-rescue call's input format)."""
+
+    def __init__(self, w, device="cuda", genome_words=None, max_n=None):
+        import torch
+        dev = torch.device(device)
+        t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+        self.n_reads = w.n_reads
+        rw, rwo = pack_reads(w.read_codes, w.read_off, w.read_len)
+        self.read_words = t(rw.view(np.int32))
+        self.read_word_off = t(rwo.view(np.int64))
+        self.read_len = t(np.asarray(w.read_len, np.int32))
+        self.mate_pos = t(np.asarray(w.mate_pos, np.uint64).view(np.int64))
+        self.mate_len = t(np.asarray(w.mate_len, np.int32))
+        self.mate_strand = t(np.asarray(w.mate_strand, np.uint8))
+        if genome_words is None:
+            genome_words = t(pack_words(w.genome).view(np.int32))
+        self.ref_words = genome_words
+        self.ref_len = int(w.genome.size)
+        nmax = int(np.max(w.read_len)) if w.n_reads else 1
+        self.max_n = int(max_n or max(1, min(MAX_READ, nmax)))
+        self.v, self.u, self.orientation = int(w.v), int(w.u), int(w.orientation)
+
+    def batch(self) -> MateBatch:
+        return MateBatch(self.read_words.data_ptr(), self.read_word_off.data_ptr(),
+                         self.read_len.data_ptr(), int(self.read_words.numel()),
+                         self.mate_pos.data_ptr(), self.mate_len.data_ptr(),
+                         self.mate_strand.data_ptr(), self.ref_words.data_ptr(), self.ref_len,
+                         self.n_reads, self.max_n, self.v, self.u, self.orientation)
+
+
+class DeviceMateResult(DeviceResult):
+    def __init__(self, n_reads, cigar_stride, device="cuda"):
+        import torch
+        super().__init__(n_reads, cigar_stride, device)
+        T = max(int(n_reads), 1)
+        dev = torch.device(device)
+        self.window_off = torch.full((T,), -1, dtype=torch.int64, device=dev)
+        self.window_len = torch.full((T,), -1, dtype=torch.int32, device=dev)
+        self.strand = torch.full((T,), 255, dtype=torch.uint8, device=dev)
+
+    def abi(self) -> MateResultABI:
+        return MateResultABI(self.score.data_ptr(), self.ref_begin.data_ptr(),
+                             self.ref_end.data_ptr(),
+                             self.cigar.data_ptr() if self.cigar_stride else None,
+                             self.cigar_stride, self.cigar_len.data_ptr(), self.status.data_ptr(),
+                             self.window_off.data_ptr(), self.window_len.data_ptr(),
+                             self.strand.data_ptr())
+
+    def to_host(self):
+        out = super().to_host()
+        T = self.n_tasks
+        out["window_off"] = self.window_off.cpu().numpy()[:T].view(np.uint64)
+        out["window_len"] = self.window_len.cpu().numpy()[:T]
+        out["strand"] = self.strand.cpu().numpy()[:T]
+        return out
+
+
 class Aligner:
     """Owns a library context on one device."""
 
@@ -421,6 +509,18 @@ class Aligner:
                                  stream, flags)
         if rc != SOAP_DP_OK:
             raise SoapDpError(rc, "soap_dp_align_batch")
+        return res
+
+    def mate_rescue(self, dm: DeviceMateWorkload, scoring=(1, -3, -5, -2), flags=BATCHED,
+                    res=None, stream=None) -> DeviceMateResult:
+        import torch
+        if res is None:
+            res = DeviceMateResult(dm.n_reads, 0 if flags & SCORE_ONLY else 2 * dm.max_n)
+        if stream is None:
+            stream = torch.cuda.current_stream().cuda_stream
+        rc = soap_dp_mate_rescue(self.ctx, dm.batch(), Scoring(*scoring), res.abi(), stream, flags)
+        if rc != SOAP_DP_OK:
+            raise SoapDpError(rc, "soap_dp_mate_rescue")
         return res
 
     def align_multi(self, dm: DeviceMultiWorkload, ceiling, scoring=(1, -3, -5, -2), res=None,

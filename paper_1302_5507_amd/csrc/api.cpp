@@ -17,6 +17,7 @@
 #include "../../include/soap_dp.h"
 #include "batch.h"
 #include "dp_internal.h"
+#include "mate.h"
 #include "multi.h"
 
 using namespace soapdp;
@@ -798,6 +799,26 @@ size_t multi_layout(int64_t R, int32_t C, uint64_t W, char *base, MultiWork *w) 
   return off;
 }
 
+// Work arrays of a mate-rescue call with R pairs and W read words, laid
+// out like multi_layout.
+size_t mate_layout(int64_t R, uint64_t W, char *base, MateWork *w) {
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    char *p = base ? base + off : nullptr;
+    off += (bytes + 255) & ~size_t(255);
+    return p;
+  };
+  MateWork m{};
+  m.reads2 = reinterpret_cast<uint32_t *>(take(2 * W * 4));
+  m.t_rwo = reinterpret_cast<uint64_t *>(take(size_t(R) * 8));
+  m.t_rbo = reinterpret_cast<uint64_t *>(take(size_t(R) * 8));
+  m.t_rl = reinterpret_cast<int32_t *>(take(size_t(R) * 4));
+  m.t_ml = reinterpret_cast<int32_t *>(take(size_t(R) * 4));
+  m.flag = reinterpret_cast<uint8_t *>(take(size_t(R)));
+  if (w) *w = m;
+  return off;
+}
+
 int ensure_multi(soap_dp_ctx *ctx, size_t bytes) {
   if (bytes <= ctx->multi_bytes) return SOAP_DP_OK;
   if (ctx->multi) {
@@ -923,6 +944,57 @@ int soap_dp_align_multi(soap_dp_ctx *ctx, const soap_dp_multi_batch *in, const s
   rc = align_batched(ctx, &b2, sc, &r2, st, false);
   if (rc) return rc;
   if ((e = launch_fixup(mi, w, mo, st)) != hipSuccess) return hip_fail(ctx, e);
+  return SOAP_DP_OK;
+}
+
+int soap_dp_mate_rescue(soap_dp_ctx *ctx, const soap_dp_mate_batch *in, const soap_dp_scoring *sc,
+                        const soap_dp_mate_result *out, void *stream, uint32_t flags) {
+  if (!ctx || !in || !out || !scoring_ok(sc)) return SOAP_DP_EINVAL;
+  if (flags & ~(SOAP_DP_BATCHED | SOAP_DP_SCORE_ONLY)) return SOAP_DP_EINVAL;
+  const bool score = (flags & SOAP_DP_SCORE_ONLY) != 0;
+  if (in->n_reads < 0 || in->n_reads > (int64_t(1) << 31) - 1) return SOAP_DP_EINVAL;
+  if (in->max_n < 1 || in->max_n > SOAP_DP_MAX_READ) return SOAP_DP_EINVAL;
+  if (in->min_frag < 1 || in->max_frag < in->min_frag ||
+      int64_t(in->max_frag) - in->min_frag + in->max_n > SOAP_DP_MAX_WINDOW)
+    return SOAP_DP_EINVAL;
+  if (in->orientation < SOAP_DP_ORIENT_FR || in->orientation > SOAP_DP_ORIENT_FF_UP)
+    return SOAP_DP_EINVAL;
+  if (in->ref_len < 1 || in->ref_len > (uint64_t(1) << 40)) return SOAP_DP_EINVAL;
+  if (!score && (!out->cigar || out->cigar_stride < 2 * in->max_n - 1)) return SOAP_DP_EINVAL;
+  if (in->n_reads == 0) return SOAP_DP_OK;
+  if (!in->read_codes || !in->read_word_off || !in->read_len || in->read_words == 0 ||
+      !in->mate_pos || !in->mate_len || !in->mate_strand || !in->ref_codes)
+    return SOAP_DP_EINVAL;
+  if (!out->score || !out->ref_begin || !out->ref_end || !out->cigar_len || !out->status ||
+      !out->window_off || !out->window_len || !out->strand)
+    return SOAP_DP_EINVAL;
+  DeviceGuard dg(ctx->device);
+  const hipStream_t st = static_cast<hipStream_t>(stream);
+  int rc = ensure_multi(ctx, mate_layout(in->n_reads, in->read_words, nullptr, nullptr));
+  if (rc) return rc;
+  MateWork w{};
+  mate_layout(in->n_reads, in->read_words, static_cast<char *>(ctx->multi), &w);
+  const MateIn mi{in->read_codes, in->read_word_off, in->read_len, in->read_words, in->mate_pos,
+                  in->mate_len, in->mate_strand, in->ref_len, in->n_reads, in->max_n,
+                  in->min_frag, in->max_frag,
+                  in->orientation == SOAP_DP_ORIENT_FF || in->orientation == SOAP_DP_ORIENT_FF_UP,
+                  in->orientation == SOAP_DP_ORIENT_RF || in->orientation == SOAP_DP_ORIENT_FF_UP};
+  const MateOut mo{out->score, out->ref_begin, out->ref_end, out->cigar_len, out->status,
+                   out->window_off, out->window_len, out->strand};
+  hipError_t e = hipMemcpyAsync(w.reads2, in->read_codes, in->read_words * 4,
+                                hipMemcpyDeviceToDevice, st);
+  if (e == hipSuccess) e = launch_mate_windows(mi, w, mo, st);
+  if (e != hipSuccess) return hip_fail(ctx, e);
+  const soap_dp_batch b{w.reads2, w.t_rwo, w.t_rl, in->ref_codes, w.t_rbo, w.t_ml, in->n_reads,
+                        in->max_n, in->max_frag - in->min_frag + in->max_n, 2 * in->read_words,
+                        (in->ref_len + 15) / 16};
+  const soap_dp_result r{out->score, out->ref_begin, out->ref_end, out->cigar, out->cigar_stride,
+                         out->cigar_len, out->status};
+  if ((rc = batch_ok(&b, &r, score)) != SOAP_DP_OK) return rc;
+  rc = (flags & SOAP_DP_BATCHED) ? align_batched(ctx, &b, sc, &r, st, score)
+                                 : align_plain(ctx, &b, sc, &r, st, score);
+  if (rc) return rc;
+  if ((e = launch_mate_fixup(mi, w, mo, st)) != hipSuccess) return hip_fail(ctx, e);
   return SOAP_DP_OK;
 }
 

@@ -94,6 +94,7 @@ def test_ctypes_structs_match_header_layout(tmp_path):
         "soap_dp_scoring": binding.Scoring, "soap_dp_batch": binding.Batch,
         "soap_dp_result": binding.Result, "soap_dp_class_info": binding.ClassInfo,
         "soap_dp_multi_batch": binding.MultiBatch, "soap_dp_multi_result": binding.MultiResultABI,
+        "soap_dp_mate_batch": binding.MateBatch, "soap_dp_mate_result": binding.MateResultABI,
         "soap_dp_server_config": serving.ServerConfig, "soap_dp_host_result": serving.HostResult,
         "soap_dp_request": serving.RequestStruct, "soap_dp_server_stats": serving.ServerStats,
     }

@@ -1,0 +1,164 @@
+"""GPU: the mate-rescue call (step 2: regions from the aligned end, the
+fragment length range and the orientation, computed on the device) through
+the C ABI against the mate-rescue oracle, every output of every pair, in
+both forms, every orientation, and with the score-only flag."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import mate as omate
+from oracle.multi import NO_CANDIDATE
+from paper_1302_5507_amd import binding, workloads
+from tests.conftest import CONFIG_SCORING
+from tests.gpu_util import aligner
+
+pytestmark = pytest.mark.gpu
+
+
+def _gpu(mw, flags, sc=CONFIG_SCORING, max_n=None):
+    import torch
+    dm = binding.DeviceMateWorkload(mw, max_n=max_n)
+    res = aligner().mate_rescue(dm, sc, flags=flags)
+    torch.cuda.synchronize()
+    return res.to_host(), dm
+
+
+def _oracle(mw, sc, max_n, mate_pos=None, mate_len=None, read_len=None):
+    return omate.rescue(mw.read_codes, mw.read_off,
+                        mw.read_len if read_len is None else read_len, mw.genome,
+                        mw.mate_pos if mate_pos is None else mate_pos,
+                        mw.mate_len if mate_len is None else mate_len, mw.mate_strand, mw.v, mw.u,
+                        mw.orientation, oracle.scoring(*sc), max_n)
+
+
+def _compare(g, ref, score_only=False, label=""):
+    status = np.where(g["status"] == binding.TASK_OK_REDONE_INT32, 0, g["status"])
+    fields = {"status": status, "score": g["score"], "ref_end": g["ref_end"],
+              "window_off": g["window_off"], "window_len": g["window_len"], "strand": g["strand"]}
+    if not score_only:
+        fields.update(ref_begin=g["ref_begin"], cigar_len=g["cigar_len"])
+    for f, got in fields.items():
+        r = np.asarray(getattr(ref, f)).astype(np.int64)
+        got = np.asarray(got).astype(np.int64)
+        bad = np.nonzero(got != r)[0]
+        assert bad.size == 0, (f"{label}: {f} differs on {bad.size} pairs, first {bad[:5].tolist()} "
+                               f"gpu={got[bad[:5]].tolist()} oracle={r[bad[:5]].tolist()}")
+    if score_only:
+        ok = ref.status == 0
+        assert (g["ref_begin"][ok] == -1).all() and (g["cigar_len"][ok] == 0).all()
+        return
+    cig = g["cigar"].view(np.uint32)
+    for r in range(len(ref.score)):
+        L = int(ref.cigar_len[r])
+        assert np.array_equal(cig[r, :L], ref.cigar_of(r)[:L]), f"{label}: cigar of pair {r}"
+
+
+@pytest.mark.parametrize("form", [binding.PLAIN, binding.BATCHED])
+@pytest.mark.parametrize("orient", [binding.ORIENT_FR, binding.ORIENT_FF, binding.ORIENT_RF,
+                                    binding.ORIENT_FF_UP])
+def test_mate_rescue_matches_oracle(form, orient):
+    mw = workloads.mate_pairs(4000, seed=60 + orient, orientation=orient)
+    g, dm = _gpu(mw, form)
+    ref = _oracle(mw, CONFIG_SCORING, dm.max_n)
+    _compare(g, ref, label=f"form {form} orientation {orient}")
+    assert (ref.status == 0).all()
+
+
+@pytest.mark.parametrize("form", [binding.PLAIN, binding.BATCHED])
+def test_mate_rescue_score_only(form):
+    mw = workloads.mate_pairs(3000, seed=64)
+    g, dm = _gpu(mw, form | binding.SCORE_ONLY)
+    ref = _oracle(mw, CONFIG_SCORING, dm.max_n)
+    _compare(g, ref, score_only=True, label="score only")
+
+
+def test_mate_rescue_lengths_and_fragment_ranges():
+    """Mixed read lengths, a wide fragment range (regions of ~1,000 bp) and
+    another scoring."""
+    for k, (n, v, u, sc) in enumerate([(150, 200, 1000, CONFIG_SCORING),
+                                       (36, 100, 130, (2, -1, -3, -3)),
+                                       (250, 300, 900, (1, -3, -5, -2))]):
+        mw = workloads.mate_pairs(1500, seed=70 + k, n=n, n_mapped=n, frag_mean=(v + u) / 2,
+                                  frag_sd=(u - v) / 4, v=v, u=u, orientation=k % 4)
+        for form in (binding.PLAIN, binding.BATCHED):
+            g, dm = _gpu(mw, form, sc)
+            _compare(g, _oracle(mw, sc, dm.max_n), label=f"n={n} v={v} u={u} form {form}")
+
+
+def test_mate_rescue_edge_cases():
+    """Invalid lengths, regions clipped at both ends of the sequence, regions
+    entirely outside it, and aligned-end positions far past its end."""
+    mw = workloads.mate_pairs(2000, seed=75)
+    G = mw.genome.size
+    read_len = mw.read_len.copy()
+    mate_len = mw.mate_len.copy()
+    mate_pos = mw.mate_pos.copy().astype(np.uint64)
+    read_len[0:10] = 0
+    read_len[10:20] = 101                       # above max_n = 100
+    mate_len[20:30] = 0
+    strand = mw.mate_strand.copy()
+    strand[30:40] = 1                           # reverse ends near the start: mate to the left
+    mate_pos[30:40] = np.arange(10) * 40        # clipped at 0 or empty
+    strand[40:50] = 0                           # forward ends near the end: mate to the right
+    mate_pos[40:50] = G - 500 + np.arange(10) * 40   # clipped at G or empty
+    mate_pos[50:55] = G + np.array([0, 1, 500, 10_000, 1 << 40])
+    mate_pos[55:60] = np.uint64((1 << 64) - 1) - np.arange(5, dtype=np.uint64)
+    w2 = workloads.MateWorkload("edge", mw.genome, mw.read_codes, mw.read_off, read_len,
+                                mate_pos, mate_len, strand, mw.v, mw.u, mw.orientation,
+                                mw.true_pos, mw.true_strand, mw.frag)
+    for form in (binding.PLAIN, binding.BATCHED):
+        g, dm = _gpu(w2, form, max_n=100)
+        ref = _oracle(w2, CONFIG_SCORING, 100, mate_pos=[int(x) for x in mate_pos],
+                      mate_len=mate_len, read_len=read_len)
+        _compare(g, ref, label=f"edge form {form}")
+    assert (ref.status[:30] == oracle.INVALID_LEN).all()
+    assert (ref.status[50:60] == NO_CANDIDATE).all()
+    for a in (30, 40):
+        wl = ref.window_len[a:a + 10]
+        assert (ref.status[a:a + 10] == NO_CANDIDATE).any() and ((wl > 0) & (wl < 250)).any()
+
+
+def test_mate_rescue_rejected_arguments():
+    import torch
+    mw = workloads.mate_pairs(20, seed=76)
+    dm = binding.DeviceMateWorkload(mw)
+    res = binding.DeviceMateResult(mw.n_reads, 2 * dm.max_n)
+    ctx = aligner().ctx
+    st = torch.cuda.current_stream().cuda_stream
+    sc = binding.Scoring(*CONFIG_SCORING)
+    for field, value in (("min_frag", 0), ("max_frag", 424), ("orientation", 4),
+                         ("max_frag", 425 + binding.MAX_WINDOW), ("ref_len", 0)):
+        b = dm.batch()
+        setattr(b, field, value)
+        assert binding.soap_dp_mate_rescue(ctx, b, sc, res.abi(), st, binding.BATCHED) == \
+            binding.SOAP_DP_EINVAL, field
+    short = binding.DeviceMateResult(mw.n_reads, 2 * dm.max_n - 2)
+    assert binding.soap_dp_mate_rescue(ctx, dm.batch(), sc, short.abi(), st, binding.PLAIN) == \
+        binding.SOAP_DP_EINVAL
+    assert binding.soap_dp_mate_rescue(ctx, dm.batch(), sc, res.abi(), st, 8) == \
+        binding.SOAP_DP_EINVAL
+    b = dm.batch()
+    b.n_reads = 0
+    assert binding.soap_dp_mate_rescue(ctx, b, sc, res.abi(), st, binding.BATCHED) == \
+        binding.SOAP_DP_OK
+    torch.cuda.synchronize()
+    assert (res.status.cpu().numpy() == 255).all()
+
+
+@pytest.mark.parametrize("form", [binding.PLAIN, binding.BATCHED])
+def test_mate_rescue_full_size_sampled(form):
+    """The default 1,000,000-pair workload, as timed: 2,000 sampled pairs
+    recomputed by the oracle; the mate is found for the pairs whose fragment
+    lies in range."""
+    mw = workloads.mate_pairs()
+    g, dm = _gpu(mw, form)
+    idx = np.sort(np.random.default_rng(77).choice(mw.n_reads, 2000, replace=False))
+    ref = omate.rescue(mw.read_codes, mw.read_off[idx], mw.read_len[idx], mw.genome,
+                       mw.mate_pos[idx], mw.mate_len[idx], mw.mate_strand[idx], mw.v, mw.u,
+                       mw.orientation, oracle.scoring(*CONFIG_SCORING), dm.max_n)
+    _compare({k: v[idx] for k, v in g.items()}, ref, label="full size")
+    status = np.where(g["status"] == binding.TASK_OK_REDONE_INT32, 0, g["status"])
+    assert (status == 0).all()
+    hit = (mw.true_pos >= 0) & (mw.frag >= mw.v) & (mw.frag <= mw.u)
+    found = g["window_off"].astype(np.int64) + g["ref_begin"] == mw.true_pos
+    assert found[hit].mean() > 0.9
