@@ -101,8 +101,11 @@ def test_mate_rescue_edge_cases():
     mate_pos[30:40] = np.arange(10) * 40        # clipped at 0 or empty
     strand[40:50] = 0                           # forward ends near the end: mate to the right
     mate_pos[40:50] = G - 500 + np.arange(10) * 40   # clipped at G or empty
+    strand[50:60] = [0] * 5 + [1] * 5            # past the end in both directions
     mate_pos[50:55] = G + np.array([0, 1, 500, 10_000, 1 << 40])
     mate_pos[55:60] = np.uint64((1 << 64) - 1) - np.arange(5, dtype=np.uint64)
+    mate_pos[60:62] = G + np.array([1, 300])     # reverse ends just past the end: mate inside
+    strand[60:62] = 1
     w2 = workloads.MateWorkload("edge", mw.genome, mw.read_codes, mw.read_off, read_len,
                                 mate_pos, mate_len, strand, mw.v, mw.u, mw.orientation,
                                 mw.true_pos, mw.true_strand, mw.frag)
@@ -112,7 +115,7 @@ def test_mate_rescue_edge_cases():
                       mate_len=mate_len, read_len=read_len)
         _compare(g, ref, label=f"edge form {form}")
     assert (ref.status[:30] == oracle.INVALID_LEN).all()
-    assert (ref.status[50:60] == NO_CANDIDATE).all()
+    assert (ref.status[50:60] == NO_CANDIDATE).all() and (ref.status[60:62] == 0).all()
     for a in (30, 40):
         wl = ref.window_len[a:a + 10]
         assert (ref.status[a:a + 10] == NO_CANDIDATE).any() and ((wl > 0) & (wl < 250)).any()
