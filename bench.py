@@ -360,7 +360,7 @@ def main():
                     default="config2")
     ap.add_argument("--ceiling", type=int, default=30, help="multi workload: candidates aligned per read")
     ap.add_argument("--cpu-reads", type=int, default=160_000, help="multi workload: oracle sample")
-    ap.add_argument("--cpu-pairs", type=int, default=400_000, help="mate workload: oracle sample")
+    ap.add_argument("--cpu-pairs", type=int, default=1_000_000, help="mate workload: oracle sample")
     ap.add_argument("--qps", type=float, default=None, help="served workload: arrival rate (0: saturate)")
     ap.add_argument("--slots", type=int, default=3)
     ap.add_argument("--slot-tasks", type=int, default=131072, help="served workload: reads per slot")
