@@ -58,6 +58,9 @@ extern "C" {
 #define SOAP_DP_TASK_NO_CANDIDATE 4    /* multi-candidate call: the read has no valid
                                           candidate region; mate rescue: the region
                                           lies outside the sequence */
+#define SOAP_DP_TASK_BELOW_CUTOFF 5    /* SOAP_DP_MIN_SCORE: the best score is below
+                                          scoring.min_score; score and ref_end are
+                                          reported, ref_begin is -1, no CIGAR */
 
 /* ---- limits ---- */
 #define SOAP_DP_MAX_READ 512      /* n; the paper does not recommend reads over 500 bp */
@@ -72,19 +75,28 @@ extern "C" {
 #define SOAP_DP_SCORE_ONLY 2u  /* OR-ed with either form: score and ref_end only (same values
                                   as the full call); no traceback: ref_begin is -1, cigar_len
                                   0, `cigar` untouched and may be NULL with any stride */
+#define SOAP_DP_MIN_SCORE 4u   /* OR-ed with either form: a task whose best score is below
+                                  scoring.min_score is reported without traceback, with
+                                  status SOAP_DP_TASK_BELOW_CUTOFF (score and ref_end as
+                                  usual, ref_begin -1, cigar_len 0); the paper's aligner
+                                  accepts an alignment only above a score threshold (its
+                                  default limits for a 100 bp read, one gap of up to 68 bp
+                                  or up to 23 one-base gaps, meet at one threshold) */
 
 /*
  * Scores, all signed and added.  A gap of k bases scores
  * gap_open + (k-1) * gap_extend.  Valid: 0 < match <= 2^14,
  * mismatch < match, gap_open <= gap_extend <= 0, gap_open < 0,
  * |every score| <= 2^14.  (BWA's "open q, extend r" convention maps to
- * gap_open = -(q + r), gap_extend = -r.)
+ * gap_open = -(q + r), gap_extend = -r.)  min_score is read only under
+ * SOAP_DP_MIN_SCORE: scores >= min_score pass.
  */
 typedef struct {
   int32_t match;
   int32_t mismatch;
   int32_t gap_open;
   int32_t gap_extend;
+  int32_t min_score;
 } soap_dp_scoring;
 
 /*
@@ -149,7 +161,8 @@ int soap_dp_destroy(soap_dp_ctx *ctx);
  * Enqueue the alignment of `in` on `stream` (a hipStream_t; NULL is the null
  * stream) and return.  Results are valid once the stream has synchronised.
  * `flags` is SOAP_DP_PLAIN or SOAP_DP_BATCHED (both give identical outputs),
- * optionally OR-ed with SOAP_DP_SCORE_ONLY; other bits are SOAP_DP_EINVAL.
+ * optionally OR-ed with SOAP_DP_SCORE_ONLY and SOAP_DP_MIN_SCORE; other bits
+ * are SOAP_DP_EINVAL.
  * The library keeps no pointer to caller buffers after the work completes.
  * One context serves one stream at a time: calls on a context must not
  * overlap in time on different streams (use one context per stream).

@@ -126,6 +126,27 @@ def align_workload(w, sc: Scoring, cigar_stride=None, n_threads: int = 0, idx=No
                        sc, cigar_stride, n_threads)
 
 
+BELOW_CUTOFF = 5
+
+
+def apply_min_score(res: Result, min_score: int) -> Result:
+    """Score threshold (the paper's aligner accepts an alignment only when
+    its score reaches a threshold; its default limits for a 100 bp read, one
+    gap of up to 68 bp or up to 23 one-base gaps, meet at one such
+    threshold).  A completed task scoring below ``min_score`` keeps its score
+    and end, and gets status BELOW_CUTOFF, begin -1 and no CIGAR.  Returns a
+    new Result."""
+    out = Result(res.score.size, res.cigar.shape[1])
+    for f in ("score", "ref_begin", "ref_end", "cigar", "cigar_len", "status"):
+        getattr(out, f)[...] = getattr(res, f)
+    cut = (res.status == OK) & (res.score < min_score)
+    out.status[cut] = BELOW_CUTOFF
+    out.ref_begin[cut] = -1
+    out.cigar_len[cut] = 0
+    out.cigar[cut] = 0
+    return out
+
+
 def align_pair(R, T, sc: Scoring):
     """(score, ref_begin, ref_end, cigar list of (len, op), status) for one pair."""
     R = np.asarray(R, dtype=np.uint8)

@@ -26,6 +26,7 @@ TASK_INVALID_LEN = 1
 TASK_OK_REDONE_INT32 = 2
 TASK_INVALID_OFFSET = 3
 TASK_NO_CANDIDATE = 4
+TASK_BELOW_CUTOFF = 5
 
 MAX_CEILING = 64
 
@@ -37,6 +38,7 @@ MAX_WINDOW = 8192
 PLAIN = 0
 BATCHED = 1
 SCORE_ONLY = 2   # OR-ed with either form: score and end only
+MIN_SCORE = 4    # OR-ed with either form: tasks below Scoring.min_score skip the traceback
 
 EXPORTED = [
     "soap_dp_create", "soap_dp_destroy", "soap_dp_align_batch", "soap_dp_workspace_bytes",
@@ -47,8 +49,10 @@ EXPORTED = [
 
 
 class Scoring(ctypes.Structure):
+    # min_score is read only under MIN_SCORE
     _fields_ = [("match", ctypes.c_int32), ("mismatch", ctypes.c_int32),
-                ("gap_open", ctypes.c_int32), ("gap_extend", ctypes.c_int32)]
+                ("gap_open", ctypes.c_int32), ("gap_extend", ctypes.c_int32),
+                ("min_score", ctypes.c_int32)]
 
 
 class Batch(ctypes.Structure):
@@ -499,14 +503,19 @@ class Aligner:
             raise SoapDpError(rc, "soap_dp_set_class_shape")
 
     def align(self, dw: DeviceWorkload, scoring=(1, -3, -5, -2), flags=PLAIN, res=None,
-              stream=None, max_n=None, max_m=None) -> DeviceResult:
+              stream=None, max_n=None, max_m=None, min_score=None) -> DeviceResult:
+        """min_score: if given, tasks scoring below it are reported without
+        traceback (status TASK_BELOW_CUTOFF)."""
         import torch
         if res is None:
             res = DeviceResult(dw.n_tasks, 2 * (max_n or dw.max_n))
         if stream is None:
             stream = torch.cuda.current_stream().cuda_stream
-        rc = soap_dp_align_batch(self.ctx, dw.batch(max_n, max_m), Scoring(*scoring), res.abi(),
-                                 stream, flags)
+        sc = Scoring(*scoring)
+        if min_score is not None:
+            sc.min_score = int(min_score)
+            flags |= MIN_SCORE
+        rc = soap_dp_align_batch(self.ctx, dw.batch(max_n, max_m), sc, res.abi(), stream, flags)
         if rc != SOAP_DP_OK:
             raise SoapDpError(rc, "soap_dp_align_batch")
         return res

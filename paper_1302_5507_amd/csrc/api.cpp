@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cstdio>
+#include <cstdint>
 #include <cstdlib>
 #include <cstring>
 #include <iterator>
@@ -117,6 +118,13 @@ bool scoring_ok(const soap_dp_scoring *sc) {
   return in(sc->match) && in(sc->mismatch) && in(sc->gap_open) && in(sc->gap_extend) &&
          sc->match > 0 && sc->mismatch < sc->match && sc->gap_open < 0 &&
          sc->gap_open <= sc->gap_extend && sc->gap_extend <= 0;
+}
+
+// The scoring the kernels see: min_score only counts under SOAP_DP_MIN_SCORE.
+soap_dp_scoring effective_scoring(const soap_dp_scoring *sc, uint32_t flags) {
+  soap_dp_scoring s = *sc;
+  if ((flags & SOAP_DP_MIN_SCORE) == 0) s.min_score = INT32_MIN;
+  return s;
 }
 
 int batch_ok(const soap_dp_batch *in, const soap_dp_result *out, bool score_only) {
@@ -284,6 +292,7 @@ DpParams make_params(const soap_dp_batch *in, const soap_dp_scoring *sc, const s
   p.cigar_len = out->cigar_len;
   p.status = out->status;
   p.ok_status = kTaskOk;
+  p.min_score = sc->min_score;
   p.defer = 1;
   return p;
 }
@@ -705,6 +714,7 @@ double time_shape(soap_dp_ctx *ctx, int prec, Shape s, const TuneData &d, int32_
   p.cigar_len = d.i32 + 3 * d.tasks; p.cigar = d.cigar; p.cigar_stride = 2 * n;
   p.status = d.status;
   p.ok_status = kTaskOk;
+  p.min_score = INT32_MIN;
   const LaunchPlan q = plan_launch(ctx, prec, s, d.tasks, m, kind_for(&sc, false), kScratchCap);
   const int grid = q.grid;
   p.slot_dwords = q.slot_dwords;
@@ -933,7 +943,8 @@ int soap_dp_align_multi(soap_dp_ctx *ctx, const soap_dp_multi_batch *in, const s
   const soap_dp_batch b1{w.reads2, w.t_rwo, w.t_rl, in->ref_codes, w.t_rbo, w.t_ml,
                          in->n_reads * C, in->max_n, in->max_m, 2 * in->read_words, in->ref_words};
   const soap_dp_result r1{w.p_score, w.p_begin, w.p_end, nullptr, 0, w.p_clen, w.p_status};
-  rc = align_batched(ctx, &b1, sc, &r1, st, true);
+  const soap_dp_scoring es = effective_scoring(sc, 0);   // no cutoff here
+  rc = align_batched(ctx, &b1, &es, &r1, st, true);
   if (rc) return rc;
   if ((e = launch_reduce(mi, w, mo, st)) != hipSuccess) return hip_fail(ctx, e);
   // each read's best pair again, with traceback, into the caller's outputs
@@ -941,7 +952,7 @@ int soap_dp_align_multi(soap_dp_ctx *ctx, const soap_dp_multi_batch *in, const s
                          in->n_reads, in->max_n, in->max_m, 2 * in->read_words, in->ref_words};
   const soap_dp_result r2{out->score, out->ref_begin, out->ref_end, out->cigar, out->cigar_stride,
                           out->cigar_len, out->status};
-  rc = align_batched(ctx, &b2, sc, &r2, st, false);
+  rc = align_batched(ctx, &b2, &es, &r2, st, false);
   if (rc) return rc;
   if ((e = launch_fixup(mi, w, mo, st)) != hipSuccess) return hip_fail(ctx, e);
   return SOAP_DP_OK;
@@ -950,7 +961,7 @@ int soap_dp_align_multi(soap_dp_ctx *ctx, const soap_dp_multi_batch *in, const s
 int soap_dp_mate_rescue(soap_dp_ctx *ctx, const soap_dp_mate_batch *in, const soap_dp_scoring *sc,
                         const soap_dp_mate_result *out, void *stream, uint32_t flags) {
   if (!ctx || !in || !out || !scoring_ok(sc)) return SOAP_DP_EINVAL;
-  if (flags & ~(SOAP_DP_BATCHED | SOAP_DP_SCORE_ONLY)) return SOAP_DP_EINVAL;
+  if (flags & ~(SOAP_DP_BATCHED | SOAP_DP_SCORE_ONLY | SOAP_DP_MIN_SCORE)) return SOAP_DP_EINVAL;
   const bool score = (flags & SOAP_DP_SCORE_ONLY) != 0;
   if (in->n_reads < 0 || in->n_reads > (int64_t(1) << 31) - 1) return SOAP_DP_EINVAL;
   if (in->max_n < 1 || in->max_n > SOAP_DP_MAX_READ) return SOAP_DP_EINVAL;
@@ -991,8 +1002,9 @@ int soap_dp_mate_rescue(soap_dp_ctx *ctx, const soap_dp_mate_batch *in, const so
   const soap_dp_result r{out->score, out->ref_begin, out->ref_end, out->cigar, out->cigar_stride,
                          out->cigar_len, out->status};
   if ((rc = batch_ok(&b, &r, score)) != SOAP_DP_OK) return rc;
-  rc = (flags & SOAP_DP_BATCHED) ? align_batched(ctx, &b, sc, &r, st, score)
-                                 : align_plain(ctx, &b, sc, &r, st, score);
+  const soap_dp_scoring es = effective_scoring(sc, flags);
+  rc = (flags & SOAP_DP_BATCHED) ? align_batched(ctx, &b, &es, &r, st, score)
+                                 : align_plain(ctx, &b, &es, &r, st, score);
   if (rc) return rc;
   if ((e = launch_mate_fixup(mi, w, mo, st)) != hipSuccess) return hip_fail(ctx, e);
   return SOAP_DP_OK;
@@ -1002,15 +1014,16 @@ int soap_dp_align_batch(soap_dp_ctx *ctx, const soap_dp_batch *in, const soap_dp
                         const soap_dp_result *out, void *stream, uint32_t flags) {
   if (!ctx) return SOAP_DP_EINVAL;
   if (!scoring_ok(sc)) return SOAP_DP_EINVAL;
-  if (flags & ~(SOAP_DP_BATCHED | SOAP_DP_SCORE_ONLY)) return SOAP_DP_EINVAL;
+  if (flags & ~(SOAP_DP_BATCHED | SOAP_DP_SCORE_ONLY | SOAP_DP_MIN_SCORE)) return SOAP_DP_EINVAL;
   const bool score = (flags & SOAP_DP_SCORE_ONLY) != 0;
   const int rc = batch_ok(in, out, score);
   if (rc) return rc;
   if (in->n_tasks == 0) return SOAP_DP_OK;
   DeviceGuard dg(ctx->device);
   const hipStream_t st = static_cast<hipStream_t>(stream);
-  return (flags & SOAP_DP_BATCHED) ? align_batched(ctx, in, sc, out, st, score)
-                                   : align_plain(ctx, in, sc, out, st, score);
+  const soap_dp_scoring es = effective_scoring(sc, flags);
+  return (flags & SOAP_DP_BATCHED) ? align_batched(ctx, in, &es, out, st, score)
+                                   : align_plain(ctx, in, &es, out, st, score);
 }
 
 size_t soap_dp_workspace_bytes(const soap_dp_ctx *ctx, int64_t n_tasks, int32_t max_n,

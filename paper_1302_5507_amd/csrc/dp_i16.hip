@@ -303,10 +303,15 @@ void dp_i16_kernel(DpParams p) {
           const int rs = lane / TPW, ui = lane % TPW;
           const int h = ui / G, gq = ui % G;
           const int32_t tn = s_n[lane], tpad = s_pad[lane], tend = s_end[lane];
-          p.score[tk] = s_score[lane] + tn * ge;
+          const int32_t tscore = s_score[lane] + tn * ge;
+          p.score[tk] = tscore;
           p.ref_end[tk] = tend;
-          p.status[tk] = p.ok_status;
-          if constexpr (kScore) {   // begin and CIGAR are not computed
+          p.status[tk] = tscore < p.min_score ? kTaskBelowCutoff : p.ok_status;
+          if (tscore < p.min_score) {   // below the cutoff: no traceback
+            (void)tpad;
+            p.ref_begin[tk] = -1;
+            p.cigar_len[tk] = 0;
+          } else if constexpr (kScore) {   // begin and CIGAR are not computed
             (void)rs; (void)h; (void)gq; (void)tpad;
             p.ref_begin[tk] = -1;
             p.cigar_len[tk] = 0;

@@ -270,10 +270,15 @@ void dp_i32_kernel(DpParams p) {
           p.status[tk] = tst;
         } else {
           const int32_t tn = s_n[lane], tpad = s_pad[lane], tend = s_end[lane];
-          p.score[tk] = s_score[lane] + tn * p.ge;
+          const int32_t tscore = s_score[lane] + tn * p.ge;
+          p.score[tk] = tscore;
           p.ref_end[tk] = tend;
-          p.status[tk] = p.ok_status;
-          if constexpr (kScore) {   // begin and CIGAR are not computed
+          p.status[tk] = tscore < p.min_score ? kTaskBelowCutoff : p.ok_status;
+          if (tscore < p.min_score) {   // below the cutoff: no traceback
+            (void)tpad;
+            p.ref_begin[tk] = -1;
+            p.cigar_len[tk] = 0;
+          } else if constexpr (kScore) {   // begin and CIGAR are not computed
             (void)tpad;
             p.ref_begin[tk] = -1;
             p.cigar_len[tk] = 0;

@@ -15,6 +15,7 @@ constexpr uint8_t kTaskOk = 0;
 constexpr uint8_t kTaskInvalidLen = 1;
 constexpr uint8_t kTaskRedone = 2;
 constexpr uint8_t kTaskInvalidOffset = 3;
+constexpr uint8_t kTaskBelowCutoff = 5;
 
 // Arguments of every DP kernel, passed by value.
 struct DpParams {
@@ -63,6 +64,9 @@ struct DpParams {
   // Nonzero: score and end only (ref_begin -1, cigar_len 0, no CIGAR, no
   // decision scratch).
   uint8_t score_only;
+  // Tasks scoring below this get kTaskBelowCutoff and no traceback
+  // (INT32_MIN: no cutoff).
+  int32_t min_score;
 };
 
 // Decision words are stored in blocks of `step_block(K)` sweep steps: within
