@@ -301,7 +301,7 @@ void dp_i32_kernel(DpParams p) {
 // ---------------------------------------------------------------- dispatch
 
 #define SOAPDP_I32_SHAPES(X) \
-  X(1, 8) X(2, 8) X(4, 9) X(4, 13) X(4, 19) X(8, 7) X(8, 10) X(8, 13) X(8, 19) \
+  X(1, 8) X(2, 8) X(4, 9) X(4, 13) X(4, 19) X(4, 25) X(8, 7) X(8, 10) X(8, 13) X(8, 19) \
   X(16, 10) X(16, 16) X(32, 16) X(64, 8)
 
 static const Shape kShapesI32[] = {

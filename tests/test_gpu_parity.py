@@ -34,6 +34,18 @@ def test_every_plain_shape(max_n):
     assert_same(g, oracle_align(w, CONFIG_SCORING, stride=2 * max_n), label=f"max_n={max_n}")
 
 
+@pytest.mark.parametrize("max_n", [100, 104, 150])
+def test_plain_shapes_general_variant(max_n):
+    """A scoring whose offset-form constants do not fit a byte runs the
+    general (compare and select) diagonal in the same shapes."""
+    sc = (5, -4, -10, 0)
+    rng = np.random.default_rng(1000 + max_n)
+    w = workloads.random_tasks(rng, 500, n_range=(max_n - 30, max_n), m_range=(1, 300),
+                               genome_len=20000)
+    g = gpu_align(w, sc, max_n=max_n)
+    assert_same(g, oracle_align(w, sc, stride=2 * max_n), label=f"general max_n={max_n}")
+
+
 def test_edge_lengths():
     rng = np.random.default_rng(5)
     g = rng.integers(0, 4, size=20000).astype(np.uint8)
