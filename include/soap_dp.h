@@ -195,17 +195,21 @@ typedef struct {
 } soap_dp_class_info;
 
 /* Choose the fastest compiled shape for every class by timing each candidate
- * on synthetic reads of the class's capacity on this device.  With a
- * non-NULL `cache_path`, a cache written earlier for the same device kind is
- * loaded instead (unless `force`), and a fresh result is written there
- * (JSON).  Synchronises the device; replaces cached graphs. */
+ * on synthetic reads of the class's capacity on this device, once for the
+ * kernels with traceback and once for the score-only kernels
+ * (SOAP_DP_SCORE_ONLY), which may run a different shape.  With a non-NULL
+ * `cache_path`, a cache written earlier for the same device kind is loaded
+ * instead (unless `force`), and a fresh result is written there (JSON).
+ * Synchronises the device; replaces cached graphs. */
 int soap_dp_autotune(soap_dp_ctx *ctx, const char *cache_path, int force);
 
-/* Copy up to n_max class descriptions; returns the number of classes. */
+/* Copy up to n_max class descriptions (the shapes with traceback); returns
+ * the number of classes. */
 int soap_dp_get_classes(const soap_dp_ctx *ctx, soap_dp_class_info *out, int32_t n_max);
 
-/* Set the shape of the class (precision, capacity); the shape must be a
- * compiled one with lanes * cells >= capacity (see soap_dp_list_shapes). */
+/* Set the shape of the class (precision, capacity), for both kinds of
+ * kernel; the shape must be a compiled one with lanes * cells >= capacity
+ * (see soap_dp_list_shapes). */
 int soap_dp_set_class_shape(soap_dp_ctx *ctx, int32_t precision, int32_t capacity, int32_t lanes,
                             int32_t cells);
 

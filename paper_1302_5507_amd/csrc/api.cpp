@@ -32,10 +32,17 @@ constexpr int kSmallInts = 6 * kMaxClasses + 4 * kMaxClasses;
 constexpr int kGraphCacheMax = 16;
 
 struct ClassSpec {
-  int prec;    // 16 or 32
-  int cap;     // upper bound on read length
-  Shape shape; // current kernel shape
+  int prec;          // 16 or 32
+  int cap;           // upper bound on read length
+  Shape shape;       // kernel shape with traceback
+  Shape score_shape; // kernel shape of the score-only kernels ({0, 0}: as `shape`)
 };
+
+// The shape a class runs with: score-only kernels carry no decision words,
+// so fewer lanes with more columns each can pay off for them.
+Shape shape_of(const ClassSpec &c, bool score) {
+  return score && c.score_shape.lanes ? c.score_shape : c.shape;
+}
 
 // Default classes: int16 by ascending capacity, then the int32 classes that
 // serve tasks outside the int16 range.  Shapes are replaced by the autotuner.
@@ -387,7 +394,7 @@ int align_plain(soap_dp_ctx *ctx, const soap_dp_batch *in, const soap_dp_scoring
 // up to max_n, window up to max_m) falls outside the int16 range of its
 // int16 class.
 std::vector<int> live_classes(const soap_dp_ctx *ctx, int32_t max_n, int32_t max_m,
-                              const soap_dp_scoring *sc) {
+                              const soap_dp_scoring *sc, bool score) {
   std::vector<int> live;
   bool need32 = false;
   int prev16 = 0;
@@ -397,7 +404,8 @@ std::vector<int> live_classes(const soap_dp_ctx *ctx, int32_t max_n, int32_t max
     if (prev16 < max_n) {
       live.push_back(int(k));
       const int32_t n_hi = std::min(c.cap, max_n);
-      if (!int16_fits(n_hi, max_m, c.shape.lanes * c.shape.cells, sc->match, sc->mismatch,
+      const Shape sh = shape_of(c, score);
+      if (!int16_fits(n_hi, max_m, sh.lanes * sh.cells, sc->match, sc->mismatch,
                       sc->gap_open, sc->gap_extend))
         need32 = true;
     }
@@ -436,7 +444,7 @@ BatchedPlan batched_plan(const soap_dp_ctx *ctx, int64_t n_tasks, int32_t max_m,
   uint64_t need = 0, want = 0;
   for (int cls : live) {
     const ClassSpec &c = ctx->classes[size_t(cls)];
-    const LaunchPlan q = plan_launch(ctx, c.prec, c.shape, n_tasks, max_m, k, SIZE_MAX);
+    const LaunchPlan q = plan_launch(ctx, c.prec, shape_of(c, k.score), n_tasks, max_m, k, SIZE_MAX);
     bp.grids.push_back(q.grid);
     need += round64(uint64_t(q.grid) * q.slot_dwords);
     want += round64(uint64_t(q.grid) * uint64_t(q.defer) * q.slot_dwords);
@@ -474,16 +482,17 @@ ClassTable class_table(const soap_dp_ctx *ctx, const std::vector<int> &live,
   ct.count = int32_t(ctx->classes.size());
   for (size_t k = 0; k < ctx->classes.size(); ++k) {
     const ClassSpec &c = ctx->classes[k];
+    const Shape sh = shape_of(c, bp.score);
     ct.cap[k] = c.cap;
-    ct.cols[k] = c.shape.lanes * c.shape.cells;
+    ct.cols[k] = sh.lanes * sh.cells;
     ct.prec[k] = c.prec;
-    ct.per_item[k] = int32_t(tasks_per_item(c.prec, c.shape));
+    ct.per_item[k] = int32_t(tasks_per_item(c.prec, sh));
     ct.grid[k] = 0;
     ct.max_defer[k] = kWave / ct.per_item[k];
-    ct.lanes[k] = c.shape.lanes;
-    ct.step_block[k] = step_block(c.shape.cells);
+    ct.lanes[k] = sh.lanes;
+    ct.step_block[k] = step_block(sh.cells);
     ct.step_dwords[k] =
-        bp.score ? 0 : int32_t(uint64_t((c.shape.cells + 7) / 8) * kWave * (c.prec == 16 ? 2 : 1));
+        bp.score ? 0 : int32_t(uint64_t((sh.cells + 7) / 8) * kWave * (c.prec == 16 ? 2 : 1));
     if (bp.score) ct.max_defer[k] = 1;
   }
   for (size_t li = 0; li < live.size(); ++li) ct.grid[live[li]] = bp.grids[li];
@@ -520,7 +529,7 @@ hipError_t enqueue_batched(soap_dp_ctx *ctx, const soap_dp_batch *in, const soap
     q.scratch_off_dev = b.scratch_off + k;
     q.ok_status = c.prec == 16 ? kTaskOk : kTaskRedone;
     q.score_only = bp.score;
-    if ((e = launch_shape(c.prec, c.shape, bp.grids[li], cs, q)) != hipSuccess) return e;
+    if ((e = launch_shape(c.prec, shape_of(c, bp.score), bp.grids[li], cs, q)) != hipSuccess) return e;
     if ((e = hipEventRecord(ctx->join_events[li], cs)) != hipSuccess) return e;
     if ((e = hipStreamWaitEvent(stream, ctx->join_events[li], 0)) != hipSuccess) return e;
   }
@@ -529,7 +538,7 @@ hipError_t enqueue_batched(soap_dp_ctx *ctx, const soap_dp_batch *in, const soap
 
 int align_batched(soap_dp_ctx *ctx, const soap_dp_batch *in, const soap_dp_scoring *sc,
                   const soap_dp_result *out, hipStream_t stream, bool score) {
-  const std::vector<int> live = live_classes(ctx, in->max_n, in->max_m, sc);
+  const std::vector<int> live = live_classes(ctx, in->max_n, in->max_m, sc, score);
   int rc = ensure_task_buffers(ctx, in->n_tasks);
   if (rc) return rc;
   rc = ensure_class_streams(ctx, live.size());
@@ -647,7 +656,7 @@ bool make_tune_data(TuneData &d, int32_t n, int64_t tasks) {
 
 std::string cache_header(const soap_dp_ctx *ctx) {
   char buf[128];
-  std::snprintf(buf, sizeof buf, "\"arch\": \"%s\", \"cus\": %d, \"version\": 1", ctx->arch.c_str(),
+  std::snprintf(buf, sizeof buf, "\"arch\": \"%s\", \"cus\": %d, \"version\": 2", ctx->arch.c_str(),
                 ctx->cu_count);
   return buf;
 }
@@ -665,13 +674,17 @@ bool load_cache(soap_dp_ctx *ctx, const char *path) {
   size_t pos = 0;
   int found = 0;
   while ((pos = text.find("{\"prec\":", pos)) != std::string::npos) {
-    int prec = 0, cap = 0, lanes = 0, cells = 0;
-    if (std::sscanf(text.c_str() + pos, "{\"prec\": %d, \"cap\": %d, \"lanes\": %d, \"cells\": %d",
-                    &prec, &cap, &lanes, &cells) == 4) {
+    int prec = 0, cap = 0, lanes = 0, cells = 0, sl = 0, sk = 0;
+    if (std::sscanf(text.c_str() + pos,
+                    "{\"prec\": %d, \"cap\": %d, \"lanes\": %d, \"cells\": %d, "
+                    "\"score_lanes\": %d, \"score_cells\": %d",
+                    &prec, &cap, &lanes, &cells, &sl, &sk) == 6) {
       for (auto &c : cls)
         if (c.prec == prec && c.cap == cap && lanes * cells >= cap &&
-            shape_compiled(prec, Shape{lanes, cells})) {
+            shape_compiled(prec, Shape{lanes, cells}) && sl * sk >= cap &&
+            shape_compiled(prec, Shape{sl, sk})) {
           c.shape = Shape{lanes, cells};
+          c.score_shape = Shape{sl, sk};
           ++found;
         }
     }
@@ -682,15 +695,20 @@ bool load_cache(soap_dp_ctx *ctx, const char *path) {
   return true;
 }
 
-bool save_cache(const soap_dp_ctx *ctx, const char *path, const std::vector<double> &gcups) {
+bool save_cache(const soap_dp_ctx *ctx, const char *path, const std::vector<double> &gcups,
+                const std::vector<double> &gcups_score) {
   const std::string tmp = std::string(path) + ".tmp";
   FILE *f = std::fopen(tmp.c_str(), "w");
   if (!f) return false;
   std::fprintf(f, "{%s, \"classes\": [\n", cache_header(ctx).c_str());
   for (size_t k = 0; k < ctx->classes.size(); ++k) {
     const ClassSpec &c = ctx->classes[k];
-    std::fprintf(f, "  {\"prec\": %d, \"cap\": %d, \"lanes\": %d, \"cells\": %d, \"gcups\": %.1f}%s\n",
-                 c.prec, c.cap, c.shape.lanes, c.shape.cells, k < gcups.size() ? gcups[k] : 0.0,
+    const Shape ss = shape_of(c, true);
+    std::fprintf(f,
+                 "  {\"prec\": %d, \"cap\": %d, \"lanes\": %d, \"cells\": %d, \"score_lanes\": %d, "
+                 "\"score_cells\": %d, \"gcups\": %.1f, \"score_gcups\": %.1f}%s\n",
+                 c.prec, c.cap, c.shape.lanes, c.shape.cells, ss.lanes, ss.cells,
+                 k < gcups.size() ? gcups[k] : 0.0, k < gcups_score.size() ? gcups_score[k] : 0.0,
                  k + 1 < ctx->classes.size() ? "," : "");
   }
   std::fprintf(f, "]}\n");
@@ -699,7 +717,8 @@ bool save_cache(const soap_dp_ctx *ctx, const char *path, const std::vector<doub
 }
 
 // Measure one shape on the class's synthetic tasks: best of three launches.
-double time_shape(soap_dp_ctx *ctx, int prec, Shape s, const TuneData &d, int32_t n, hipStream_t st) {
+double time_shape(soap_dp_ctx *ctx, int prec, Shape s, const TuneData &d, int32_t n, hipStream_t st,
+                  bool score) {
   const int32_t m = n + 160;
   soap_dp_scoring sc{1, -3, -5, -2};
   DpParams p{};
@@ -715,7 +734,8 @@ double time_shape(soap_dp_ctx *ctx, int prec, Shape s, const TuneData &d, int32_
   p.status = d.status;
   p.ok_status = kTaskOk;
   p.min_score = INT32_MIN;
-  const LaunchPlan q = plan_launch(ctx, prec, s, d.tasks, m, kind_for(&sc, false), kScratchCap);
+  p.score_only = score;
+  const LaunchPlan q = plan_launch(ctx, prec, s, d.tasks, m, kind_for(&sc, score), kScratchCap);
   const int grid = q.grid;
   p.slot_dwords = q.slot_dwords;
   p.defer = q.defer;
@@ -743,10 +763,11 @@ double time_shape(soap_dp_ctx *ctx, int prec, Shape s, const TuneData &d, int32_
   return double(d.tasks) * double(n) * double(m) / (best_ms * 1e-3) / 1e9;
 }
 
-int autotune(soap_dp_ctx *ctx, std::vector<double> &gcups) {
+int autotune(soap_dp_ctx *ctx, std::vector<double> &gcups, std::vector<double> &gcups_score) {
   hipStream_t st = nullptr;
   if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) return hip_fail(ctx, hipGetLastError());
   gcups.assign(ctx->classes.size(), 0.0);
+  gcups_score.assign(ctx->classes.size(), 0.0);
   int rc = SOAP_DP_OK;
   for (size_t k = 0; k < ctx->classes.size() && rc == SOAP_DP_OK; ++k) {
     ClassSpec &c = ctx->classes[k];
@@ -759,18 +780,21 @@ int autotune(soap_dp_ctx *ctx, std::vector<double> &gcups) {
     if (!make_tune_data(d, n, tasks)) { rc = SOAP_DP_ENOMEM; break; }
     int cnt = 0;
     const Shape *all = c.prec == 16 ? shapes_i16(&cnt) : shapes_i32(&cnt);
-    double best = -1;
-    Shape best_s = c.shape;
-    for (int q = 0; q < cnt; ++q) {
-      const Shape s = all[q];
-      const int cols = s.lanes * s.cells;
-      if (cols < c.cap || cols > c.cap + std::max(c.cap / 6, 8)) continue;
-      if (c.prec == 16 && !int16_fits(n, n + 160, cols, 1, -3, -5, -2)) continue;
-      const double g = time_shape(ctx, c.prec, s, d, n, st);
-      if (g > best) { best = g; best_s = s; }
+    // with traceback, then score only: the best shape of each kind
+    for (int kind = 0; kind < 2; ++kind) {
+      double best = -1;
+      Shape best_s = kind ? shape_of(c, true) : c.shape;
+      for (int q = 0; q < cnt; ++q) {
+        const Shape s = all[q];
+        const int cols = s.lanes * s.cells;
+        if (cols < c.cap || cols > c.cap + std::max(c.cap / 6, 8)) continue;
+        if (c.prec == 16 && !int16_fits(n, n + 160, cols, 1, -3, -5, -2)) continue;
+        const double g = time_shape(ctx, c.prec, s, d, n, st, kind == 1);
+        if (g > best) { best = g; best_s = s; }
+      }
+      (kind ? c.score_shape : c.shape) = best_s;
+      (kind ? gcups_score : gcups)[k] = best;
     }
-    c.shape = best_s;
-    gcups[k] = best;
   }
   (void)hipStreamDestroy(st);
   clear_graphs(ctx);
@@ -1069,10 +1093,10 @@ int soap_dp_autotune(soap_dp_ctx *ctx, const char *cache_path, int force) {
     clear_graphs(ctx);
     return SOAP_DP_OK;
   }
-  std::vector<double> gcups;
-  const int rc = autotune(ctx, gcups);
+  std::vector<double> gcups, gcups_score;
+  const int rc = autotune(ctx, gcups, gcups_score);
   if (rc) return rc;
-  if (cache_path && !save_cache(ctx, cache_path, gcups)) return SOAP_DP_EINVAL;
+  if (cache_path && !save_cache(ctx, cache_path, gcups, gcups_score)) return SOAP_DP_EINVAL;
   return SOAP_DP_OK;
 }
 
@@ -1098,6 +1122,7 @@ int soap_dp_set_class_shape(soap_dp_ctx *ctx, int32_t precision, int32_t capacit
   for (auto &c : ctx->classes)
     if (c.prec == precision && c.cap == capacity) {
       c.shape = s;
+      c.score_shape = s;
       clear_graphs(ctx);
       return SOAP_DP_OK;
     }

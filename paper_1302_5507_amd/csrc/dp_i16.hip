@@ -338,7 +338,8 @@ void dp_i16_kernel(DpParams p) {
 
 #define SOAPDP_I16_SHAPES(X)                                                            \
   X(2, 8) X(4, 4) X(4, 8) X(2, 16) X(4, 10) X(8, 5) X(4, 14) X(8, 7) X(4, 16) X(8, 8)   \
-  X(4, 20) X(8, 10) X(8, 13) X(16, 7) X(8, 16) X(16, 8) X(8, 19) X(16, 10) X(8, 24)     \
+  X(4, 20) X(8, 10) X(8, 13) X(4, 26) X(16, 7) X(8, 16) X(4, 32) X(16, 8) X(8, 19)      \
+  X(16, 10) X(8, 24)                                                                    \
   X(16, 12) X(16, 16) X(32, 8) X(16, 20) X(32, 10) X(16, 24) X(32, 12) X(32, 16) X(64, 8)
 
 static const Shape kShapesI16[] = {

@@ -132,8 +132,12 @@ def test_every_int16_shape(al):
                                        genome_len=20000)
             g = run(al, w, CONFIG_SCORING)
             assert (g["status"] == 0).all()
-            assert_same(g, oracle_align(w, CONFIG_SCORING, stride=2 * cap),
-                        label=f"int16 shape {lanes}x{cells} in class {cap}")
+            ref = oracle_align(w, CONFIG_SCORING, stride=2 * cap)
+            assert_same(g, ref, label=f"int16 shape {lanes}x{cells} in class {cap}")
+            # the score-only kernel of the same shape
+            gs = run(al, w, CONFIG_SCORING, flags=binding.BATCHED | binding.SCORE_ONLY)
+            for f in ("status", "score", "ref_end"):
+                assert np.array_equal(gs[f], getattr(ref, f)), (f, lanes, cells)
             d = [c for c in defaults if c[0] == 16 and c[1] == cap][0]
             al.set_class_shape(16, cap, d[2], d[3])
     finally:
