@@ -772,10 +772,12 @@ int autotune(soap_dp_ctx *ctx, std::vector<double> &gcups, std::vector<double> &
   for (size_t k = 0; k < ctx->classes.size() && rc == SOAP_DP_OK; ++k) {
     ClassSpec &c = ctx->classes[k];
     const int32_t n = c.cap, m = n + 160;
-    // about 3e9 cells, and never fewer than 65,536 tasks: enough work items
-    // that the persistent grid runs many rounds, as it does on real batches
+    // about 1.2e10 cells (a few ms per launch, also for the faster
+    // score-only kernels), and never fewer than 65,536 tasks: enough work
+    // items that the persistent grid runs many rounds, as it does on real
+    // batches
     const int64_t tasks =
-        std::max<int64_t>(65536, std::min<int64_t>(1 << 20, int64_t(3e9 / (double(n) * m))));
+        std::max<int64_t>(65536, std::min<int64_t>(1 << 20, int64_t(1.2e10 / (double(n) * m))));
     TuneData d;
     if (!make_tune_data(d, n, tasks)) { rc = SOAP_DP_ENOMEM; break; }
     int cnt = 0;
@@ -801,19 +803,20 @@ int autotune(soap_dp_ctx *ctx, std::vector<double> &gcups, std::vector<double> &
   return rc;
 }
 
-// Work arrays of a multi-candidate call with R reads, ceiling C and W read
-// words, laid out 256-byte aligned from `base`; returns the bytes needed
-// (with base == nullptr only the size is computed).
-size_t multi_layout(int64_t R, int32_t C, uint64_t W, char *base, MultiWork *w) {
+// Work arrays of a multi-candidate call with R reads, T task slots and W
+// read words, laid out 256-byte aligned from `base`; returns the bytes
+// needed (with base == nullptr only the size is computed).
+size_t multi_layout(int64_t R, int64_t T, uint64_t W, char *base, MultiWork *w) {
   size_t off = 0;
   auto take = [&](size_t bytes) {
     char *p = base ? base + off : nullptr;
     off += (bytes + 255) & ~size_t(255);
     return p;
   };
-  const size_t T = size_t(R) * size_t(C);
   MultiWork m{};
   m.reads2 = reinterpret_cast<uint32_t *>(take(2 * W * 4));
+  m.off = reinterpret_cast<int64_t *>(take(size_t(R + 1) * 8));
+  m.bsum = reinterpret_cast<int64_t *>(take(size_t(R / 1024 + 2) * 8));
   m.t_rwo = reinterpret_cast<uint64_t *>(take(T * 8));
   m.t_rbo = reinterpret_cast<uint64_t *>(take(T * 8));
   m.t_rl = reinterpret_cast<int32_t *>(take(T * 4));
@@ -935,7 +938,10 @@ int soap_dp_align_multi(soap_dp_ctx *ctx, const soap_dp_multi_batch *in, const s
   if (in->max_n < 1 || in->max_n > SOAP_DP_MAX_READ || in->max_m < 1 || in->max_m > SOAP_DP_MAX_WINDOW)
     return SOAP_DP_EINVAL;
   if (out->cigar_stride < 2 * in->max_n - 1) return SOAP_DP_EINVAL;
-  if (in->n_reads * int64_t(in->ceiling) > (int64_t(1) << 31) - 1) return SOAP_DP_EINVAL;
+  if (in->n_reads > (int64_t(1) << 31) - 1 || in->n_cands > (int64_t(1) << 40)) return SOAP_DP_EINVAL;
+  // task slots: at most one per candidate, at most `ceiling` per read
+  const int64_t T = std::min<int64_t>(in->n_cands, in->n_reads * int64_t(in->ceiling));
+  if (T > (int64_t(1) << 31) - 1) return SOAP_DP_EINVAL;
   if (in->n_reads == 0) return SOAP_DP_OK;
   if (!in->read_codes || !in->read_word_off || !in->read_len || !in->cand_start ||
       (in->n_cands > 0 && (!in->cand_base_off || !in->cand_len || !in->cand_support ||
@@ -948,13 +954,13 @@ int soap_dp_align_multi(soap_dp_ctx *ctx, const soap_dp_multi_batch *in, const s
   DeviceGuard dg(ctx->device);
   const hipStream_t st = static_cast<hipStream_t>(stream);
   const int32_t C = in->ceiling;
-  int rc = ensure_multi(ctx, multi_layout(in->n_reads, C, in->read_words, nullptr, nullptr));
+  int rc = ensure_multi(ctx, multi_layout(in->n_reads, T, in->read_words, nullptr, nullptr));
   if (rc) return rc;
   MultiWork w{};
-  multi_layout(in->n_reads, C, in->read_words, static_cast<char *>(ctx->multi), &w);
+  multi_layout(in->n_reads, T, in->read_words, static_cast<char *>(ctx->multi), &w);
   const MultiIn mi{in->read_codes, in->read_word_off, in->read_len, in->read_words, in->cand_start,
                    in->cand_base_off, in->cand_len, in->cand_support, in->cand_strand,
-                   in->ref_words, in->n_reads, in->n_cands, in->max_n, in->max_m, C};
+                   in->ref_words, in->n_reads, in->n_cands, in->max_n, in->max_m, C, T};
   const MultiOut mo{out->score, out->ref_begin, out->ref_end, out->cigar_len, out->status,
                     out->best_cand, out->second_score, out->n_aligned};
   // reads and their reverse complements, candidate ranking into task slots
@@ -965,11 +971,10 @@ int soap_dp_align_multi(soap_dp_ctx *ctx, const soap_dp_multi_batch *in, const s
   if (e != hipSuccess) return hip_fail(ctx, e);
   // every ranked (read, candidate) pair, score only
   const soap_dp_batch b1{w.reads2, w.t_rwo, w.t_rl, in->ref_codes, w.t_rbo, w.t_ml,
-                         in->n_reads * C, in->max_n, in->max_m, 2 * in->read_words, in->ref_words};
+                         T, in->max_n, in->max_m, 2 * in->read_words, in->ref_words};
   const soap_dp_result r1{w.p_score, w.p_begin, w.p_end, nullptr, 0, w.p_clen, w.p_status};
   const soap_dp_scoring es = effective_scoring(sc, 0);   // no cutoff here
-  rc = align_batched(ctx, &b1, &es, &r1, st, true);
-  if (rc) return rc;
+  if (T > 0 && (rc = align_batched(ctx, &b1, &es, &r1, st, true)) != SOAP_DP_OK) return rc;
   if ((e = launch_reduce(mi, w, mo, st)) != hipSuccess) return hip_fail(ctx, e);
   // each read's best pair again, with traceback, into the caller's outputs
   const soap_dp_batch b2{w.reads2, w.f_rwo, w.f_rl, in->ref_codes, w.f_rbo, w.f_ml,

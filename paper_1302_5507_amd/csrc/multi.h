@@ -19,13 +19,18 @@ struct MultiIn {
   uint64_t ref_words;
   int64_t n_reads, n_cands;
   int32_t max_n, max_m, ceiling;
+  int64_t n_slots;   // task slots: min(n_cands, n_reads * ceiling)
 };
 
-// Work arrays: one task per (read, rank) slot, task r * ceiling + k; the
-// read buffer `reads2` holds the reads (words [0, read_words)) and their
-// reverse complements at the same offsets plus read_words.
+// Work arrays.  Tasks are dense: read r's ranked candidates are tasks
+// off[r] .. off[r] + n_aligned[r] - 1 (rank order), and slots from
+// off[n_reads] on are zero-length.  The read buffer `reads2` holds the reads
+// (words [0, read_words)) and their reverse complements at the same offsets
+// plus read_words.
 struct MultiWork {
   uint32_t *reads2;
+  int64_t *off;    // n_reads + 1 task offsets
+  int64_t *bsum;   // per block of reads: count, then its exclusive offset
   uint64_t *t_rwo, *t_rbo;
   int32_t *t_rl, *t_ml;
   int64_t *t_cand;
@@ -48,7 +53,8 @@ struct MultiOut {
 // Reverse complements of the valid reads into reads2 (after the reads were
 // copied there).
 hipError_t launch_revcomp(const MultiIn &in, const MultiWork &w, hipStream_t stream);
-// Rank and keep each read's best candidates; fill the task slots.
+// Count, place and rank each read's candidates under the ceiling; fill the
+// task slots.
 hipError_t launch_select(const MultiIn &in, const MultiWork &w, const MultiOut &out,
                          hipStream_t stream);
 // Best and second best per read from the score-only pass; final tasks.

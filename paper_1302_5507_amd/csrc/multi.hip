@@ -11,7 +11,7 @@ namespace soapdp {
 
 namespace {
 
-constexpr int kBlock = 64;
+constexpr int kBlock = 256;
 
 __device__ __forceinline__ bool read_ok(const MultiIn &in, int64_t r, uint8_t *status) {
   const int32_t n = in.read_len[r];
@@ -49,65 +49,140 @@ __global__ __launch_bounds__(kBlock) void revcomp_kernel(MultiIn in, MultiWork w
   }
 }
 
-// Rank the valid candidates of read r by (support desc, index asc) and keep
-// the first `ceiling` in a sorted list in LDS; candidates arrive in index
-// order, so equal support never moves a later one ahead.
-__global__ __launch_bounds__(kBlock) void select_kernel(MultiIn in, MultiWork w, MultiOut out) {
-  // list entry k of thread x at [k][x]: the threads of a wavefront touch
-  // consecutive words
-  __shared__ int64_t s_idx[SOAP_DP_MAX_CEILING][kBlock];
-  __shared__ int32_t s_sup[SOAP_DP_MAX_CEILING][kBlock];
+__device__ __forceinline__ bool cand_ok(const MultiIn &in, int64_t c) {
+  const int32_t m = in.cand_len[c];
+  return m >= 1 && m <= in.max_m && in.cand_base_off[c] + (uint64_t)m <= in.ref_words * 16;
+}
+
+// Per read: validity and the number of valid candidates kept under the
+// ceiling (its task count).
+__global__ __launch_bounds__(kBlock) void count_kernel(MultiIn in, MultiWork w, MultiOut out) {
   const int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (r >= in.n_reads) return;
-  const int x = threadIdx.x;
-  auto idx = [&](int32_t k) -> int64_t & { return s_idx[k][x]; };
-  auto sup = [&](int32_t k) -> int32_t & { return s_sup[k][x]; };
-  const int32_t C = in.ceiling;
   uint8_t st;
-  int32_t cnt = 0;
+  int64_t valid = 0;
   if (read_ok(in, r, &st)) {
     const int64_t a = in.cand_start[r], b = in.cand_start[r + 1];
-    if (a < 0 || b < a || b > in.n_cands) {
+    if (a < 0 || b < a || b > in.n_cands)
       st = kTaskInvalidOffset;
-    } else {
-      for (int64_t c = a; c < b; ++c) {
-        const int32_t m = in.cand_len[c];
-        if (m < 1 || m > in.max_m || in.cand_base_off[c] + (uint64_t)m > in.ref_words * 16) continue;
-        const int32_t s = in.cand_support[c];
-        if (cnt == C && s <= sup(C - 1)) continue;
-        int32_t k = cnt < C ? cnt : C - 1;
-        while (k > 0 && sup(k - 1) < s) {
-          idx(k) = idx(k - 1);
-          sup(k) = sup(k - 1);
-          --k;
-        }
-        idx(k) = c;
-        sup(k) = s;
-        if (cnt < C) ++cnt;
-      }
-    }
+    else
+      for (int64_t c = a; c < b; ++c) valid += cand_ok(in, c) ? 1 : 0;
   }
-  const int32_t n = in.read_len[r];
-  const uint64_t off = in.read_word_off[r];
-  for (int32_t k = 0; k < C; ++k) {
-    const int64_t t = r * C + k;
-    if (k < cnt) {
-      const int64_t c = idx(k);
-      w.t_rwo[t] = off + (in.cand_strand[c] ? in.read_words : 0);
-      w.t_rl[t] = n;
-      w.t_rbo[t] = in.cand_base_off[c];
-      w.t_ml[t] = in.cand_len[c];
-      w.t_cand[t] = c;
-    } else {   // empty slot: a zero-length task the batched form skips
-      w.t_rwo[t] = 0;
-      w.t_rl[t] = 0;
-      w.t_rbo[t] = 0;
-      w.t_ml[t] = 0;
-      w.t_cand[t] = -1;
-    }
-  }
+  const int32_t cnt = st == kTaskOk ? (int32_t)min(valid, (int64_t)in.ceiling) : 0;
   out.n_aligned[r] = cnt;
   w.flag[r] = st != kTaskOk ? st : (cnt == 0 ? (uint8_t)SOAP_DP_TASK_NO_CANDIDATE : kTaskOk);
+}
+
+// Exclusive scan of the task counts in three steps: within blocks of
+// kScanBlock reads, over the block sums (one workgroup), then the block
+// offsets added back.
+constexpr int kScanPer = 4;
+constexpr int kScanBlock = kBlock * kScanPer;
+
+__device__ __forceinline__ int64_t block_exclusive_scan(int64_t v, int64_t *s_tmp, int64_t *total) {
+  // Hillis-Steele over the workgroup in LDS
+  const int x = threadIdx.x;
+  s_tmp[x] = v;
+  __syncthreads();
+  for (int d = 1; d < kBlock; d <<= 1) {
+    const int64_t add = x >= d ? s_tmp[x - d] : 0;
+    __syncthreads();
+    s_tmp[x] += add;
+    __syncthreads();
+  }
+  const int64_t incl = s_tmp[x];
+  *total = s_tmp[kBlock - 1];
+  __syncthreads();
+  return incl - v;
+}
+
+__global__ __launch_bounds__(kBlock) void scan_local_kernel(MultiIn in, MultiWork w, MultiOut out) {
+  __shared__ int64_t s_tmp[kBlock];
+  const int64_t base = (int64_t)blockIdx.x * kScanBlock + (int64_t)threadIdx.x * kScanPer;
+  int64_t v[kScanPer], sum = 0;
+#pragma unroll
+  for (int j = 0; j < kScanPer; ++j) {
+    v[j] = base + j < in.n_reads ? out.n_aligned[base + j] : 0;
+    sum += v[j];
+  }
+  int64_t total;
+  int64_t run = block_exclusive_scan(sum, s_tmp, &total);
+#pragma unroll
+  for (int j = 0; j < kScanPer; ++j) {
+    if (base + j < in.n_reads) w.off[base + j] = run;
+    run += v[j];
+  }
+  if (threadIdx.x == 0) w.bsum[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(kBlock) void scan_blocks_kernel(MultiIn in, MultiWork w, int64_t nb) {
+  __shared__ int64_t s_tmp[kBlock];
+  // each thread scans a contiguous chunk of the block sums
+  const int64_t per = (nb + kBlock - 1) / kBlock;
+  const int64_t a = min((int64_t)threadIdx.x * per, nb), b = min(a + per, nb);
+  int64_t sum = 0;
+  for (int64_t k = a; k < b; ++k) sum += w.bsum[k];
+  int64_t total;
+  int64_t run = block_exclusive_scan(sum, s_tmp, &total);
+  for (int64_t k = a; k < b; ++k) {
+    const int64_t c = w.bsum[k];
+    w.bsum[k] = run;
+    run += c;
+  }
+  if (threadIdx.x == 0) w.off[in.n_reads] = total;
+}
+
+__global__ __launch_bounds__(kBlock) void scan_add_kernel(MultiIn in, MultiWork w) {
+  const int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (r >= in.n_reads) return;
+  w.off[r] += w.bsum[r / kScanBlock];
+}
+
+// Every slot emptied (a zero-length task the batched form skips) before
+// the ranking fills the live ones: slots past the last task stay empty, and
+// a malformed candidate list cannot leave an earlier call's task behind.
+__global__ __launch_bounds__(kBlock) void pad_kernel(MultiIn in, MultiWork w) {
+  const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (t >= in.n_slots) return;
+  w.t_rwo[t] = 0;
+  w.t_rl[t] = 0;
+  w.t_rbo[t] = 0;
+  w.t_ml[t] = 0;
+  w.t_cand[t] = -1;
+}
+
+// Per candidate: its rank among the valid candidates of its read by
+// (support desc, index asc) -- the number of valid candidates ahead of it;
+// a rank under the ceiling places the candidate at task off[r] + rank.
+__global__ __launch_bounds__(kBlock) void rank_kernel(MultiIn in, MultiWork w) {
+  const int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (c >= in.n_cands) return;
+  // owning read: the last r with cand_start[r] <= c
+  int64_t lo = 0, hi = in.n_reads - 1;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi + 1) >> 1;
+    if (in.cand_start[mid] <= c) lo = mid; else hi = mid - 1;
+  }
+  const int64_t r = lo;
+  if (w.flag[r] != kTaskOk || !cand_ok(in, c)) return;
+  const int64_t a = in.cand_start[r], b = in.cand_start[r + 1];
+  if (c < a || c >= b) return;
+  const int32_t s = in.cand_support[c];
+  const int32_t C = in.ceiling;
+  int32_t rank = 0;
+  for (int64_t d = a; d < b && rank < C; ++d) {
+    if (d == c || !cand_ok(in, d)) continue;
+    const int32_t sd = in.cand_support[d];
+    rank += (sd > s || (sd == s && d < c)) ? 1 : 0;
+  }
+  const int64_t t = w.off[r] + rank;
+  // (a malformed, overlapping candidate list could count past the slots)
+  if (rank >= C || t >= in.n_slots) return;
+  w.t_rwo[t] = in.read_word_off[r] + (in.cand_strand[c] ? in.read_words : 0);
+  w.t_rl[t] = in.read_len[r];
+  w.t_rbo[t] = in.cand_base_off[c];
+  w.t_ml[t] = in.cand_len[c];
+  w.t_cand[t] = c;
 }
 
 // Highest score, ties to the earlier rank; every other aligned candidate
@@ -116,12 +191,12 @@ __global__ __launch_bounds__(kBlock) void select_kernel(MultiIn in, MultiWork w,
 __global__ __launch_bounds__(kBlock) void reduce_kernel(MultiIn in, MultiWork w, MultiOut out) {
   const int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (r >= in.n_reads) return;
-  const int32_t C = in.ceiling;
   int32_t best = -1, best_s = 0, second = INT32_MIN;
+  const int64_t t0 = w.off[r];
   if (w.flag[r] == kTaskOk) {
     const int32_t cnt = out.n_aligned[r];
-    for (int32_t k = 0; k < cnt; ++k) {
-      const int64_t t = r * C + k;
+    for (int32_t k = 0; k < cnt && t0 + k < in.n_slots; ++k) {
+      const int64_t t = t0 + k;
       const uint8_t ts = w.p_status[t];
       if (ts != kTaskOk && ts != kTaskRedone) continue;
       const int32_t s = w.p_score[t];
@@ -136,7 +211,7 @@ __global__ __launch_bounds__(kBlock) void reduce_kernel(MultiIn in, MultiWork w,
     if (best < 0) w.flag[r] = SOAP_DP_TASK_NO_CANDIDATE;
   }
   if (best >= 0) {
-    const int64_t t = r * C + best;
+    const int64_t t = t0 + best;
     w.f_rwo[r] = w.t_rwo[t];
     w.f_rl[r] = w.t_rl[t];
     w.f_rbo[r] = w.t_rbo[t];
@@ -178,7 +253,15 @@ hipError_t launch_revcomp(const MultiIn &in, const MultiWork &w, hipStream_t str
 
 hipError_t launch_select(const MultiIn &in, const MultiWork &w, const MultiOut &out,
                          hipStream_t stream) {
-  hipLaunchKernelGGL(select_kernel, grid_of(in.n_reads), dim3(kBlock), 0, stream, in, w, out);
+  const int64_t nb = (in.n_reads + kScanBlock - 1) / kScanBlock;
+  hipLaunchKernelGGL(count_kernel, grid_of(in.n_reads), dim3(kBlock), 0, stream, in, w, out);
+  hipLaunchKernelGGL(scan_local_kernel, dim3((uint32_t)nb), dim3(kBlock), 0, stream, in, w, out);
+  hipLaunchKernelGGL(scan_blocks_kernel, dim3(1), dim3(kBlock), 0, stream, in, w, nb);
+  hipLaunchKernelGGL(scan_add_kernel, grid_of(in.n_reads), dim3(kBlock), 0, stream, in, w);
+  if (in.n_slots > 0)
+    hipLaunchKernelGGL(pad_kernel, grid_of(in.n_slots), dim3(kBlock), 0, stream, in, w);
+  if (in.n_cands > 0)
+    hipLaunchKernelGGL(rank_kernel, grid_of(in.n_cands), dim3(kBlock), 0, stream, in, w);
   return hipGetLastError();
 }
 
