@@ -370,6 +370,8 @@ def main():
     ap.add_argument("--form", choices=["plain", "batched", "both"], default="both")
     ap.add_argument("--cpu-tasks", type=int, default=1_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--score-only", action="store_true",
+                    help="score and end only (SOAP_DP_SCORE_ONLY), no traceback")
     ap.add_argument("--tune-cache", default=os.environ.get("SOAPDP_TUNE_CACHE"))
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run device-to-device copies of BYTES (HBM counter calibration)")
@@ -407,27 +409,31 @@ def main():
     w = getattr(workloads, gen)()
     al = binding.Aligner(0)
     dw = binding.DeviceWorkload(w)
-    res = binding.DeviceResult(w.n_tasks, 2 * dw.max_n)
+    # --score-only: score and end of every task, no traceback (its own
+    # kernels and shapes); reported at 10 ops per cell
+    extra = binding.SCORE_ONLY if args.score_only else 0
+    ops = OPS_PER_CELL_SCORE if args.score_only else OPS_PER_CELL
+    res = binding.DeviceResult(w.n_tasks, 0 if args.score_only else 2 * dw.max_n)
 
     forms = {}
     if args.form in ("batched", "both"):
         al.autotune(args.tune_cache)
-        s, k = time_form(al, dw, res, binding.BATCHED, args.steps, args.warmup)
+        s, k = time_form(al, dw, res, binding.BATCHED | extra, args.steps, args.warmup)
         forms["batched"] = (s, k)
     if args.form in ("plain", "both"):
-        s, k = time_form(al, dw, res, binding.PLAIN, args.steps, args.warmup)
+        s, k = time_form(al, dw, res, binding.PLAIN | extra, args.steps, args.warmup)
         forms["plain"] = (s, k)
     main_form = headline if headline in forms else next(iter(forms))
 
     def summary(form):
         s, k = forms[form]
         peak = PEAK_INT32_TOPS if form == "plain" else PEAK_INT16_TOPS
-        achieved = OPS_PER_CELL * w.cells / (k * 1e-3) / 1e12
+        achieved = ops * w.cells / (k * 1e-3) / 1e12
         return s, k, peak, achieved
 
     s, k, peak, achieved = summary(main_form)
     line = {
-        "metric": METRIC,
+        "metric": METRIC if not args.score_only else "GCUPS score only (no traceback), batched vs plain kernel",
         "value": round(w.cells / s / 1e9, 2),
         "unit": "GCUPS",
         "n_gpus": 1,
@@ -447,8 +453,8 @@ def main():
             "peak": round(peak, 1),
             "unit": "TOP/s",
             "frac": round(achieved / peak, 4),
-            "traffic": traffic_bytes(args.workload, main_form),
-            "ops_per_cell": OPS_PER_CELL,
+            "traffic": None if args.score_only else traffic_bytes(args.workload, main_form),
+            "ops_per_cell": ops,
             "kernel_ms": round(k, 3),
         },
         "forms": {},
