@@ -107,7 +107,10 @@ void dp_i32_kernel(DpParams p) {
     if (valid) rw.load(p.read_codes, rwo, n, lg * K - pad);
     const int32_t ge = p.ge;
     const int32_t c_go = p.go - ge;          // gap open in offset form
-    const int32_t c_ma = p.ma - 2 * ge;      // diagonal constants in offset form
+    // H holds G = M^ + c_go: the gap-open candidate of the cell to the right
+    // (same row) and of the cell below (next row) without another add.  The
+    // diagonal constants are taken relative to it: delta - 2 S_GE - c_go.
+    const int32_t c_ma = p.ma - 2 * ge - c_go;
     // Read codes (4 left of the read, never a window base).  General
     // variant: one register per column plus its mismatch constant.  Byte
     // variant: four columns' codes per register, one byte each.
@@ -125,10 +128,11 @@ void dp_i32_kernel(DpParams p) {
         R4[c / 4] |= code << (8 * (c % 4));
       } else {
         Rc[c] = (int32_t)code;
-        Mi[c] = real ? p.mi - 2 * ge : -2 * ge;
+        Mi[c] = real ? p.mi - 2 * ge - c_go : -2 * ge - c_go;
       }
-      // M^(0, j), j = q + 1: S_GO + (j-1) S_GE - j S_GE, or 0 - j S_GE left of the read
-      H[c] = real ? c_go : -(q + 1) * ge;
+      // M^(0, j), j = q + 1: S_GO + (j-1) S_GE - j S_GE, or 0 - j S_GE left
+      // of the read; held as G = M^ + c_go
+      H[c] = (real ? c_go : -(q + 1) * ge) + c_go;
       F[c] = kNeg32;                       // D(0, j)
       // finish each column before the next: bounds live registers in set-up
       if constexpr (kByte)
@@ -141,10 +145,10 @@ void dp_i32_kernel(DpParams p) {
     // x of the table (tab_hi:tab_lo) with byte b of tab_lo holding the match
     // value, the other bytes of tab_lo the mismatch value and tab_hi (codes
     // 4..7) the value left of the read.
-    const uint32_t d_mi = (uint32_t)(p.mi - 2 * ge) & 0xffu;
+    const uint32_t d_mi = (uint32_t)(p.mi - 2 * ge - c_go) & 0xffu;
     const uint32_t tab_mis = d_mi * 0x01010101u;
     const uint32_t tab_flip = ((uint32_t)c_ma & 0xffu) ^ d_mi;
-    const uint32_t tab_hi = ((uint32_t)(-2 * ge) & 0xffu) * 0x01010101u;
+    const uint32_t tab_hi = ((uint32_t)(-2 * ge - c_go) & 0xffu) * 0x01010101u;
 
     // window bases, 16 at a time, realigned from the base offset
     const uint64_t wlim = p.ref_words - 1;
@@ -157,14 +161,14 @@ void dp_i32_kernel(DpParams p) {
     uint32_t tn0, tn1, tw = 0;
     load_block(0, tn0, tn1);
 
-    int32_t hl_out = H[K - 1];   // M^(0, last column of the strip)
+    int32_t hl_out = H[K - 1];   // G(0, last column of the strip)
     int32_t el_out = kNeg32;
     int32_t t_out = 0;
-    // left boundary M^(i, -pad) = -(i - pad) S_GE (true value 0): row 0 is the
-    // first lane's first diagonal, row 1 its first left neighbour
-    int32_t hl_prev = pad * ge;
-    int32_t bnd = (pad - 1) * ge;
-    int32_t rge = (1 - lg) * ge;   // i * S_GE of this lane's current row
+    // left boundary M^(i, -pad) = -(i - pad) S_GE (true value 0), as G: row 0
+    // is the first lane's first diagonal, row 1 its first left neighbour
+    int32_t hl_prev = pad * ge + c_go;
+    int32_t bnd = (pad - 1) * ge + c_go;
+    int32_t rge = (1 - lg) * ge - c_go;   // i * S_GE of the current row, minus c_go
     int32_t best = INT32_MIN, endi = 0;
     uint32_t acc[W];
 #pragma unroll
@@ -206,10 +210,10 @@ void dp_i32_kernel(DpParams p) {
         int32_t diag = hd + delta(0);
 #pragma unroll
         for (int c = 0; c < K; ++c) {
-          const int32_t ad = H[c] + c_go;
+          const int32_t ad = H[c];   // G of the cell above: D-open candidate
           int32_t diag_next = 0;
           if (c + 1 < K) diag_next = H[c] + delta(c + 1);
-          const int32_t ai = hl + c_go;
+          const int32_t ai = hl;     // G of the cell to the left: I-open candidate
           el = max(ai, el);
           const int32_t f = max(ad, F[c]);
           const int32_t h = max(max(diag, el), f);
@@ -221,9 +225,9 @@ void dp_i32_kernel(DpParams p) {
             a = push_sign(a, f - h);
             acc[c / 8] = a;
           }
-          H[c] = h;
+          H[c] = h + c_go;
           F[c] = f;
-          hl = h;
+          hl = H[c];
           diag = diag_next;
           // keep each column's decisions next to its scores: without this the
           // optimiser sinks them below all columns and every column's
@@ -236,7 +240,7 @@ void dp_i32_kernel(DpParams p) {
           if (K % 8) acc[W - 1] <<= 4 * (8 - K % 8);
         hl_out = hl;
         el_out = el;
-        // M(i, n) - n S_GE = M^(i, n) + i S_GE
+        // M(i, n) - n S_GE = M^(i, n) + i S_GE = G - c_go + i S_GE
         const int32_t v = H[K - 1] + rge;
         if (last && v > best) { best = v; endi = i; }
       }
@@ -350,7 +354,7 @@ int occupancy_i32(bool byte, bool score) {
 }
 
 hipError_t launch_dp_i32(Shape s, int grid, hipStream_t stream, const DpParams &p) {
-  const bool byte = byte_delta_fits(p.ma, p.mi, p.ge);
+  const bool byte = byte_delta_fits_i32(p.ma, p.mi, p.go, p.ge);
 #define X(l, k) \
   if (s.lanes == l && s.cells == k) return launch_i32<l, k>(grid, stream, p, byte, p.score_only != 0);
   SOAPDP_I32_SHAPES(X)

@@ -99,6 +99,17 @@ __host__ __device__ inline bool byte_delta_fits(int32_t ma, int32_t mi, int32_t 
   return d_mi >= 0 && d_ma <= 255 && d_v <= 255;
 }
 
+// int32 kernel: M is carried as G = X - (i+j) S_GE + (S_GO - S_GE), the
+// value that opens a gap next to the cell, so the diagonal constants are
+// S_MA - S_GE - S_GO, S_MI - S_GE - S_GO and -S_GE - S_GO left of the read.
+// True when they fit an unsigned byte (the byte-table variant).
+__host__ __device__ inline bool byte_delta_fits_i32(int32_t ma, int32_t mi, int32_t go, int32_t ge) {
+  const int64_t d_ma = int64_t(ma) - int64_t(ge) - int64_t(go);
+  const int64_t d_mi = int64_t(mi) - int64_t(ge) - int64_t(go);
+  const int64_t d_v = -int64_t(ge) - int64_t(go);
+  return d_mi >= 0 && d_ma <= 255 && d_v <= 255;
+}
+
 __host__ __device__ inline bool int16_fits(int32_t n, int32_t m, int32_t cols, int32_t ma,
                                            int32_t mi, int32_t go, int32_t ge) {
   if (!byte_delta_fits(ma, mi, ge)) return false;
@@ -114,7 +125,7 @@ __host__ __device__ inline bool int16_fits(int32_t n, int32_t m, int32_t cols, i
 
 // Launch the int32 kernel of shape `s` (must be one of the compiled shapes);
 // the variant with the byte-table diagonal runs when the scoring allows it
-// (byte_delta_fits).
+// (byte_delta_fits_i32).
 hipError_t launch_dp_i32(Shape s, int grid, hipStream_t stream, const DpParams &p);
 // Occupancy (workgroups of one wave per CU) of the int32 kernel of shape `s`,
 // byte-table variant or general one, full or score-only.

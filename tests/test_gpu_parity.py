@@ -36,9 +36,10 @@ def test_every_plain_shape(max_n):
 
 @pytest.mark.parametrize("max_n", [100, 104, 150])
 def test_plain_shapes_general_variant(max_n):
-    """A scoring whose offset-form constants do not fit a byte runs the
-    general (compare and select) diagonal in the same shapes."""
-    sc = (5, -4, -10, 0)
+    """A scoring whose diagonal constants (relative to the gap-open value)
+    do not fit a byte runs the general (compare and select) diagonal in the
+    same shapes: here S_MI - S_GE - S_GO < 0."""
+    sc = (1, -9, -3, -1)
     rng = np.random.default_rng(1000 + max_n)
     w = workloads.random_tasks(rng, 500, n_range=(max_n - 30, max_n), m_range=(1, 300),
                                genome_len=20000)
