@@ -169,7 +169,7 @@ struct Kind {
 };
 
 Kind kind_for(const soap_dp_scoring *sc, bool score) {
-  return Kind{byte_delta_fits_i32(sc->match, sc->mismatch, sc->gap_open, sc->gap_extend) ? kByte
+  return Kind{byte_delta_fits(sc->match, sc->mismatch, sc->gap_open, sc->gap_extend) ? kByte
                                                                                       : kGeneral,
               score};
 }

@@ -90,13 +90,17 @@ void dp_i16_kernel(DpParams p) {
   const int64_t n_items = (n_tasks + TPW - 1) / TPW;
 
   const int32_t ma = p.ma, mi = p.mi, go = p.go, ge = p.ge;
-  const uint32_t c_go = pack16(go - ge, go - ge);    // gap open, offset form
+  const int32_t go1 = go - ge;                        // gap open, offset form
+  const uint32_t c_go = pack16(go1, go1);
   const uint32_t c_ge = pack16(ge, ge);
   const uint32_t c_nge = pack16(-ge, -ge);
-  // x = 0 match, 1..3 mismatch, 4..7 virtual
-  const uint32_t tab_lo = ((uint32_t)(ma - 2 * ge) & 0xffu) |
-                          ((uint32_t)(mi - 2 * ge) & 0xffu) * 0x01010100u;
-  const uint32_t tab_hi = ((uint32_t)(-2 * ge) & 0xffu) * 0x01010101u;
+  // H holds G = M^ + (S_GO - S_GE): the gap-open candidate of the cell to the
+  // right (same row) and of the cell below (next row) without another add.
+  // Diagonal constants relative to it, x = 0 match, 1..3 mismatch, 4..7
+  // virtual: delta - 2 S_GE - (S_GO - S_GE).
+  const uint32_t tab_lo = ((uint32_t)(ma - 2 * ge - go1) & 0xffu) |
+                          ((uint32_t)(mi - 2 * ge - go1) & 0xffu) * 0x01010100u;
+  const uint32_t tab_hi = ((uint32_t)(-2 * ge - go1) & 0xffu) * 0x01010101u;
 
   int64_t item = blockIdx.x;
   while (item < n_items) {
@@ -157,8 +161,9 @@ void dp_i16_kernel(DpParams p) {
         const int32_t q = lg * K + c - pad[h];   // 0-based read index of this column
         const bool real = mg[h] > 0 && q >= 0;
         code[h] = real ? rw[h].code(q) : 4u;     // virtual: table entries 4..7
-        // M^(0, j), j = q + 1: S_GO + (j-1) S_GE - j S_GE, or 0 - j S_GE left of the read
-        hv[h] = real ? go - ge : -(q + 1) * ge;
+        // M^(0, j), j = q + 1: S_GO + (j-1) S_GE - j S_GE, or 0 - j S_GE left
+        // of the read; held as G = M^ + (S_GO - S_GE)
+        hv[h] = (real ? go1 : -(q + 1) * ge) + go1;
       }
       Rc[c] = (code[0] | 0x0c00u) | ((code[1] | 0x0c00u) << 16);
       H[c] = pack16(hv[0], hv[1]);
@@ -167,10 +172,11 @@ void dp_i16_kernel(DpParams p) {
       asm volatile("" : "+v"(Rc[c]), "+v"(H[c]));
       __builtin_amdgcn_sched_barrier(0);
     }
-    // left boundary M^(i, -pad) = -(i - pad) S_GE (true value 0): row 0 is the
-    // first lane's first diagonal, row 1 its first left neighbour
-    uint32_t bnd = pack16((pad[0] - 1) * ge, (pad[1] - 1) * ge);
-    uint32_t rge = pack16((1 - lg) * ge, (1 - lg) * ge);   // i * S_GE of this lane's row
+    // left boundary M^(i, -pad) = -(i - pad) S_GE (true value 0), as G: row 0
+    // is the first lane's first diagonal, row 1 its first left neighbour
+    uint32_t bnd = pack16((pad[0] - 1) * ge + go1, (pad[1] - 1) * ge + go1);
+    // i * S_GE of this lane's row, minus (S_GO - S_GE)
+    uint32_t rge = pack16((1 - lg) * ge - go1, (1 - lg) * ge - go1);
 
     // window bases, 16 at a time per task, realigned from the base offset
     const uint64_t wlim = p.ref_words - 1;
@@ -183,7 +189,7 @@ void dp_i16_kernel(DpParams p) {
     uint32_t hl_out = H[K - 1];
     uint32_t el_out = kNeg16x2;
     uint32_t t_out = 0;
-    uint32_t hl_prev = pack16(pad[0] * ge, pad[1] * ge);
+    uint32_t hl_prev = pack16(pad[0] * ge + go1, pad[1] * ge + go1);
     int32_t best0 = INT32_MIN, best1 = INT32_MIN;
     uint32_t accA[W], accB[W];
 #pragma unroll
@@ -215,10 +221,10 @@ void dp_i16_kernel(DpParams p) {
         uint32_t diag = add16(hd, __builtin_amdgcn_perm(tab_hi, tab_lo, Rc[0] ^ T));
 #pragma unroll
         for (int c = 0; c < K; ++c) {
-          const uint32_t ad = add16(H[c], c_go);
+          const uint32_t ad = H[c];   // G of the cell above: D-open candidate
           uint32_t diag_next = 0;
           if (c + 1 < K) diag_next = add16(H[c], __builtin_amdgcn_perm(tab_hi, tab_lo, Rc[c + 1] ^ T));
-          const uint32_t ai = add16(hl, c_go);
+          const uint32_t ai = hl;     // G of the cell to the left: I-open candidate
           el = max16(ai, el);
           const uint32_t f = max16(ad, F[c]);
           const uint32_t hv = max16(max16(diag, el), f);
@@ -236,9 +242,9 @@ void dp_i16_kernel(DpParams p) {
               accB[c / 8] |= tB & msk;
             }
           }
-          H[c] = hv;
+          H[c] = add16(hv, c_go);
           F[c] = f;
-          hl = hv;
+          hl = H[c];
           diag = diag_next;
           // keep each column's decisions next to its scores: without this the
           // optimiser sinks them below all columns and every column's
@@ -251,7 +257,8 @@ void dp_i16_kernel(DpParams p) {
         el_out = el;
         if (last) {
           // key = ((M^(i, n) + i S_GE) << 16) | (0xffff - i): the max is the
-          // best score M(i, n) - n S_GE, then the smallest row
+          // best score M(i, n) - n S_GE, then the smallest row (H holds
+          // M^ + (S_GO - S_GE), which rge takes off again)
           const uint32_t inv = 0xffffu - (uint32_t)i;
           const uint32_t v = add16(H[K - 1], rge);
           const int32_t k0 = (int32_t)((v << 16) | inv);

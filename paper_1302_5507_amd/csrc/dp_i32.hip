@@ -354,7 +354,7 @@ int occupancy_i32(bool byte, bool score) {
 }
 
 hipError_t launch_dp_i32(Shape s, int grid, hipStream_t stream, const DpParams &p) {
-  const bool byte = byte_delta_fits_i32(p.ma, p.mi, p.go, p.ge);
+  const bool byte = byte_delta_fits(p.ma, p.mi, p.go, p.ge);
 #define X(l, k) \
   if (s.lanes == l && s.cells == k) return launch_i32<l, k>(grid, stream, p, byte, p.score_only != 0);
   SOAPDP_I32_SHAPES(X)

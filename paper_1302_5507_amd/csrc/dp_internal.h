@@ -82,38 +82,30 @@ struct Shape {
   int cells;
 };
 
-// int16 form: a task (read of n bases, window of m) can run in packed int16
-// iff the diagonal constants of the offset form X - (i+j) S_GE fit a byte
-// table (0 <= S_MI - 2 S_GE, S_MA - 2 S_GE <= 255) and every value the
-// kernel forms stays inside int16: real cells lie between the lowest
-// possible maximum and n S_MA, shifted up by at most (m + n) |S_GE|; virtual
-// columns hold (i+j) |S_GE| with j down to -cols; each bound is widened by
-// twice the largest constant added.  Evaluated identically on host and device.
-// The diagonal constants of the offset form X - (i+j) S_GE (S_MA - 2 S_GE on
-// a match, S_MI - 2 S_GE on a mismatch, -2 S_GE left of the read) fit an
-// unsigned byte, so one byte permute looks them up.
-__host__ __device__ inline bool byte_delta_fits(int32_t ma, int32_t mi, int32_t ge) {
-  const int64_t d_ma = int64_t(ma) - 2 * int64_t(ge);
-  const int64_t d_mi = int64_t(mi) - 2 * int64_t(ge);
-  const int64_t d_v = -2 * int64_t(ge);
-  return d_mi >= 0 && d_ma <= 255 && d_v <= 255;
-}
-
-// int32 kernel: M is carried as G = X - (i+j) S_GE + (S_GO - S_GE), the
-// value that opens a gap next to the cell, so the diagonal constants are
-// S_MA - S_GE - S_GO, S_MI - S_GE - S_GO and -S_GE - S_GO left of the read.
-// True when they fit an unsigned byte (the byte-table variant).
-__host__ __device__ inline bool byte_delta_fits_i32(int32_t ma, int32_t mi, int32_t go, int32_t ge) {
+// The sweeps carry M as G = X - (i+j) S_GE + (S_GO - S_GE): the value that
+// opens a gap next to the cell, so the cells to the right and below use it
+// without another add.  The diagonal constants relative to it are
+// S_MA - S_GE - S_GO on a match, S_MI - S_GE - S_GO on a mismatch and
+// -S_GE - S_GO left of the read.  True when they fit an unsigned byte, so
+// one byte permute looks them up.
+__host__ __device__ inline bool byte_delta_fits(int32_t ma, int32_t mi, int32_t go, int32_t ge) {
   const int64_t d_ma = int64_t(ma) - int64_t(ge) - int64_t(go);
   const int64_t d_mi = int64_t(mi) - int64_t(ge) - int64_t(go);
   const int64_t d_v = -int64_t(ge) - int64_t(go);
   return d_mi >= 0 && d_ma <= 255 && d_v <= 255;
 }
 
+// int16 form: a task (read of n bases, window of m) can run in packed int16
+// iff the diagonal constants fit a byte table (byte_delta_fits) and every
+// value the kernel forms stays inside int16: real cells lie between the
+// lowest possible maximum and n S_MA, shifted up by at most (m + n) |S_GE|;
+// virtual columns hold (i+j) |S_GE| with j down to -cols; each bound is
+// widened by twice the largest constant added (S_GO - S_GE, the diagonal
+// constants, S_GE).  Evaluated identically on host and device.
 __host__ __device__ inline bool int16_fits(int32_t n, int32_t m, int32_t cols, int32_t ma,
                                            int32_t mi, int32_t go, int32_t ge) {
-  if (!byte_delta_fits(ma, mi, ge)) return false;
-  const int64_t d_ma = int64_t(ma) - 2 * int64_t(ge);
+  if (!byte_delta_fits(ma, mi, go, ge)) return false;
+  const int64_t d_ma = int64_t(ma) - int64_t(ge) - int64_t(go);
   auto iabs = [](int64_t v) { return v < 0 ? -v : v; };
   int64_t s = iabs(int64_t(go) - ge);
   s = s > d_ma ? s : d_ma;
@@ -125,7 +117,7 @@ __host__ __device__ inline bool int16_fits(int32_t n, int32_t m, int32_t cols, i
 
 // Launch the int32 kernel of shape `s` (must be one of the compiled shapes);
 // the variant with the byte-table diagonal runs when the scoring allows it
-// (byte_delta_fits_i32).
+// (byte_delta_fits).
 hipError_t launch_dp_i32(Shape s, int grid, hipStream_t stream, const DpParams &p);
 // Occupancy (workgroups of one wave per CU) of the int32 kernel of shape `s`,
 // byte-table variant or general one, full or score-only.

@@ -79,10 +79,11 @@ def _int16_class_cols(al, n):
 
 def _int16_fits(n, m, cols, sc):
     """The int16 range rule of the batched form, restated: the diagonal
-    constants of the offset form X - (i+j) S_GE fit a byte, and the value
-    bounds widened by twice the largest added constant stay inside int16."""
+    constants relative to M + (S_GO - S_GE) in the offset form X - (i+j) S_GE
+    fit a byte, and the value bounds widened by twice the largest added
+    constant stay inside int16."""
     ma, mi, go, ge = sc
-    d_ma, d_mi, d_v = ma - 2 * ge, mi - 2 * ge, -2 * ge
+    d_ma, d_mi, d_v = ma - ge - go, mi - ge - go, -ge - go
     if d_mi < 0 or d_ma > 255 or d_v > 255:
         return False
     s = max(abs(go - ge), d_ma, abs(ge))
