@@ -227,7 +227,11 @@ int hip_fail(soap_dp_ctx *ctx, hipError_t e) {
   return SOAP_DP_EHIP;
 }
 
+// Drop every cached graph.  A cached graph may have been launched moments
+// ago (the caller's stream does not wait for the host), so the device is
+// synchronised before an executable graph is destroyed.
 void clear_graphs(soap_dp_ctx *ctx) {
+  if (!ctx->graphs.empty()) (void)hipDeviceSynchronize();
   for (auto &g : ctx->graphs) (void)hipGraphExecDestroy(g.exec);
   ctx->graphs.clear();
   ++ctx->epoch;
@@ -584,6 +588,11 @@ int align_batched(soap_dp_ctx *ctx, const soap_dp_batch *in, const soap_dp_scori
                                      [](const GraphEntry &a, const GraphEntry &b) {
                                        return a.last_use < b.last_use;
                                      });
+      // its last launch may still run: wait before destroying it
+      if ((e = hipDeviceSynchronize()) != hipSuccess) {
+        (void)hipGraphExecDestroy(exec);
+        return hip_fail(ctx, e);
+      }
       (void)hipGraphExecDestroy(oldest->exec);
       ctx->graphs.erase(oldest);
     }

@@ -167,3 +167,32 @@ def test_multi_full_size_sampled():
     status = np.where(g["status"] == binding.TASK_OK_REDONE_INT32, 0, g["status"])
     assert (status == 0).all()
     assert np.mean(g["best_cand"] == mw.true_cand) > 0.97
+
+
+def test_multi_fresh_context_first_call():
+    """A fresh context's first call grows the workspace between the two
+    passes while the first pass's graph is still running; cached graphs
+    must only be dropped after the device has finished them."""
+    import torch
+    mw = workloads.multi_candidate(60_000, seed=58)
+    dm = binding.DeviceMultiWorkload(mw)
+    al = binding.Aligner(0)
+    try:
+        res = al.align_multi(dm, 30, CONFIG_SCORING)
+        res2 = al.align_multi(dm, 30, CONFIG_SCORING)
+        torch.cuda.synchronize()
+        g, g2 = res.to_host(), res2.to_host()
+    finally:
+        al.close()
+    for f in ("score", "ref_end", "best_cand", "second_score", "n_aligned", "status"):
+        assert np.array_equal(g[f], g2[f]), f
+    idx = np.sort(np.random.default_rng(59).choice(mw.n_reads, 200, replace=False))
+    counts = np.diff(mw.cand_start)[idx]
+    keep = np.concatenate([np.arange(mw.cand_start[r], mw.cand_start[r + 1]) for r in idx])
+    sub = workloads.MultiWorkload("sample", mw.genome, mw.read_codes, mw.read_off[idx],
+                                  mw.read_len[idx], np.concatenate([[0], np.cumsum(counts)]),
+                                  mw.cand_off[keep], mw.cand_len[keep], mw.cand_support[keep],
+                                  mw.cand_strand[keep], mw.true_cand[idx])
+    ref = _oracle(sub, 30, CONFIG_SCORING, dm.max_n, dm.max_m)
+    ref.best_cand = np.where(ref.best_cand >= 0, keep[np.maximum(ref.best_cand, 0)], -1)
+    _compare({k: v[idx] for k, v in g.items()}, ref, "fresh context")
