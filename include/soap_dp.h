@@ -442,8 +442,9 @@ int soap_dp_server_submit(soap_dp_server *srv, const soap_dp_request *req, uint6
 int soap_dp_server_poll(soap_dp_server *srv, uint64_t ticket);
 
 /* Block until the request has completed and release its ticket; its
- * completion time (when the dispatcher saw its batch finish) goes to
- * *done_ns when non-NULL.  Returns the request's result code. */
+ * completion time (when its results were all in the caller's buffers, on
+ * soap_dp_now_ns's clock) goes to *done_ns when non-NULL.  Returns the
+ * request's result code. */
 int soap_dp_server_wait(soap_dp_server *srv, uint64_t ticket, uint64_t *done_ns);
 
 /* Block until every submitted request has completed. */

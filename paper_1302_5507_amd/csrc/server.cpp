@@ -150,7 +150,7 @@ int init_slot(soap_dp_server *srv, Slot &s) {
 // Finished batch: copy each request's slice to its caller buffers.  CIGARs
 // come from the dense head copy; the rest of the rare longer rows is
 // fetched with one queued copy per row and a single wait.
-void retire(soap_dp_server *srv, Slot &s, uint64_t t_done) {
+void retire(soap_dp_server *srv, Slot &s) {
   const int32_t T = srv->cfg.max_tasks;
   const int32_t S = srv->stride;
   constexpr int32_t H = soapdp::kCigarHeadWords;
@@ -172,7 +172,12 @@ void retire(soap_dp_server *srv, Slot &s, uint64_t t_done) {
     rest += len - H;
   }
   if (!rest_at.empty()) fetched = fetched && hipStreamSynchronize(s.stream) == hipSuccess;
-  std::vector<std::pair<uint64_t, int>> finished;
+  struct Finished {
+    uint64_t ticket;
+    int rc;
+    uint64_t done_ns;   // when the request's results were all in its buffers
+  };
+  std::vector<Finished> finished;
   for (size_t r = 0; r < s.reqs.size(); ++r) {
     Request &q = *s.reqs[r];
     const int32_t f = s.first_task[r], n = q.n_tasks;
@@ -184,34 +189,40 @@ void retire(soap_dp_server *srv, Slot &s, uint64_t t_done) {
     std::memcpy(o.status, s.h_status + f, size_t(n));
     int64_t words = 0;
     int rc = SOAP_DP_OK;
+    const int32_t *lens = s.h_i32 + 3 * T + f;
+    const uint32_t *head = s.h_head + int64_t(f) * H;
     for (int32_t t = 0; t < n; ++t) {
-      const int32_t len = std::min(std::max(o.cigar_len[t], 0), S);
+      const int32_t len = std::min(std::max(lens[t], 0), S);
       if (words + len > o.cigar_capacity) {
         rc = SOAP_DP_E2BIG;   // keeps counting; writes nothing past the buffer
       } else {
-        std::memcpy(o.cigar + words, s.h_head + int64_t(f + t) * H, size_t(std::min(len, H)) * 4);
+        // most rows are a few words: a plain loop beats a memcpy call
+        uint32_t *dst = o.cigar + words;
+        const uint32_t *src = head + int64_t(t) * H;
+        const int32_t hn = std::min(len, H);
+        for (int32_t k = 0; k < hn; ++k) dst[k] = src[k];
         if (len > H) {
           auto it = rest_at.find(f + t);
-          uint32_t *dst = o.cigar + words + H;
+          uint32_t *rdst = dst + H;
           if (it != rest_at.end() && fetched)
-            std::memcpy(dst, s.h_rest + it->second, size_t(len - H) * 4);
+            std::memcpy(rdst, s.h_rest + it->second, size_t(len - H) * 4);
           else if (it != rest_at.end() ||
-                   hipMemcpy(dst, s.d_cigar + int64_t(f + t) * S + H, size_t(len - H) * 4,
+                   hipMemcpy(rdst, s.d_cigar + int64_t(f + t) * S + H, size_t(len - H) * 4,
                              hipMemcpyDeviceToHost) != hipSuccess)
             rc = SOAP_DP_EHIP;
         }
       }
       words += len;
     }
-    finished.emplace_back(q.ticket, rc);
+    finished.push_back(Finished{q.ticket, rc, now_ns()});
   }
   {
     std::lock_guard<std::mutex> lk(srv->mu);
-    for (auto &fq : finished) {
-      TicketState &ts = srv->tickets[fq.first];
+    for (const Finished &fq : finished) {
+      TicketState &ts = srv->tickets[fq.ticket];
       ts.done = true;
-      ts.rc = fq.second;
-      ts.done_ns = t_done;
+      ts.rc = fq.rc;
+      ts.done_ns = fq.done_ns;
     }
     srv->stats.completed += finished.size();
     srv->stats.batches += 1;
@@ -377,7 +388,7 @@ void slot_worker(soap_dp_server *srv, size_t k) {
       continue;
     }
     t0 = now_ns();
-    retire(srv, s, t0);
+    retire(srv, s);
     {
       std::lock_guard<std::mutex> lk(srv->mu);
       srv->stats.host_retire_s += double(now_ns() - t0) * 1e-9;
