@@ -154,8 +154,6 @@ void retire(soap_dp_server *srv, Slot &s) {
   const int32_t T = srv->cfg.max_tasks;
   const int32_t S = srv->stride;
   constexpr int32_t H = soapdp::kCigarHeadWords;
-  float ms = 0;
-  (void)hipEventElapsedTime(&ms, s.start, s.done);
   // rows longer than the head: their rest packed into h_rest (T * H words);
   // in the unlikely case that it fills up, the remaining rows are fetched
   // one by one below
@@ -228,9 +226,16 @@ void retire(soap_dp_server *srv, Slot &s) {
     srv->stats.batches += 1;
     srv->stats.tasks += uint64_t(s.tasks);
     for (auto &q : s.reqs) srv->stats.cells += uint64_t(q->cells);
-    srv->stats.device_busy_s += double(ms) * 1e-3;
   }
   srv->cv_done.notify_all();
+  // device time of the batch, for the stats only: taken after the results
+  // are handed over (the runtime call can wait on other threads' calls)
+  float ms = 0;
+  (void)hipEventElapsedTime(&ms, s.start, s.done);
+  {
+    std::lock_guard<std::mutex> lk(srv->mu);
+    srv->stats.device_busy_s += double(ms) * 1e-3;
+  }
   s.reqs.clear();
   s.first_task.clear();
   s.tasks = 0;
