@@ -196,3 +196,26 @@ def test_multi_fresh_context_first_call():
     ref = _oracle(sub, 30, CONFIG_SCORING, dm.max_n, dm.max_m)
     ref.best_cand = np.where(ref.best_cand >= 0, keep[np.maximum(ref.best_cand, 0)], -1)
     _compare({k: v[idx] for k, v in g.items()}, ref, "fresh context")
+
+
+def test_multi_malformed_candidate_start():
+    """A candidate list that runs backwards (cand_start[r+1] < cand_start[r])
+    marks that read INVALID_OFFSET; the overlap it creates with the next
+    read's list leaves no stale tasks, and reads away from it are exact."""
+    mw = workloads.multi_candidate(400, seed=60)
+    cs = mw.cand_start.copy()
+    r = 200
+    cs[r + 1] = cs[r] - 3            # read r runs backwards; read r+1 overlaps read r-1
+    bad = workloads.MultiWorkload("malformed", mw.genome, mw.read_codes, mw.read_off,
+                                  mw.read_len, cs, mw.cand_off, mw.cand_len, mw.cand_support,
+                                  mw.cand_strand, mw.true_cand)
+    g, dm = _gpu(bad, 30)
+    assert g["status"][r] == binding.TASK_INVALID_OFFSET and g["n_aligned"][r] == 0
+    ref = _oracle(mw, 30, CONFIG_SCORING, dm.max_n, dm.max_m)
+    away = np.r_[0:r - 1, r + 2:mw.n_reads]
+    gs = {k: v[away] for k, v in g.items()}
+    for f in ("score", "ref_begin", "ref_end", "cigar_len", "best_cand", "second_score",
+              "n_aligned"):
+        assert np.array_equal(np.asarray(gs[f]).astype(np.int64),
+                              np.asarray(getattr(ref, f))[away].astype(np.int64)), f
+    assert np.isin(g["status"][r + 1], (0, 2, 4))
