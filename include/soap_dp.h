@@ -274,9 +274,11 @@ typedef struct {
 /* Enqueue on `stream` like soap_dp_align_batch: all candidates are first
  * scored (score-only batched form), then each read's best one is aligned
  * again with traceback.  Same error codes; the context's workspace grows
- * with the reads and min(n_cands, n_reads * ceiling).  Candidate lists must
- * not overlap (cand_start non-decreasing); a read whose list is out of range
- * gets SOAP_DP_TASK_INVALID_OFFSET. */
+ * with the reads and min(n_cands, n_reads * ceiling).  cand_start must be
+ * non-decreasing, so that the lists do not overlap; if any entry is smaller
+ * than the one before it, every read of the call gets
+ * SOAP_DP_TASK_INVALID_OFFSET (n_aligned 0).  Otherwise a read whose list
+ * lies outside [0, n_cands) gets SOAP_DP_TASK_INVALID_OFFSET on its own. */
 int soap_dp_align_multi(soap_dp_ctx *ctx, const soap_dp_multi_batch *in, const soap_dp_scoring *sc,
                         const soap_dp_multi_result *out, void *stream);
 

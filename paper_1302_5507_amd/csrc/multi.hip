@@ -55,29 +55,42 @@ __device__ __forceinline__ bool cand_ok(const MultiIn &in, int64_t c) {
 }
 
 // Per read: validity and the number of valid candidates kept under the
-// ceiling (its task count).
+// ceiling (its task count).  A list that runs backwards (cand_start[r+1] <
+// cand_start[r]) makes the lists of other reads overlap, whatever read r's
+// own status: its count is written as -1, which the scan turns into the
+// mark kBadList that condemns the whole call.
 __global__ __launch_bounds__(kBlock) void count_kernel(MultiIn in, MultiWork w, MultiOut out) {
   const int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (r >= in.n_reads) return;
+  const int64_t a = in.cand_start[r], b = in.cand_start[r + 1];
   uint8_t st;
   int64_t valid = 0;
   if (read_ok(in, r, &st)) {
-    const int64_t a = in.cand_start[r], b = in.cand_start[r + 1];
     if (a < 0 || b < a || b > in.n_cands)
       st = kTaskInvalidOffset;
     else
       for (int64_t c = a; c < b; ++c) valid += cand_ok(in, c) ? 1 : 0;
   }
   const int32_t cnt = st == kTaskOk ? (int32_t)min(valid, (int64_t)in.ceiling) : 0;
-  out.n_aligned[r] = cnt;
+  out.n_aligned[r] = b < a ? -1 : cnt;
   w.flag[r] = st != kTaskOk ? st : (cnt == 0 ? (uint8_t)SOAP_DP_TASK_NO_CANDIDATE : kTaskOk);
 }
 
 // Exclusive scan of the task counts in three steps: within blocks of
 // kScanBlock reads, over the block sums (one workgroup), then the block
-// offsets added back.
+// offsets added back.  Every sum saturates at kBadList, far above any real
+// total (at most n_reads * ceiling), so a backwards list anywhere leaves
+// the total, off[n_reads], at exactly kBadList without overflow; a
+// well-formed call never reaches it.
 constexpr int kScanPer = 4;
 constexpr int kScanBlock = kBlock * kScanPer;
+constexpr int64_t kBadList = int64_t(1) << 48;
+
+__device__ __forceinline__ int64_t sat_add(int64_t x, int64_t y) { return min(x + y, kBadList); }
+
+__device__ __forceinline__ bool call_is_bad(const MultiIn &in, const MultiWork &w) {
+  return w.off[in.n_reads] >= kBadList;
+}
 
 __device__ __forceinline__ int64_t block_exclusive_scan(int64_t v, int64_t *s_tmp, int64_t *total) {
   // Hillis-Steele over the workgroup in LDS
@@ -87,7 +100,7 @@ __device__ __forceinline__ int64_t block_exclusive_scan(int64_t v, int64_t *s_tm
   for (int d = 1; d < kBlock; d <<= 1) {
     const int64_t add = x >= d ? s_tmp[x - d] : 0;
     __syncthreads();
-    s_tmp[x] += add;
+    s_tmp[x] = sat_add(s_tmp[x], add);
     __syncthreads();
   }
   const int64_t incl = s_tmp[x];
@@ -102,15 +115,16 @@ __global__ __launch_bounds__(kBlock) void scan_local_kernel(MultiIn in, MultiWor
   int64_t v[kScanPer], sum = 0;
 #pragma unroll
   for (int j = 0; j < kScanPer; ++j) {
-    v[j] = base + j < in.n_reads ? out.n_aligned[base + j] : 0;
-    sum += v[j];
+    const int32_t n = base + j < in.n_reads ? out.n_aligned[base + j] : 0;
+    v[j] = n < 0 ? kBadList : n;
+    sum = sat_add(sum, v[j]);
   }
   int64_t total;
   int64_t run = block_exclusive_scan(sum, s_tmp, &total);
 #pragma unroll
   for (int j = 0; j < kScanPer; ++j) {
     if (base + j < in.n_reads) w.off[base + j] = run;
-    run += v[j];
+    run = sat_add(run, v[j]);
   }
   if (threadIdx.x == 0) w.bsum[blockIdx.x] = total;
 }
@@ -121,13 +135,13 @@ __global__ __launch_bounds__(kBlock) void scan_blocks_kernel(MultiIn in, MultiWo
   const int64_t per = (nb + kBlock - 1) / kBlock;
   const int64_t a = min((int64_t)threadIdx.x * per, nb), b = min(a + per, nb);
   int64_t sum = 0;
-  for (int64_t k = a; k < b; ++k) sum += w.bsum[k];
+  for (int64_t k = a; k < b; ++k) sum = sat_add(sum, w.bsum[k]);
   int64_t total;
   int64_t run = block_exclusive_scan(sum, s_tmp, &total);
   for (int64_t k = a; k < b; ++k) {
     const int64_t c = w.bsum[k];
     w.bsum[k] = run;
-    run += c;
+    run = sat_add(run, c);
   }
   if (threadIdx.x == 0) w.off[in.n_reads] = total;
 }
@@ -135,7 +149,7 @@ __global__ __launch_bounds__(kBlock) void scan_blocks_kernel(MultiIn in, MultiWo
 __global__ __launch_bounds__(kBlock) void scan_add_kernel(MultiIn in, MultiWork w) {
   const int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (r >= in.n_reads) return;
-  w.off[r] += w.bsum[r / kScanBlock];
+  w.off[r] = sat_add(w.off[r], w.bsum[r / kScanBlock]);
 }
 
 // Every slot emptied (a zero-length task the batched form skips) before
@@ -156,8 +170,9 @@ __global__ __launch_bounds__(kBlock) void pad_kernel(MultiIn in, MultiWork w) {
 // a rank under the ceiling places the candidate at task off[r] + rank.
 __global__ __launch_bounds__(kBlock) void rank_kernel(MultiIn in, MultiWork w) {
   const int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (c >= in.n_cands) return;
-  // owning read: the last r with cand_start[r] <= c
+  if (c >= in.n_cands || call_is_bad(in, w)) return;
+  // owning read: the last r with cand_start[r] <= c (cand_start is
+  // non-decreasing in a call that is not condemned)
   int64_t lo = 0, hi = in.n_reads - 1;
   while (lo < hi) {
     const int64_t mid = (lo + hi + 1) >> 1;
@@ -176,8 +191,7 @@ __global__ __launch_bounds__(kBlock) void rank_kernel(MultiIn in, MultiWork w) {
     rank += (sd > s || (sd == s && d < c)) ? 1 : 0;
   }
   const int64_t t = w.off[r] + rank;
-  // (a malformed, overlapping candidate list could count past the slots)
-  if (rank >= C || t >= in.n_slots) return;
+  if (rank >= C || t >= in.n_slots) return;   // (t < n_slots holds here; kept as a guard)
   w.t_rwo[t] = in.read_word_off[r] + (in.cand_strand[c] ? in.read_words : 0);
   w.t_rl[t] = in.read_len[r];
   w.t_rbo[t] = in.cand_base_off[c];
@@ -193,7 +207,9 @@ __global__ __launch_bounds__(kBlock) void reduce_kernel(MultiIn in, MultiWork w,
   if (r >= in.n_reads) return;
   int32_t best = -1, best_s = 0, second = INT32_MIN;
   const int64_t t0 = w.off[r];
-  if (w.flag[r] == kTaskOk) {
+  if (call_is_bad(in, w)) {
+    w.flag[r] = kTaskInvalidOffset;   // overlapping lists: every read rejected
+  } else if (w.flag[r] == kTaskOk) {
     const int32_t cnt = out.n_aligned[r];
     for (int32_t k = 0; k < cnt && t0 + k < in.n_slots; ++k) {
       const int64_t t = t0 + k;

@@ -199,23 +199,23 @@ def test_multi_fresh_context_first_call():
 
 
 def test_multi_malformed_candidate_start():
-    """A candidate list that runs backwards (cand_start[r+1] < cand_start[r])
-    marks that read INVALID_OFFSET; the overlap it creates with the next
-    read's list leaves no stale tasks, and reads away from it are exact."""
+    """cand_start that runs backwards anywhere (cand_start[r+1] <
+    cand_start[r]) makes lists overlap: every read of the call is rejected
+    with INVALID_OFFSET, whether the backwards read's own length is valid or
+    not, and the same context then aligns a well-formed call exactly."""
     mw = workloads.multi_candidate(400, seed=60)
-    cs = mw.cand_start.copy()
-    r = 200
-    cs[r + 1] = cs[r] - 3            # read r runs backwards; read r+1 overlaps read r-1
-    bad = workloads.MultiWorkload("malformed", mw.genome, mw.read_codes, mw.read_off,
-                                  mw.read_len, cs, mw.cand_off, mw.cand_len, mw.cand_support,
-                                  mw.cand_strand, mw.true_cand)
-    g, dm = _gpu(bad, 30)
-    assert g["status"][r] == binding.TASK_INVALID_OFFSET and g["n_aligned"][r] == 0
-    ref = _oracle(mw, 30, CONFIG_SCORING, dm.max_n, dm.max_m)
-    away = np.r_[0:r - 1, r + 2:mw.n_reads]
-    gs = {k: v[away] for k, v in g.items()}
-    for f in ("score", "ref_begin", "ref_end", "cigar_len", "best_cand", "second_score",
-              "n_aligned"):
-        assert np.array_equal(np.asarray(gs[f]).astype(np.int64),
-                              np.asarray(getattr(ref, f))[away].astype(np.int64)), f
-    assert np.isin(g["status"][r + 1], (0, 2, 4))
+    for r, bad_len in ((200, False), (399, False), (0, True)):
+        cs = mw.cand_start.copy()
+        cs[r + 1] = cs[r] - 3
+        rl = mw.read_len.copy()
+        if bad_len:
+            rl[r] = 0
+        bad = workloads.MultiWorkload("malformed", mw.genome, mw.read_codes, mw.read_off,
+                                      rl, cs, mw.cand_off, mw.cand_len, mw.cand_support,
+                                      mw.cand_strand, mw.true_cand)
+        g, _ = _gpu(bad, 30)
+        assert (g["status"] == binding.TASK_INVALID_OFFSET).all(), r
+        assert (g["n_aligned"] == 0).all() and (g["best_cand"] == -1).all()
+        assert (g["score"] == 0).all() and (g["cigar_len"] == 0).all()
+    g, dm = _gpu(mw, 30)
+    _compare(g, _oracle(mw, 30, CONFIG_SCORING, dm.max_n, dm.max_m), "after a rejected call")
