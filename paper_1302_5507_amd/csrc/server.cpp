@@ -24,6 +24,7 @@
 
 #include "../../include/soap_dp.h"
 #include "batch.h"
+#include "serve_rest.h"
 
 namespace {
 
@@ -74,13 +75,20 @@ struct Slot {
   uint32_t *d_cigar = nullptr;
   uint32_t *d_head = nullptr;     // first CIGAR words of every task (dense)
   uint8_t *d_status = nullptr;
+  // rests of the rows longer than the head, packed on the device
+  int32_t rest_rows = 0, rest_words = 0;   // capacities
+  int32_t *d_rest_hdr = nullptr;
+  soapdp::RestRow *d_rest_rows = nullptr;
+  uint32_t *d_rest = nullptr;
   // pinned host staging
   uint32_t *h_reads = nullptr;
   uint64_t *h_rwo = nullptr, *h_rbo = nullptr;
   int32_t *h_rl = nullptr, *h_ml = nullptr;
   int32_t *h_i32 = nullptr;
   uint32_t *h_head = nullptr;     // copy of d_head
-  uint32_t *h_rest = nullptr;     // rest of the CIGARs longer than the head
+  int32_t *h_rest_hdr = nullptr;  // copies of d_rest_hdr, d_rest_rows, d_rest
+  soapdp::RestRow *h_rest_rows = nullptr;
+  uint32_t *h_rest = nullptr;
   uint8_t *h_status = nullptr;
   // batch in flight
   bool busy = false;
@@ -114,10 +122,12 @@ void free_slot(Slot &s) {
   if (s.start) (void)hipEventDestroy(s.start);
   if (s.done) (void)hipEventDestroy(s.done);
   for (void *p : {(void *)s.d_reads, (void *)s.d_rwo, (void *)s.d_rbo, (void *)s.d_rl, (void *)s.d_ml,
-                  (void *)s.d_i32, (void *)s.d_cigar, (void *)s.d_status, (void *)s.d_head})
+                  (void *)s.d_i32, (void *)s.d_cigar, (void *)s.d_status, (void *)s.d_head,
+                  (void *)s.d_rest_hdr, (void *)s.d_rest_rows, (void *)s.d_rest})
     if (p) (void)hipFree(p);
   for (void *p : {(void *)s.h_reads, (void *)s.h_rwo, (void *)s.h_rbo, (void *)s.h_rl, (void *)s.h_ml,
-                  (void *)s.h_i32, (void *)s.h_head, (void *)s.h_rest, (void *)s.h_status})
+                  (void *)s.h_i32, (void *)s.h_head, (void *)s.h_rest_hdr, (void *)s.h_rest_rows,
+                  (void *)s.h_rest, (void *)s.h_status})
     if (p) (void)hipHostFree(p);
   s = Slot{};
 }
@@ -131,14 +141,21 @@ int init_slot(soap_dp_server *srv, Slot &s) {
       hipEventCreateWithFlags(&s.start, hipEventDefault) != hipSuccess ||
       hipEventCreateWithFlags(&s.done, hipEventDefault) != hipSuccess)
     return SOAP_DP_EHIP;
+  // room for the rests of up to 1,024 long rows per batch (fewer for small
+  // slots), 128 KB of words
+  s.rest_rows = int32_t(std::min<size_t>(T, 1024));
+  s.rest_words = int32_t(std::min<size_t>(T * soapdp::kCigarHeadWords, 32768));
   const bool ok = dalloc(&s.d_reads, Wd) && dalloc(&s.d_rwo, T) && dalloc(&s.d_rbo, T) &&
                   dalloc(&s.d_rl, T) && dalloc(&s.d_ml, T) && dalloc(&s.d_i32, 4 * T) &&
                   dalloc(&s.d_cigar, T * S) && dalloc(&s.d_status, T) &&
                   dalloc(&s.d_head, T * soapdp::kCigarHeadWords) &&
+                  dalloc(&s.d_rest_hdr, 2) && dalloc(&s.d_rest_rows, size_t(s.rest_rows)) &&
+                  dalloc(&s.d_rest, size_t(s.rest_words)) &&
                   halloc(&s.h_reads, Wd) && halloc(&s.h_rwo, T) && halloc(&s.h_rbo, T) &&
                   halloc(&s.h_rl, T) && halloc(&s.h_ml, T) && halloc(&s.h_i32, 4 * T) &&
                   halloc(&s.h_head, T * soapdp::kCigarHeadWords) &&
-                  halloc(&s.h_rest, T * soapdp::kCigarHeadWords) &&
+                  halloc(&s.h_rest_hdr, 2) && halloc(&s.h_rest_rows, size_t(s.rest_rows)) &&
+                  halloc(&s.h_rest, size_t(s.rest_words)) &&
                   halloc(&s.h_status, T);
   if (!ok) {
     (void)hipGetLastError();
@@ -148,28 +165,17 @@ int init_slot(soap_dp_server *srv, Slot &s) {
 }
 
 // Finished batch: copy each request's slice to its caller buffers.  CIGARs
-// come from the dense head copy; the rest of the rare longer rows is
-// fetched with one queued copy per row and a single wait.
+// come from the dense head copy; the rests of the rare longer rows were
+// packed on the device and came back with the batch.  A long row that did
+// not fit that area is fetched on its own, with a synchronous copy.
 void retire(soap_dp_server *srv, Slot &s) {
   const int32_t T = srv->cfg.max_tasks;
   const int32_t S = srv->stride;
   constexpr int32_t H = soapdp::kCigarHeadWords;
-  // rows longer than the head: their rest packed into h_rest (T * H words);
-  // in the unlikely case that it fills up, the remaining rows are fetched
-  // one by one below
-  bool fetched = true;
-  std::unordered_map<int32_t, int64_t> rest_at;   // task -> offset in h_rest
-  int64_t rest = 0;
-  for (int32_t t = 0; t < s.tasks; ++t) {
-    const int32_t len = std::min(s.h_i32[3 * T + t], S);
-    if (len <= H || rest + (len - H) > int64_t(T) * H) continue;
-    fetched = fetched && hipMemcpyAsync(s.h_rest + rest, s.d_cigar + int64_t(t) * S + H,
-                                        size_t(len - H) * 4, hipMemcpyDeviceToHost,
-                                        s.stream) == hipSuccess;
-    rest_at.emplace(t, rest);
-    rest += len - H;
-  }
-  if (!rest_at.empty()) fetched = fetched && hipStreamSynchronize(s.stream) == hipSuccess;
+  std::unordered_map<int32_t, int32_t> rest_at;   // task -> offset in h_rest
+  const int32_t listed = std::min(s.h_rest_hdr[0], s.rest_rows);
+  for (int32_t k = 0; k < listed; ++k)
+    if (s.h_rest_rows[k].off >= 0) rest_at.emplace(s.h_rest_rows[k].task, s.h_rest_rows[k].off);
   struct Finished {
     uint64_t ticket;
     int rc;
@@ -189,23 +195,33 @@ void retire(soap_dp_server *srv, Slot &s) {
     int rc = SOAP_DP_OK;
     const int32_t *lens = s.h_i32 + 3 * T + f;
     const uint32_t *head = s.h_head + int64_t(f) * H;
+    int64_t total = 0;
+    for (int32_t t = 0; t < n; ++t) total += std::min(std::max(lens[t], 0), S);
+    // A row whose full head (H words) ends within the request's packed
+    // CIGARs is copied whole, with no length-dependent branch; the words
+    // past the row are rewritten by the rows after it, which are copied
+    // later.  Other rows, and every row of a request that does not fit its
+    // buffer, are copied word by word up to their length.
+    const bool whole = total <= o.cigar_capacity;
     for (int32_t t = 0; t < n; ++t) {
       const int32_t len = std::min(std::max(lens[t], 0), S);
       if (words + len > o.cigar_capacity) {
         rc = SOAP_DP_E2BIG;   // keeps counting; writes nothing past the buffer
       } else {
-        // most rows are a few words: a plain loop beats a memcpy call
         uint32_t *dst = o.cigar + words;
         const uint32_t *src = head + int64_t(t) * H;
-        const int32_t hn = std::min(len, H);
-        for (int32_t k = 0; k < hn; ++k) dst[k] = src[k];
+        if (whole && words + H <= total) {
+          std::memcpy(dst, src, sizeof(uint32_t) * H);
+        } else {
+          const int32_t hn = std::min(len, H);
+          for (int32_t k = 0; k < hn; ++k) dst[k] = src[k];
+        }
         if (len > H) {
           auto it = rest_at.find(f + t);
           uint32_t *rdst = dst + H;
-          if (it != rest_at.end() && fetched)
+          if (it != rest_at.end())
             std::memcpy(rdst, s.h_rest + it->second, size_t(len - H) * 4);
-          else if (it != rest_at.end() ||
-                   hipMemcpy(rdst, s.d_cigar + int64_t(f + t) * S + H, size_t(len - H) * 4,
+          else if (hipMemcpy(rdst, s.d_cigar + int64_t(f + t) * S + H, size_t(len - H) * 4,
                              hipMemcpyDeviceToHost) != hipSuccess)
             rc = SOAP_DP_EHIP;
         }
@@ -299,7 +315,10 @@ int launch(soap_dp_server *srv, Slot &s, std::vector<std::unique_ptr<Request>> &
   out.status = s.d_status;
   const int rc = soap_dp_align_batch(s.ctx, &in, &c.scoring, &out, st, SOAP_DP_BATCHED);
   if (rc) return rc;
-  ok = soapdp::launch_gather_cigar_head(s.d_cigar, S, s.d_i32 + 3 * T, nt, s.d_head, st) == hipSuccess;
+  ok = soapdp::launch_gather_cigar_head(s.d_cigar, S, s.d_i32 + 3 * T, nt, s.d_head, st) == hipSuccess &&
+       soapdp::launch_pack_cigar_rest(s.d_cigar, S, s.d_i32 + 3 * T, nt, soapdp::kCigarHeadWords,
+                                      s.d_rest_hdr, s.d_rest_rows, s.rest_rows, s.d_rest,
+                                      s.rest_words, st) == hipSuccess;
   for (int a = 0; ok && a < 4; ++a)
     ok = hipMemcpyAsync(s.h_i32 + size_t(a) * T, s.d_i32 + size_t(a) * T, size_t(nt) * 4,
                         hipMemcpyDeviceToHost, st) == hipSuccess;
@@ -307,6 +326,12 @@ int launch(soap_dp_server *srv, Slot &s, std::vector<std::unique_ptr<Request>> &
        hipMemcpyAsync(s.h_status, s.d_status, size_t(nt), hipMemcpyDeviceToHost, st) == hipSuccess &&
        hipMemcpyAsync(s.h_head, s.d_head, size_t(nt) * soapdp::kCigarHeadWords * 4,
                       hipMemcpyDeviceToHost, st) == hipSuccess &&
+       hipMemcpyAsync(s.h_rest_hdr, s.d_rest_hdr, 2 * sizeof(int32_t), hipMemcpyDeviceToHost,
+                      st) == hipSuccess &&
+       hipMemcpyAsync(s.h_rest_rows, s.d_rest_rows, size_t(s.rest_rows) * sizeof(soapdp::RestRow),
+                      hipMemcpyDeviceToHost, st) == hipSuccess &&
+       hipMemcpyAsync(s.h_rest, s.d_rest, size_t(s.rest_words) * 4, hipMemcpyDeviceToHost,
+                      st) == hipSuccess &&
        hipEventRecord(s.done, st) == hipSuccess;
   if (!ok) return SOAP_DP_EHIP;
   s.busy = true;
