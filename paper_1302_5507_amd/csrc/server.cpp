@@ -77,6 +77,7 @@ struct Slot {
   uint8_t *d_status = nullptr;
   // rests of the rows longer than the head, packed on the device
   int32_t rest_rows = 0, rest_words = 0;   // capacities
+  int32_t batch_rest_rows = 0, batch_rest_words = 0;   // the part the batch in flight uses
   int32_t *d_rest_hdr = nullptr;
   soapdp::RestRow *d_rest_rows = nullptr;
   uint32_t *d_rest = nullptr;
@@ -173,7 +174,7 @@ void retire(soap_dp_server *srv, Slot &s) {
   const int32_t S = srv->stride;
   constexpr int32_t H = soapdp::kCigarHeadWords;
   std::unordered_map<int32_t, int32_t> rest_at;   // task -> offset in h_rest
-  const int32_t listed = std::min(s.h_rest_hdr[0], s.rest_rows);
+  const int32_t listed = std::min(s.h_rest_hdr[0], s.batch_rest_rows);
   for (int32_t k = 0; k < listed; ++k)
     if (s.h_rest_rows[k].off >= 0) rest_at.emplace(s.h_rest_rows[k].task, s.h_rest_rows[k].off);
   struct Finished {
@@ -315,10 +316,13 @@ int launch(soap_dp_server *srv, Slot &s, std::vector<std::unique_ptr<Request>> &
   out.status = s.d_status;
   const int rc = soap_dp_align_batch(s.ctx, &in, &c.scoring, &out, st, SOAP_DP_BATCHED);
   if (rc) return rc;
+  // the rest area this batch may use, and copy back, grows with its tasks
+  s.batch_rest_rows = std::min(s.rest_rows, std::max(16, nt / 64));
+  s.batch_rest_words = std::min(s.rest_words, std::max(512, nt / 4));
   ok = soapdp::launch_gather_cigar_head(s.d_cigar, S, s.d_i32 + 3 * T, nt, s.d_head, st) == hipSuccess &&
        soapdp::launch_pack_cigar_rest(s.d_cigar, S, s.d_i32 + 3 * T, nt, soapdp::kCigarHeadWords,
-                                      s.d_rest_hdr, s.d_rest_rows, s.rest_rows, s.d_rest,
-                                      s.rest_words, st) == hipSuccess;
+                                      s.d_rest_hdr, s.d_rest_rows, s.batch_rest_rows, s.d_rest,
+                                      s.batch_rest_words, st) == hipSuccess;
   for (int a = 0; ok && a < 4; ++a)
     ok = hipMemcpyAsync(s.h_i32 + size_t(a) * T, s.d_i32 + size_t(a) * T, size_t(nt) * 4,
                         hipMemcpyDeviceToHost, st) == hipSuccess;
@@ -328,9 +332,10 @@ int launch(soap_dp_server *srv, Slot &s, std::vector<std::unique_ptr<Request>> &
                       hipMemcpyDeviceToHost, st) == hipSuccess &&
        hipMemcpyAsync(s.h_rest_hdr, s.d_rest_hdr, 2 * sizeof(int32_t), hipMemcpyDeviceToHost,
                       st) == hipSuccess &&
-       hipMemcpyAsync(s.h_rest_rows, s.d_rest_rows, size_t(s.rest_rows) * sizeof(soapdp::RestRow),
-                      hipMemcpyDeviceToHost, st) == hipSuccess &&
-       hipMemcpyAsync(s.h_rest, s.d_rest, size_t(s.rest_words) * 4, hipMemcpyDeviceToHost,
+       hipMemcpyAsync(s.h_rest_rows, s.d_rest_rows,
+                      size_t(s.batch_rest_rows) * sizeof(soapdp::RestRow), hipMemcpyDeviceToHost,
+                      st) == hipSuccess &&
+       hipMemcpyAsync(s.h_rest, s.d_rest, size_t(s.batch_rest_words) * 4, hipMemcpyDeviceToHost,
                       st) == hipSuccess &&
        hipEventRecord(s.done, st) == hipSuccess;
   if (!ok) return SOAP_DP_EHIP;
