@@ -125,3 +125,33 @@ def test_long_cigars_fetched_in_full():
             _check_oracle(pool, r)
     finally:
         srv.close()
+
+
+def test_many_long_cigars_in_one_batch():
+    """A batch of 2,048 reads whose CIGARs all run past the 16-word head:
+    the device packs the rests of the first rows it lists (32 rows, 512
+    words for a batch this size); the rows that do not fit that area, and
+    those past the list, are fetched one by one.  Every CIGAR must equal the
+    oracle's."""
+    import torch
+    from paper_1302_5507_amd.workloads import _geometric_trunc, simulate
+    g = workloads.random_genome(2_000_000, 9)
+    gw = torch.from_numpy(binding.pack_words(g).view(np.int32)).cuda()
+    rng = np.random.Generator(np.random.PCG64(22))
+    n = np.full(2048, 250)
+    m = n + 160
+    pool = simulate("long-cigars-2k", g, n, m, lambda r, idx: r.integers(0, 100, size=idx.size),
+                    0.02, 0.12, lambda r, k: _geometric_trunc(r, 0.5, k, 4), rng)
+    ref = oracle_align(pool, CONFIG_SCORING, stride=500)
+    assert (ref.cigar_len > 16).sum() > 1000, "fixture should have many long CIGARs"
+    srv = serving.Server(gw, n_slots=1, max_tasks=2048, max_n=250, max_m=410, autotune=False)
+    try:
+        r = serving.requests_from_pool(pool, [2048])[0]
+        big = serving.HostRequest(r.read_words, r.read_word_off, r.read_len, r.ref_base_off,
+                                  r.ref_len, cigar_words_per_task=499)
+        big.pool_idx = r.pool_idx
+        srv.submit(big)
+        assert srv.wait(big) == 0
+        _check_oracle(pool, big)
+    finally:
+        srv.close()
