@@ -521,7 +521,11 @@ hipError_t enqueue_batched(soap_dp_ctx *ctx, const soap_dp_batch *in, const soap
   if ((e = hipEventRecord(ctx->fork_event, stream)) != hipSuccess) return e;
   p.task_list = ctx->task_list;
   p.scratch = static_cast<uint32_t *>(ctx->scratch);
-  for (size_t li = 0; li < live.size(); ++li) {
+  // Largest capacity first: the classes of long reads run longest, and the
+  // class streams share a few hardware queues, where a kernel enqueued
+  // behind another waits for it to finish.  Longest first keeps the batch
+  // close to its longest kernel.
+  for (size_t li = live.size(); li-- > 0;) {
     const int k = live[li];
     const ClassSpec &c = ctx->classes[size_t(k)];
     hipStream_t cs = ctx->class_streams[li];
