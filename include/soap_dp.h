@@ -380,7 +380,7 @@ typedef struct soap_dp_server soap_dp_server;
 
 typedef struct {
   int device_ordinal;
-  int n_slots;                 /* batches in flight at once (streams), 1..16 */
+  int n_slots;                 /* batches in flight at once (streams), 1..4 */
   int32_t max_tasks;           /* tasks per slot (per merged batch) */
   int64_t max_read_words;      /* packed read words per slot */
   int32_t max_n, max_m;        /* bounds on every task of every request */

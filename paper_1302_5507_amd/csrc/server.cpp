@@ -437,10 +437,15 @@ extern "C" {
 
 uint64_t soap_dp_now_ns(void) { return now_ns(); }
 
+// Slot counts run and checked: 1 to 4.  A run with 6 slots of 32,768 reads
+// ended in a host crash whose cause is not known; larger counts are refused
+// until it is.
+constexpr int kMaxSlots = 4;
+
 int soap_dp_server_create(soap_dp_server **out, const soap_dp_server_config *cfg) {
   if (!out || !cfg) return SOAP_DP_EINVAL;
   *out = nullptr;
-  if (cfg->n_slots < 1 || cfg->n_slots > 16 || cfg->max_tasks < 1 || cfg->max_read_words < 1 ||
+  if (cfg->n_slots < 1 || cfg->n_slots > kMaxSlots || cfg->max_tasks < 1 || cfg->max_read_words < 1 ||
       cfg->max_n < 1 || cfg->max_n > SOAP_DP_MAX_READ || cfg->max_m < 1 ||
       cfg->max_m > SOAP_DP_MAX_WINDOW || !cfg->genome || cfg->genome_words == 0)
     return SOAP_DP_EINVAL;

@@ -118,3 +118,16 @@ def test_ctypes_structs_match_header_layout(tmp_path):
         assert got[(cname, "size")] == ctypes.sizeof(py), cname
         for f in py._fields_:
             assert got[(cname, f[0])] == getattr(py, f[0]).offset, (cname, f[0])
+
+
+def test_server_rejects_slot_counts_outside_1_to_4():
+    """Argument checks of soap_dp_server_create run before any device call."""
+    import ctypes
+    from paper_1302_5507_amd import serving
+    L = serving._lib()
+    for n in (0, 5, 16):
+        cfg = serving.ServerConfig(0, n, 1024, 1024 * 16, 250, 410, binding.Scoring(1, -3, -5, -2),
+                                   ctypes.c_void_p(64), 1, 0)
+        h = ctypes.c_void_p()
+        assert L.soap_dp_server_create(ctypes.byref(h), ctypes.byref(cfg)) == binding.SOAP_DP_EINVAL
+        assert not h.value
