@@ -55,6 +55,10 @@ const ClassSpec kDefaultClasses[] = {
     {32, 152, {8, 19}},  {32, 256, {16, 16}}, {32, 512, {32, 16}},
 };
 
+// What a captured batched call depends on: every pointer and size of the
+// batch and the outputs, the scoring, the context's buffer epoch and the
+// flags.  Compared field by field (the ABI structs carry padding whose
+// bytes are unspecified).
 struct GraphKey {
   soap_dp_batch in;
   soap_dp_scoring sc;
@@ -63,13 +67,35 @@ struct GraphKey {
   uint32_t flags;
 };
 
+bool same_batch(const soap_dp_batch &a, const soap_dp_batch &b) {
+  return a.read_codes == b.read_codes && a.read_word_off == b.read_word_off &&
+         a.read_len == b.read_len && a.ref_codes == b.ref_codes &&
+         a.ref_base_off == b.ref_base_off && a.ref_len == b.ref_len && a.n_tasks == b.n_tasks &&
+         a.max_n == b.max_n && a.max_m == b.max_m && a.read_words == b.read_words &&
+         a.ref_words == b.ref_words;
+}
+
+bool same_scoring(const soap_dp_scoring &a, const soap_dp_scoring &b) {
+  return a.match == b.match && a.mismatch == b.mismatch && a.gap_open == b.gap_open &&
+         a.gap_extend == b.gap_extend && a.min_score == b.min_score;
+}
+
+bool same_result(const soap_dp_result &a, const soap_dp_result &b) {
+  return a.score == b.score && a.ref_begin == b.ref_begin && a.ref_end == b.ref_end &&
+         a.cigar == b.cigar && a.cigar_stride == b.cigar_stride && a.cigar_len == b.cigar_len &&
+         a.status == b.status;
+}
+
 struct GraphEntry {
   GraphKey key;
   hipGraphExec_t exec;
   uint64_t last_use;
 };
 
-bool same_key(const GraphKey &a, const GraphKey &b) { return std::memcmp(&a, &b, sizeof(GraphKey)) == 0; }
+bool same_key(const GraphKey &a, const GraphKey &b) {
+  return same_batch(a.in, b.in) && same_scoring(a.sc, b.sc) && same_result(a.out, b.out) &&
+         a.epoch == b.epoch && a.flags == b.flags;
+}
 
 }  // namespace
 

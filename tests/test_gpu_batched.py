@@ -7,6 +7,7 @@ import os
 import numpy as np
 import pytest
 
+import oracle
 from paper_1302_5507_amd import binding, workloads
 from tests.conftest import CONFIG_SCORING, SCORING_SETS
 from tests.gpu_util import assert_same, oracle_align
@@ -14,13 +15,14 @@ from tests.gpu_util import assert_same, oracle_align
 pytestmark = pytest.mark.gpu
 
 
-def run(al, w, sc, flags=binding.BATCHED, max_n=None, max_m=None, repeat=1):
+def run(al, w, sc, flags=binding.BATCHED, max_n=None, max_m=None, repeat=1, min_score=None):
     import torch
     dw = binding.DeviceWorkload(w)
     mn = max_n or dw.max_n
-    res = binding.DeviceResult(w.n_tasks, 2 * mn)
+    res = binding.DeviceResult(w.n_tasks, 0 if flags & binding.SCORE_ONLY else 2 * mn)
     for _ in range(repeat):
-        al.align(dw, sc, flags=flags, res=res, max_n=mn, max_m=max_m or dw.max_m)
+        al.align(dw, sc, flags=flags, res=res, max_n=mn, max_m=max_m or dw.max_m,
+                 min_score=min_score)
     torch.cuda.synchronize()
     return res.to_host()
 
@@ -92,11 +94,55 @@ def _int16_fits(n, m, cols, sc):
     return lo - 2 * s > -32000 and hi + 2 * s < 32000
 
 
+def _redo_set(al, w, sc):
+    """Tasks the batched form must leave to the int32 kernels: those outside
+    the int16 range rule of their length class."""
+    return np.array([not _int16_fits(int(n), int(m), _int16_class_cols(al, int(n)), sc)
+                     for n, m in zip(w.read_len, w.ref_len)])
+
+
+@pytest.mark.parametrize("k,int32_lengths", [(20, {250}), (30, {150, 250})])
+def test_mixed_int16_int32_batch(al, k, int32_lengths):
+    """All scores x k with k in the range where one batch populates both the
+    int16 and the int32 class kernels: at x20 only the 250 bp reads leave
+    int16, at x30 the 150 and 250 bp reads.  Every output of the full, the
+    score-only and the threshold calls equals the oracle's, and the tasks
+    marked OK_REDONE_INT32 are exactly those outside the int16 range."""
+    sc = tuple(k * x for x in CONFIG_SCORING)
+    w = workloads.config3(n_reads=6000, seed=23)
+    want = _redo_set(al, w, sc)
+    assert set(np.unique(w.read_len[want]).tolist()) == int32_lengths
+    assert want.any() and (~want).any()
+    ref = oracle_align(w, sc)
+    assert (ref.status == 0).all()
+    base = oracle_align(w, CONFIG_SCORING)
+    assert np.array_equal(ref.score, k * base.score)
+    # full call
+    g = run(al, w, sc)
+    assert np.array_equal(g["status"] == binding.TASK_OK_REDONE_INT32, want)
+    assert (g["status"][~want] == binding.TASK_OK).all()
+    assert_same(as_oracle_status(g), ref, label=f"x{k} full")
+    # score only
+    gs = run(al, w, sc, flags=binding.BATCHED | binding.SCORE_ONLY)
+    assert np.array_equal(gs["status"] == binding.TASK_OK_REDONE_INT32, want)
+    assert np.array_equal(gs["score"], ref.score) and np.array_equal(gs["ref_end"], ref.ref_end)
+    # score threshold: tasks below it report BELOW_CUTOFF whatever kernel ran them
+    for t in (0, 120 * sc[0]):
+        cut = oracle.apply_min_score(ref, t)
+        gc = run(al, w, sc, min_score=t)
+        below = cut.status == binding.TASK_BELOW_CUTOFF
+        assert below.any() and (~below).any()
+        assert np.array_equal(gc["status"] == binding.TASK_OK_REDONE_INT32, want & ~below)
+        assert_same(as_oracle_status(gc), cut, label=f"x{k} cutoff {t}")
+
+
 @pytest.mark.parametrize("k", [50, 100, 128])
-def test_overflow_redo_scaled(al, k):
-    """All scores x k: reads whose values leave int16 are re-run in int32
-    (status 2) and every output still equals the oracle's, which equals k
-    times the unscaled score with the same alignment."""
+def test_all_int32_scaled(al, k):
+    """All scores x k with k >= 32: the match constant relative to the
+    carried gap-open value, S_MA - S_GE - S_GO = 8k, no longer fits a byte,
+    so every task runs in the int32 kernels (status 2); every output still
+    equals the oracle's, which is k times the unscaled score with the same
+    alignment."""
     sc = tuple(k * x for x in CONFIG_SCORING)
     w = workloads.config3(n_reads=6000)
     g = run(al, w, sc)
@@ -104,10 +150,8 @@ def test_overflow_redo_scaled(al, k):
     assert_same(as_oracle_status(g), ref, label=f"x{k}")
     base = oracle_align(w, CONFIG_SCORING)
     assert np.array_equal(ref.score, k * base.score)
-    want = np.array([not _int16_fits(int(n), int(m), _int16_class_cols(al, int(n)), sc)
-                     for n, m in zip(w.read_len, w.ref_len)])
-    assert np.array_equal(g["status"] == binding.TASK_OK_REDONE_INT32, want)
-    assert want.any()
+    assert _redo_set(al, w, sc).all()
+    assert (g["status"] == binding.TASK_OK_REDONE_INT32).all()
 
 
 def test_small_scores_all_int16(al):

@@ -1,8 +1,9 @@
 """GPU: the score-only flag (SOAP_DP_SCORE_ONLY) gives exactly the score,
 end and status of the full call, in both forms and for every kernel path
-(int16, the int32 byte-table and general variants, the int32 re-run of
-tasks outside the int16 range), writes ref_begin -1 and cigar_len 0, and
-accepts a NULL CIGAR buffer."""
+(int16, the int32 byte-table and general variants; x30 scoring, where the
+150 and 250 bp reads leave the int16 range and one batch runs both int16
+and int32 class kernels; x50 scoring, where every task runs in int32),
+writes ref_begin -1 and cigar_len 0, and accepts a NULL CIGAR buffer."""
 import numpy as np
 import pytest
 
@@ -23,7 +24,7 @@ def _run(w, sc, flags, cigar=True):
 
 
 @pytest.mark.parametrize("form", [binding.PLAIN, binding.BATCHED])
-@pytest.mark.parametrize("sc", SCORING_SETS + [tuple(50 * x for x in CONFIG_SCORING)])
+@pytest.mark.parametrize("sc", SCORING_SETS + [tuple(k * x for x in CONFIG_SCORING) for k in (30, 50)])
 def test_score_only_equals_full(form, sc):
     w = workloads.config3(n_reads=4000, seed=31)
     ref = oracle_align(w, sc)
