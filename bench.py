@@ -118,7 +118,7 @@ def serve_bench(args):
     sizes = workloads.request_sizes(n_total, seed=104)
     reqs = serving.requests_from_pool(pool, sizes)
     srv = serving.Server(gw, n_slots=args.slots, max_tasks=args.slot_tasks, max_n=250, max_m=410,
-                         autotune=True)
+                         autotune=True, device_bytes=args.device_bytes)
     qps = args.qps if args.qps is not None else SERVE_QPS
     # the whole schedule is submitted ahead; the server admits each request
     # at its arrival time (all at once when measuring capacity)
@@ -136,6 +136,18 @@ def serve_bench(args):
         cells = sum(r.cells for r in reqs)
         span = (done.max() - arr.min()) * 1e-9
     lat = (done[meas] - arr[meas]) * 1e-6
+    # where the time went: queue (arrival to taken into a batch), launch
+    # (merge and enqueue), device (until the batch's results are in host
+    # memory), retire (hand-off into the request's buffers)
+    phases = np.array([r.phases_ns() for r in reqs[meas]], np.float64) * 1e-6
+    slow = lat >= np.percentile(lat, 99)
+    names = ("queue", "launch", "device", "retire")
+    breakdown = {
+        "p50": {k: round(float(np.percentile(phases[:, i], 50)), 3) for i, k in enumerate(names)},
+        "p99": {k: round(float(np.percentile(phases[:, i], 99)), 3) for i, k in enumerate(names)},
+        "slowest_1pct_mean": {k: round(float(phases[slow, i].mean()), 3)
+                              for i, k in enumerate(names)},
+    }
     rng = np.random.default_rng(4)
     checked = 0
     for k in rng.choice(np.arange(args.serve_warmup, n_total), size=min(20, args.serve_requests),
@@ -171,6 +183,7 @@ def serve_bench(args):
         "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3),
                        "p99": round(float(np.percentile(lat, 99)), 3),
                        "max": round(float(lat.max()), 3)},
+        "latency_phases_ms": breakdown,
         "achieved_qps": round((args.serve_requests if qps > 0 else n_total) / span, 1),
         "late_submissions": int((lag[meas] > 0).sum()),
         "server": {k: (round(v, 4) if isinstance(v, float) else v) for k, v in st.items()},
@@ -374,6 +387,9 @@ def main():
     ap.add_argument("--slots", type=int, default=3)
     ap.add_argument("--slot-tasks", type=int, default=131072, help="served workload: reads per slot")
     ap.add_argument("--pool-reads", type=int, default=400_000)
+    ap.add_argument("--device-bytes", type=int, default=0,
+                    help="served workload: device memory the batches in flight share (0: one "
+                         "full batch per slot)")
     ap.add_argument("--serve-warmup", type=int, default=1000)
     ap.add_argument("--serve-requests", type=int, default=20000)
     ap.add_argument("--form", choices=["plain", "batched", "both"], default="both")

@@ -361,33 +361,53 @@ int soap_dp_mate_rescue(soap_dp_ctx *ctx, const soap_dp_mate_batch *in, const so
 /* ------------------------------------------------------------------------
  * Serving: continuous batching over a device-resident genome.
  *
- * A server owns `n_slots` slots, each with its own stream, library context
- * and device buffers for up to `max_tasks` tasks.  Requests are queued on
- * submit; a dispatcher thread merges queued requests, first in first out,
- * into one batch per free slot (a request is admitted when the slot's
- * buffers have room for it), uploads the reads, runs the batched form on
- * the slot's stream and copies the results back, so several batches
- * overlap on the device while new requests keep arriving.  Windows are
- * base offsets into the resident genome: no sequence is copied for them.
- * Results are written into the caller's host buffers, which must stay
- * valid until the request completes; a request completes when
+ * A server owns `n_slots` slots, each with its own worker thread, stream,
+ * library context and pinned host staging for up to `max_tasks` tasks and
+ * `max_read_words` packed read words per batch.  Requests are queued on
+ * submit.  A free slot's worker takes the requests that have arrived, first
+ * in first out, and merges them into one batch while the batch stays within
+ * the slot's limits and its device buffers (reads, task arrays, outputs and
+ * CIGAR rows) fit the free part of the server's device memory budget
+ * (`device_bytes`, shared by all batches in flight).  It uploads the batch,
+ * runs the batched form on the slot's stream, copies the results back and
+ * hands each request its slice; the batch's device memory is then free for
+ * the next one.  Batches of different sizes therefore overlap on the device
+ * as memory and slots free up, while new requests keep arriving.  Windows
+ * are base offsets into the resident genome: no sequence is copied for them.
+ * Results are written into the caller's host buffers, which must stay valid
+ * until the request completes; a request completes when
  * soap_dp_server_wait returns for it.
- */
-#define SOAP_DP_E2BIG (-5)   /* request larger than one slot's capacity */
+ *
+ * A task of a request gets the same outputs whatever else is served with
+ * it, and the same as soap_dp_align_batch(SOAP_DP_BATCHED) gives for the
+ * request on its own (with read_words = the request's read_words): a task
+ * whose read lies outside the request's read words gets
+ * SOAP_DP_TASK_INVALID_OFFSET.
+ *
+ * The slots' contexts reserve their workspace and stream set at creation
+ * (after autotuning, when asked) and warm every kernel up there; serving
+ * then allocates nothing, captures no graph and never synchronises the
+ * whole device.
+ * ------------------------------------------------------------------------ */
+#define SOAP_DP_E2BIG (-5)   /* request larger than a slot or than the device budget */
 #define SOAP_DP_ESTOPPED (-6) /* server is shutting down */
 
 typedef struct soap_dp_server soap_dp_server;
 
 typedef struct {
   int device_ordinal;
-  int n_slots;                 /* batches in flight at once (streams), 1..4 */
-  int32_t max_tasks;           /* tasks per slot (per merged batch) */
-  int64_t max_read_words;      /* packed read words per slot */
+  int n_slots;                 /* batches in flight at once (worker threads, streams), 1..4 */
+  int32_t max_tasks;           /* tasks per merged batch */
+  int64_t max_read_words;      /* packed read words per merged batch */
   int32_t max_n, max_m;        /* bounds on every task of every request */
   soap_dp_scoring scoring;
   const uint32_t *genome;      /* DEVICE pointer, packed, caller-owned, resident */
   uint64_t genome_words;
   int autotune;                /* nonzero: autotune the slots' shapes at start */
+  uint64_t device_bytes;       /* device memory for the batches in flight, shared by the
+                                  slots; 0: room for n_slots batches at the slot limits.
+                                  It must hold at least one batch of one largest request;
+                                  the contexts' decision scratch is reserved apart from it */
 } soap_dp_server_config;
 
 /* HOST results of one served request.  CIGARs are packed: task t's runs
@@ -405,6 +425,15 @@ typedef struct {
   int64_t cigar_capacity;
 } soap_dp_host_result;
 
+/* Where a served request's time went, on soap_dp_now_ns's clock. */
+typedef struct {
+  uint64_t arrival_ns;   /* when it was due (admitted no earlier) */
+  uint64_t taken_ns;     /* a free slot's worker took it into a batch */
+  uint64_t launched_ns;  /* its batch's uploads, kernels and copies back were enqueued */
+  uint64_t device_ns;    /* the worker saw its batch's results arrive in host memory */
+  uint64_t done_ns;      /* its results were all in its buffers */
+} soap_dp_request_stamps;
+
 typedef struct {
   /* HOST arrays describing the request's tasks */
   const uint32_t *read_codes;     /* packed reads, read t at word read_word_off[t] */
@@ -418,6 +447,7 @@ typedef struct {
   uint64_t arrival_ns;            /* arrival time on the soap_dp_now_ns() clock: the
                                      request is admitted no earlier (0: on submission);
                                      requests are admitted in submission order */
+  soap_dp_request_stamps *stamps; /* HOST, optional: filled when the request completes */
 } soap_dp_request;
 
 typedef struct {
@@ -425,8 +455,10 @@ typedef struct {
   uint64_t tasks, cells;
   double device_busy_s;   /* sum over batches of upload start .. results copied
                              (slots overlap, so this can exceed wall time) */
-  double host_launch_s;   /* dispatcher time merging and enqueueing batches */
-  double host_retire_s;   /* dispatcher time handing results to requests */
+  double host_launch_s;   /* worker time merging and enqueueing batches */
+  double host_retire_s;   /* worker time handing results to requests */
+  uint64_t device_bytes;       /* the budget the batches in flight share */
+  uint64_t device_bytes_peak;  /* most of it the batches in flight held at once */
 } soap_dp_server_stats;
 
 /* Monotonic clock used for arrival and completion times (nanoseconds). */
@@ -435,8 +467,9 @@ uint64_t soap_dp_now_ns(void);
 int soap_dp_server_create(soap_dp_server **srv, const soap_dp_server_config *cfg);
 
 /* Queue a request; returns a ticket.  SOAP_DP_E2BIG if it can never fit a
- * slot.  The request's host arrays are copied before this returns; the
- * result arrays are written when it completes. */
+ * slot or the device budget.  The request's host arrays are copied before
+ * this returns; the result arrays (and stamps) are written when it
+ * completes. */
 int soap_dp_server_submit(soap_dp_server *srv, const soap_dp_request *req, uint64_t *ticket);
 
 /* 1 when the request has completed (results written), 0 while pending,

@@ -17,6 +17,7 @@
 
 #include "../../include/soap_dp.h"
 #include "batch.h"
+#include "ctx_internal.h"
 #include "dp_internal.h"
 #include "mate.h"
 #include "multi.h"
@@ -126,6 +127,8 @@ struct soap_dp_ctx {
   mutable std::unordered_map<uint32_t, int> occupancy;
   uint64_t use_clock = 0;
   bool use_graphs = true;
+  // serving: no growth, no graph capture (see ctx_set_frozen)
+  bool frozen = false;
   // multi-candidate work arrays (task slots, reverse complements)
   void *multi = nullptr;
   size_t multi_bytes = 0;
@@ -265,6 +268,7 @@ void clear_graphs(soap_dp_ctx *ctx) {
 
 int ensure_scratch(soap_dp_ctx *ctx, size_t bytes) {
   if (bytes <= ctx->scratch_bytes) return SOAP_DP_OK;
+  if (ctx->frozen) return SOAP_DP_ENOMEM;
   if (ctx->scratch) {
     if (hipDeviceSynchronize() != hipSuccess) return SOAP_DP_EHIP;   // earlier work may read it
     (void)hipFree(ctx->scratch);
@@ -284,6 +288,7 @@ int ensure_scratch(soap_dp_ctx *ctx, size_t bytes) {
 
 int ensure_task_buffers(soap_dp_ctx *ctx, int64_t n_tasks) {
   if (n_tasks <= ctx->task_cap) return SOAP_DP_OK;
+  if (ctx->frozen) return SOAP_DP_ENOMEM;
   if (ctx->task_list) {
     if (hipDeviceSynchronize() != hipSuccess) return SOAP_DP_EHIP;
     (void)hipFree(ctx->task_list);
@@ -491,6 +496,7 @@ size_t batched_scratch_bytes(const soap_dp_ctx *ctx, int64_t n_tasks, int32_t ma
 }
 
 int ensure_class_streams(soap_dp_ctx *ctx, size_t n) {
+  if (ctx->frozen && (ctx->class_streams.size() < n || !ctx->fork_event)) return SOAP_DP_ENOMEM;
   if (!ctx->fork_event &&
       hipEventCreateWithFlags(&ctx->fork_event, hipEventDisableTiming) != hipSuccess)
     return hip_fail(ctx, hipGetLastError());
@@ -582,7 +588,7 @@ int align_batched(soap_dp_ctx *ctx, const soap_dp_batch *in, const soap_dp_scori
   const BatchedPlan bp = batched_plan(ctx, in->n_tasks, in->max_m, kind_for(sc, score), live);
   rc = ensure_scratch(ctx, bp.bytes());
   if (rc) return rc;
-  if (!ctx->use_graphs) {
+  if (!ctx->use_graphs || ctx->frozen) {
     const hipError_t e = enqueue_batched(ctx, in, sc, out, live, bp, stream);
     return e == hipSuccess ? SOAP_DP_OK : hip_fail(ctx, e);
   }
@@ -899,6 +905,7 @@ size_t mate_layout(int64_t R, uint64_t W, char *base, MateWork *w) {
 
 int ensure_multi(soap_dp_ctx *ctx, size_t bytes) {
   if (bytes <= ctx->multi_bytes) return SOAP_DP_OK;
+  if (ctx->frozen) return SOAP_DP_ENOMEM;
   if (ctx->multi) {
     if (hipDeviceSynchronize() != hipSuccess) return SOAP_DP_EHIP;
     (void)hipFree(ctx->multi);
@@ -1124,10 +1131,19 @@ int soap_dp_reserve(soap_dp_ctx *ctx, int64_t n_tasks, int32_t max_n, int32_t ma
   DeviceGuard dg(ctx->device);
   const size_t small = kSmallInts * sizeof(int32_t);
   size_t scratch = b - small;
-  if (flags != SOAP_DP_PLAIN) {
+  if (flags & SOAP_DP_BATCHED) {
     scratch -= size_t(n_tasks) * 5;
-    const int rc = ensure_task_buffers(ctx, n_tasks);
+    int rc = ensure_task_buffers(ctx, n_tasks);
     if (rc) return rc;
+    // one stream per class a call with these bounds can populate
+    size_t n_live = 0;
+    int prev16 = 0, prev32 = 0;
+    for (const ClassSpec &c : ctx->classes) {
+      int &prev = c.prec == 16 ? prev16 : prev32;
+      if (prev < max_n) ++n_live;
+      prev = c.cap;
+    }
+    if ((rc = ensure_class_streams(ctx, n_live)) != SOAP_DP_OK) return rc;
   }
   return ensure_scratch(ctx, scratch);
 }
@@ -1202,3 +1218,7 @@ const char *soap_dp_strerror(int code) {
 int soap_dp_last_hip_error(const soap_dp_ctx *ctx) { return ctx ? ctx->last_hip_error : 0; }
 
 }  // extern "C"
+
+void soapdp::ctx_set_frozen(soap_dp_ctx *ctx, bool frozen) {
+  if (ctx) ctx->frozen = frozen;
+}

@@ -1,6 +1,7 @@
 // Length classes of the batched form and the device buffers of its bucketing.
 #pragma once
 #include "dp_internal.h"
+#include "serve_host.h"
 
 namespace soapdp {
 
@@ -56,7 +57,6 @@ hipError_t launch_zero(int32_t *a, int n, hipStream_t stream);
 // First CIGAR words of every task, gathered densely for one small copy back
 // to the host: head[t * kCigarHeadWords + k] = word k of task t's row for
 // k < cigar_len[t], else 0; tasks [0, n).
-constexpr int kCigarHeadWords = 16;
 hipError_t launch_gather_cigar_head(const uint32_t *cigar, int32_t stride, const int32_t *cigar_len,
                                     int32_t n, uint32_t *head, hipStream_t stream);
 

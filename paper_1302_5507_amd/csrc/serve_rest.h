@@ -7,13 +7,9 @@
 
 #include <cstdint>
 
-namespace soapdp {
+#include "serve_host.h"
 
-// One packed row: task index and the offset of its rest in the word area.
-struct RestRow {
-  int32_t task;
-  int32_t off;   // -1: the word area was full, the row was not packed
-};
+namespace soapdp {
 
 // Enqueue on `stream`: hdr[0] and hdr[1] are cleared, then every task
 // t < n whose row (cigar_len[t], clamped to the stride) is longer than

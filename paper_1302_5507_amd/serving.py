@@ -1,7 +1,7 @@
 """Python side of the continuous-batching server (soap_dp_server_* in
 include/soap_dp.h): argument marshalling, request construction and an
-open-loop client.  All scheduling, merging, transfers and alignment happen
-in the library's dispatcher thread and HIP kernels."""
+open-loop client.  All scheduling, admission, merging, transfers and
+alignment happen in the library's slot worker threads and HIP kernels."""
 from __future__ import annotations
 
 import ctypes
@@ -21,7 +21,8 @@ class ServerConfig(ctypes.Structure):
     _fields_ = [("device_ordinal", ctypes.c_int), ("n_slots", ctypes.c_int),
                 ("max_tasks", ctypes.c_int32), ("max_read_words", ctypes.c_int64),
                 ("max_n", ctypes.c_int32), ("max_m", ctypes.c_int32), ("scoring", Scoring),
-                ("genome", vp), ("genome_words", ctypes.c_uint64), ("autotune", ctypes.c_int)]
+                ("genome", vp), ("genome_words", ctypes.c_uint64), ("autotune", ctypes.c_int),
+                ("device_bytes", ctypes.c_uint64)]
 
 
 class HostResult(ctypes.Structure):
@@ -29,10 +30,17 @@ class HostResult(ctypes.Structure):
                 ("status", vp), ("cigar", vp), ("cigar_capacity", ctypes.c_int64)]
 
 
+class RequestStamps(ctypes.Structure):
+    _fields_ = [("arrival_ns", ctypes.c_uint64), ("taken_ns", ctypes.c_uint64),
+                ("launched_ns", ctypes.c_uint64), ("device_ns", ctypes.c_uint64),
+                ("done_ns", ctypes.c_uint64)]
+
+
 class RequestStruct(ctypes.Structure):
     _fields_ = [("read_codes", vp), ("read_word_off", vp), ("read_len", vp),
                 ("read_words", ctypes.c_uint64), ("ref_base_off", vp), ("ref_len", vp),
-                ("n_tasks", ctypes.c_int32), ("out", HostResult), ("arrival_ns", ctypes.c_uint64)]
+                ("n_tasks", ctypes.c_int32), ("out", HostResult), ("arrival_ns", ctypes.c_uint64),
+                ("stamps", ctypes.POINTER(RequestStamps))]
 
 
 class ServerStats(ctypes.Structure):
@@ -40,7 +48,8 @@ class ServerStats(ctypes.Structure):
                 ("rejected", ctypes.c_uint64), ("batches", ctypes.c_uint64),
                 ("tasks", ctypes.c_uint64), ("cells", ctypes.c_uint64),
                 ("device_busy_s", ctypes.c_double), ("host_launch_s", ctypes.c_double),
-                ("host_retire_s", ctypes.c_double)]
+                ("host_retire_s", ctypes.c_double), ("device_bytes", ctypes.c_uint64),
+                ("device_bytes_peak", ctypes.c_uint64)]
 
 
 _ready = False
@@ -99,15 +108,25 @@ class HostRequest:
         self.status = np.full(n, 255, np.uint8)
         self.cigar = np.zeros(max(1, n * cigar_words_per_task + cigar_extra), np.uint32)
         self.cells = int(np.dot(self.read_len.astype(np.int64), self.ref_len.astype(np.int64)))
+        self.stamps = RequestStamps()
         self.struct = RequestStruct(
             _p(self.read_words), _p(self.read_word_off), _p(self.read_len), self.read_words.size,
             _p(self.ref_base_off), _p(self.ref_len), n,
             HostResult(_p(self.score), _p(self.ref_begin), _p(self.ref_end), _p(self.cigar_len),
-                       _p(self.status), _p(self.cigar), self.cigar.size), 0)
+                       _p(self.status), _p(self.cigar), self.cigar.size), 0,
+            ctypes.pointer(self.stamps))
         self.ticket = None
         self.rc = None
         self.arrival_ns = 0
         self.done_ns = 0
+
+    def phases_ns(self):
+        """(queue, launch, device, retire) of a completed request: arrival to
+        taken into a batch, to its batch enqueued, to its results in host
+        memory, to its results in this request's buffers."""
+        st = self.stamps
+        return (st.taken_ns - st.arrival_ns, st.launched_ns - st.taken_ns,
+                st.device_ns - st.launched_ns, st.done_ns - st.device_ns)
 
     def cigar_rows(self):
         """Per-task CIGAR arrays (unpacked from the packed buffer)."""
@@ -117,15 +136,18 @@ class HostRequest:
 
 class Server:
     def __init__(self, genome_words, n_slots=4, max_tasks=16384, max_read_words=None, max_n=250,
-                 max_m=410, scoring=(1, -3, -5, -2), autotune=True, device_ordinal=0):
+                 max_m=410, scoring=(1, -3, -5, -2), autotune=True, device_ordinal=0,
+                 device_bytes=0):
         """``genome_words``: a device tensor (int32/uint32 view) holding the
-        packed genome; it must stay alive while the server runs."""
+        packed genome; it must stay alive while the server runs.
+        ``device_bytes``: device memory the batches in flight share (0: room
+        for ``n_slots`` full batches)."""
         self.genome = genome_words
         if max_read_words is None:
             max_read_words = max_tasks * ((max_n + 15) // 16)
         cfg = ServerConfig(device_ordinal, n_slots, max_tasks, max_read_words, max_n, max_m,
                            Scoring(*scoring), genome_words.data_ptr(), genome_words.numel(),
-                           int(bool(autotune)))
+                           int(bool(autotune)), int(device_bytes))
         h = vp()
         rc = _lib().soap_dp_server_create(ctypes.byref(h), ctypes.byref(cfg))
         if rc != 0:

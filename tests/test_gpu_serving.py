@@ -155,3 +155,118 @@ def test_many_long_cigars_in_one_batch():
         _check_oracle(pool, big)
     finally:
         srv.close()
+
+
+def test_autotuned_three_slots_mix_equals_alone():
+    """The configuration the benchmark serves with: shapes autotuned at
+    creation, then every slot reserved for them.  Mixed results equal the
+    oracle's and each request's result alone."""
+    import torch
+    g = workloads.random_genome(2_000_000, 5)
+    gw = torch.from_numpy(binding.pack_words(g).view(np.int32)).cuda()
+    pool = workloads.serving_pool(g, 20000, seed=17)
+    srv = serving.Server(gw, n_slots=3, max_tasks=8192, max_n=250, max_m=410, autotune=True)
+    try:
+        sizes = workloads.request_sizes(150, seed=13, max_batch=2048)
+        mix = serving.requests_from_pool(pool, sizes)
+        arr, done, lag = serving.run_open_loop(srv, mix, rate_hz=0.0, seed=3)
+        assert all(r.rc == 0 for r in mix)
+        for r in mix[::5]:
+            _check_oracle(pool, r)
+        alone = serving.requests_from_pool(pool, sizes)
+        for k in np.random.default_rng(2).choice(len(mix), 10, replace=False):
+            srv.submit(alone[k])
+            assert srv.wait(alone[k]) == 0
+            a, b = _fields(alone[k]), _fields(mix[k])
+            assert all(np.array_equal(x, y) for x, y in zip(a[:5], b[:5]))
+            assert all(np.array_equal(x, y) for x, y in zip(a[5], b[5]))
+    finally:
+        srv.close()
+
+
+def test_device_budget_never_exceeded():
+    """A device budget of 8 MB holds only a few small batches at once:
+    requests are admitted as memory frees up, the batches in flight never
+    hold more than the budget, a request too large for the budget (though
+    within the slot's task limit) is refused, and every result still equals
+    the oracle's and the request's result alone."""
+    import torch
+    g = workloads.random_genome(2_000_000, 6)
+    gw = torch.from_numpy(binding.pack_words(g).view(np.int32)).cuda()
+    pool = workloads.serving_pool(g, 20000, seed=19)
+    budget = 8 << 20
+    srv = serving.Server(gw, n_slots=3, max_tasks=4096, max_n=250, max_m=410, autotune=False,
+                         device_bytes=budget)
+    try:
+        big = serving.requests_from_pool(pool, [4096])[0]
+        with pytest.raises(binding.SoapDpError) as e:
+            srv.submit(big)
+        assert e.value.code == serving.SOAP_DP_E2BIG
+        sizes = workloads.request_sizes(200, seed=14, max_batch=1024)
+        mix = serving.requests_from_pool(pool, sizes)
+        arr, done, lag = serving.run_open_loop(srv, mix, rate_hz=0.0, seed=4)
+        assert all(r.rc == 0 for r in mix)
+        st = srv.stats()
+        assert st["device_bytes"] <= budget
+        assert 0 < st["device_bytes_peak"] <= st["device_bytes"]
+        assert st["batches"] > 3   # the budget split the stream into many batches
+        for r in mix[::7]:
+            _check_oracle(pool, r)
+        alone = serving.requests_from_pool(pool, sizes)
+        for k in np.random.default_rng(3).choice(len(mix), 8, replace=False):
+            srv.submit(alone[k])
+            assert srv.wait(alone[k]) == 0
+            a, b = _fields(alone[k]), _fields(mix[k])
+            assert all(np.array_equal(x, y) for x, y in zip(a[:5], b[:5]))
+            assert all(np.array_equal(x, y) for x, y in zip(a[5], b[5]))
+    finally:
+        srv.close()
+
+
+def test_read_outside_its_request_is_invalid_offset(setup):
+    """A task whose read words lie outside its own request (though inside
+    the merged batch) gets INVALID_OFFSET and zero outputs, alone and in a
+    mix, as soap_dp_align_batch gives for the request on its own; the
+    request's other tasks are exact."""
+    g, gw, pool, srv = setup
+    def bad_requests():
+        reqs = serving.requests_from_pool(pool, [40, 64, 40], start=5000)
+        r = reqs[1]
+        r.read_word_off[5] = r.read_words.size            # starts past its words
+        r.read_word_off[9] = r.read_words.size - 1        # runs past them
+        r.read_word_off[20] = r.read_words.size + 10**6   # far outside
+        return reqs
+    mix = bad_requests()
+    for r in mix:
+        srv.submit(r)
+    for r in mix:
+        assert srv.wait(r) == 0
+    alone = bad_requests()[1]
+    srv.submit(alone)
+    assert srv.wait(alone) == 0
+    bad = [5, 9, 20]
+    for r in (mix[1], alone):
+        assert (r.status[bad] == binding.TASK_INVALID_OFFSET).all()
+        for f in ("score", "ref_begin", "ref_end", "cigar_len"):
+            assert (getattr(r, f)[bad] == 0).all()
+    ok = np.setdiff1d(np.arange(64), bad)
+    ref = oracle_align(pool, CONFIG_SCORING, idx=mix[1].pool_idx[ok], stride=500)
+    for r in (mix[1], alone):
+        for f in ("status", "score", "ref_begin", "ref_end", "cigar_len"):
+            assert np.array_equal(getattr(r, f)[ok], getattr(ref, f)), f
+    a, b = _fields(alone), _fields(mix[1])
+    assert all(np.array_equal(x, y) for x, y in zip(a[:5], b[:5]))
+    assert all(np.array_equal(x, y) for x, y in zip(a[5], b[5]))
+    for r in (mix[0], mix[2]):
+        _check_oracle(pool, r)
+
+
+def test_request_stamps_are_ordered(setup):
+    g, gw, pool, srv = setup
+    reqs = serving.requests_from_pool(pool, workloads.request_sizes(60, seed=15, max_batch=512))
+    arr, done, lag = serving.run_open_loop(srv, reqs, rate_hz=5000.0, seed=5)
+    for r in reqs:
+        st = r.stamps
+        assert st.arrival_ns == r.arrival_ns and st.done_ns == r.done_ns
+        assert st.arrival_ns <= st.taken_ns <= st.launched_ns <= st.device_ns <= st.done_ns
+        assert sum(r.phases_ns()) == r.done_ns - r.arrival_ns
