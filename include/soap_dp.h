@@ -82,6 +82,16 @@ extern "C" {
                                   accepts an alignment only above a score threshold (its
                                   default limits for a 100 bp read, one gap of up to 68 bp
                                   or up to 23 one-base gaps, meet at one threshold) */
+#define SOAP_DP_FULL_WINDOW 8u /* OR-ed with either form: decision bits for every cell of the
+                                  window in one pass.  Without it a call with traceback runs
+                                  two passes: score and end of every task first (no decision
+                                  bits), then decision bits and traceback only over the window
+                                  rows an optimal alignment can reach.  With S_GE < 0 an
+                                  alignment of score S deletes at most
+                                  Dmax = 1 + (n S_MA + S_GO - S) / |S_GE| window bases (none
+                                  when n S_MA + S_GO < S), so it starts at row
+                                  max(0, end - n - Dmax) or later; with S_GE = 0 the band is the
+                                  whole window.  Outputs are identical either way. */
 
 /*
  * Scores, all signed and added.  A gap of k bases scores

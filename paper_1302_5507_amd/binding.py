@@ -20,6 +20,8 @@ SOAP_DP_EINVAL = -1
 SOAP_DP_ENOMEM = -2
 SOAP_DP_EHIP = -3
 SOAP_DP_ENODEV = -4
+SOAP_DP_E2BIG = -5
+SOAP_DP_ESTOPPED = -6
 
 TASK_OK = 0
 TASK_INVALID_LEN = 1
@@ -39,6 +41,7 @@ PLAIN = 0
 BATCHED = 1
 SCORE_ONLY = 2   # OR-ed with either form: score and end only
 MIN_SCORE = 4    # OR-ed with either form: tasks below Scoring.min_score skip the traceback
+FULL_WINDOW = 8  # OR-ed with either form: one pass with decision bits over the whole window
 
 EXPORTED = [
     "soap_dp_create", "soap_dp_destroy", "soap_dp_align_batch", "soap_dp_workspace_bytes",

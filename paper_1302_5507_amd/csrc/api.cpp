@@ -16,6 +16,7 @@
 #include <vector>
 
 #include "../../include/soap_dp.h"
+#include "band.h"
 #include "batch.h"
 #include "ctx_internal.h"
 #include "dp_internal.h"
@@ -28,12 +29,13 @@ namespace {
 
 constexpr size_t kScratchCap = size_t(16) << 30;  // decision-bit scratch budget
 // Small device buffer (int32 units): hist | max_m | offset | cursor |
-// work_counter | defer, then two uint64 tables (slot_dwords, scratch_off).
-constexpr int kSmallInts = 6 * kMaxClasses + 4 * kMaxClasses;
+// work_counter | defer, then two uint64 tables (slot_dwords, scratch_off),
+// then the int32 re-run's task count and work counter.
+constexpr int kSmallInts = 6 * kMaxClasses + 4 * kMaxClasses + 4;
 constexpr int kGraphCacheMax = 16;
 
 struct ClassSpec {
-  int prec;          // 16 or 32
+  int prec;          // kPrecI16 (offset form), kPrecI16Direct or kPrecI32
   int cap;           // upper bound on read length
   Shape shape;       // kernel shape with traceback
   Shape score_shape; // kernel shape of the score-only kernels ({0, 0}: as `shape`)
@@ -45,16 +47,35 @@ Shape shape_of(const ClassSpec &c, bool score) {
   return score && c.score_shape.lanes ? c.score_shape : c.shape;
 }
 
-// Default classes: int16 by ascending capacity, then the int32 classes that
-// serve tasks outside the int16 range.  Shapes are replaced by the autotuner.
+// Default classes: int16 in the offset form by ascending capacity, the same
+// capacities and shapes in the direct form (tasks the offset form's range
+// rule excludes), then the int32 classes for tasks neither int16 form
+// covers.  Shapes are replaced by the autotuner; a direct-form class always
+// runs the shape of the offset-form class of its capacity.
 const ClassSpec kDefaultClasses[] = {
     {16, 16, {2, 8}},    {16, 32, {4, 8}},    {16, 40, {4, 10}},   {16, 56, {8, 7}},
     {16, 64, {8, 8}},    {16, 80, {8, 10}},   {16, 104, {8, 13}},  {16, 128, {8, 16}},
     {16, 152, {8, 19}},  {16, 192, {16, 12}}, {16, 256, {16, 16}}, {16, 320, {32, 10}},
     {16, 384, {32, 12}}, {16, 512, {32, 16}},
+    {17, 16, {2, 8}},    {17, 32, {4, 8}},    {17, 40, {4, 10}},   {17, 56, {8, 7}},
+    {17, 64, {8, 8}},    {17, 80, {8, 10}},   {17, 104, {8, 13}},  {17, 128, {8, 16}},
+    {17, 152, {8, 19}},  {17, 192, {16, 12}}, {17, 256, {16, 16}}, {17, 320, {32, 10}},
+    {17, 384, {32, 12}}, {17, 512, {32, 16}},
     {32, 36, {4, 9}},    {32, 56, {8, 7}},    {32, 80, {8, 10}},   {32, 104, {8, 13}},
     {32, 152, {8, 19}},  {32, 256, {16, 16}}, {32, 512, {32, 16}},
 };
+static_assert(sizeof(kDefaultClasses) / sizeof(kDefaultClasses[0]) <= kMaxClasses, "class table");
+
+// Direct-form classes mirror the offset-form class of the same capacity.
+void mirror_direct_shapes(std::vector<ClassSpec> &cls) {
+  for (auto &d : cls)
+    if (d.prec == kPrecI16Direct)
+      for (const auto &o : cls)
+        if (o.prec == kPrecI16 && o.cap == d.cap) {
+          d.shape = o.shape;
+          d.score_shape = o.score_shape;
+        }
+}
 
 // What a captured batched call depends on: every pointer and size of the
 // batch and the outputs, the scoring, the context's buffer epoch and the
@@ -64,6 +85,7 @@ struct GraphKey {
   soap_dp_batch in;
   soap_dp_scoring sc;
   soap_dp_result out;
+  const int32_t *order;
   uint64_t epoch;
   uint32_t flags;
 };
@@ -95,7 +117,7 @@ struct GraphEntry {
 
 bool same_key(const GraphKey &a, const GraphKey &b) {
   return same_batch(a.in, b.in) && same_scoring(a.sc, b.sc) && same_result(a.out, b.out) &&
-         a.epoch == b.epoch && a.flags == b.flags;
+         a.order == b.order && a.epoch == b.epoch && a.flags == b.flags;
 }
 
 }  // namespace
@@ -111,6 +133,7 @@ struct soap_dp_ctx {
   int32_t *small = nullptr;          // bucketing tables and class plans (kSmallInts)
   uint8_t *task_class = nullptr;
   int32_t *task_list = nullptr;
+  int32_t *redo_list = nullptr;   // tasks the direct-form kernels flag for the int32 re-run
   int64_t task_cap = 0;
   // batched form
   std::vector<ClassSpec> classes;
@@ -132,6 +155,9 @@ struct soap_dp_ctx {
   // multi-candidate work arrays (task slots, reverse complements)
   void *multi = nullptr;
   size_t multi_bytes = 0;
+  // two-pass work arrays (pass-1 results, bands, pass-2 order)
+  void *band = nullptr;
+  size_t band_bytes = 0;
 };
 
 namespace {
@@ -181,7 +207,7 @@ int batch_ok(const soap_dp_batch *in, const soap_dp_result *out, bool score_only
 
 bool shape_compiled(int prec, Shape s) {
   int cnt = 0;
-  const Shape *all = prec == 16 ? shapes_i16(&cnt) : shapes_i32(&cnt);
+  const Shape *all = packed16(prec) ? shapes_i16(&cnt) : shapes_i32(&cnt);
   for (int k = 0; k < cnt; ++k)
     if (all[k].lanes == s.lanes && all[k].cells == s.cells) return true;
   return false;
@@ -211,14 +237,15 @@ int occupancy(const soap_dp_ctx *ctx, int prec, Shape s, Kind k) {
                        uint32_t(s.lanes) << 8 | uint32_t(s.cells);
   auto it = ctx->occupancy.find(key);
   if (it != ctx->occupancy.end()) return it->second;
-  int o = prec == 16 ? occupancy_dp_i16(s, k.score) : occupancy_dp_i32(s, k.v == kByte, k.score);
+  int o = packed16(prec) ? occupancy_dp_i16(s, k.score, prec == kPrecI16Direct)
+                         : occupancy_dp_i32(s, k.v == kByte, k.score);
   o = o < 1 ? 1 : o;
   ctx->occupancy.emplace(key, o);
   return o;
 }
 
 uint64_t slot_dwords(int prec, Shape s, int32_t max_m) {
-  return prec == 16 ? slot_dwords_i16(s, max_m) : slot_dwords_i32(s, max_m);
+  return packed16(prec) ? slot_dwords_i16(s, max_m) : slot_dwords_i32(s, max_m);
 }
 
 // Plain form: the compiled int32 shape covering max_n with the least work
@@ -241,7 +268,7 @@ Shape plain_shape(int32_t max_n, int32_t max_m) {
 // Persistent grid of one launch: every resident workgroup slot, limited by
 // the scratch budget and by the work available.
 int grid_for(const soap_dp_ctx *ctx, int prec, Shape s, int64_t n_tasks, int32_t max_m, Kind k) {
-  const int64_t per_wave = (prec == 16 ? 2 : 1) * kWave / s.lanes;
+  const int64_t per_wave = (packed16(prec) ? 2 : 1) * kWave / s.lanes;
   const int64_t items = (n_tasks + per_wave - 1) / per_wave;
   int64_t grid = int64_t(ctx->cu_count) * occupancy(ctx, prec, s, k);
   const uint64_t slot_bytes = slot_dwords(prec, s, max_m) * 4;
@@ -293,18 +320,23 @@ int ensure_task_buffers(soap_dp_ctx *ctx, int64_t n_tasks) {
     if (hipDeviceSynchronize() != hipSuccess) return SOAP_DP_EHIP;
     (void)hipFree(ctx->task_list);
     (void)hipFree(ctx->task_class);
+    (void)hipFree(ctx->redo_list);
     ctx->task_list = nullptr;
     ctx->task_class = nullptr;
+    ctx->redo_list = nullptr;
     ctx->task_cap = 0;
   }
   clear_graphs(ctx);
   const int64_t cap = std::max<int64_t>(n_tasks, 1024);
   if (hipMalloc(reinterpret_cast<void **>(&ctx->task_list), size_t(cap) * 4) != hipSuccess ||
-      hipMalloc(reinterpret_cast<void **>(&ctx->task_class), size_t(cap)) != hipSuccess) {
+      hipMalloc(reinterpret_cast<void **>(&ctx->task_class), size_t(cap)) != hipSuccess ||
+      hipMalloc(reinterpret_cast<void **>(&ctx->redo_list), size_t(cap) * 4) != hipSuccess) {
     (void)hipGetLastError();
     if (ctx->task_list) (void)hipFree(ctx->task_list);
+    if (ctx->task_class) (void)hipFree(ctx->task_class);
     ctx->task_list = nullptr;
     ctx->task_class = nullptr;
+    ctx->redo_list = nullptr;
     return SOAP_DP_ENOMEM;
   }
   ctx->task_cap = cap;
@@ -342,7 +374,7 @@ DpParams make_params(const soap_dp_batch *in, const soap_dp_scoring *sc, const s
 }
 
 // Work items of one launch and the tasks each serves.
-int64_t tasks_per_item(int prec, Shape s) { return (prec == 16 ? 2 : 1) * kWave / s.lanes; }
+int64_t tasks_per_item(int prec, Shape s) { return (packed16(prec) ? 2 : 1) * kWave / s.lanes; }
 
 // Grid, traceback deferral and scratch of one kernel launch.
 struct LaunchPlan {
@@ -374,7 +406,8 @@ LaunchPlan plan_launch(const soap_dp_ctx *ctx, int prec, Shape s, int64_t n_task
 }
 
 hipError_t launch_shape(int prec, Shape s, int grid, hipStream_t stream, const DpParams &p) {
-  return prec == 16 ? launch_dp_i16(s, grid, stream, p) : launch_dp_i32(s, grid, stream, p);
+  return packed16(prec) ? launch_dp_i16(s, grid, stream, p, prec == kPrecI16Direct)
+                        : launch_dp_i32(s, grid, stream, p);
 }
 
 // Device tables of the bucketing and the class plans, carved from `small`.
@@ -390,6 +423,9 @@ BucketBuffers bucket_buffers(const soap_dp_ctx *ctx) {
   b.defer = ctx->small + 5 * kMaxClasses;
   b.slot_dwords = reinterpret_cast<uint64_t *>(ctx->small + 6 * kMaxClasses);
   b.scratch_off = reinterpret_cast<uint64_t *>(ctx->small + 8 * kMaxClasses);
+  b.redo_count = ctx->small + 10 * kMaxClasses;
+  b.redo_work_counter = ctx->small + 10 * kMaxClasses + 1;
+  b.redo_list = ctx->redo_list;
   return b;
 }
 
@@ -403,7 +439,8 @@ size_t plain_scratch_bytes(const soap_dp_ctx *ctx, int64_t n_tasks, int32_t max_
 }
 
 int align_plain(soap_dp_ctx *ctx, const soap_dp_batch *in, const soap_dp_scoring *sc,
-                const soap_dp_result *out, hipStream_t stream, bool score) {
+                const soap_dp_result *out, hipStream_t stream, bool score,
+                const int32_t *order = nullptr) {
   const Shape s = plain_shape(in->max_n, in->max_m);
   if (s.lanes == 0) return SOAP_DP_EINVAL;
   const LaunchPlan q = plan_launch(ctx, 32, s, in->n_tasks, in->max_m, kind_for(sc, score), kScratchCap);
@@ -417,6 +454,7 @@ int align_plain(soap_dp_ctx *ctx, const soap_dp_batch *in, const soap_dp_scoring
   // work queue: waves share SIMDs unevenly, so a static split of the work
   // items would leave the launch waiting on the most crowded SIMDs
   p.work_counter = bucket_buffers(ctx).work_counter;
+  p.task_list = order;   // work items take consecutive tasks of this order
   hipError_t e = launch_zero(p.work_counter, 1, stream);
   if (e == hipSuccess) e = launch_dp_i32(s, q.grid, stream, p);
   if (e != hipSuccess) return hip_fail(ctx, e);
@@ -426,38 +464,56 @@ int align_plain(soap_dp_ctx *ctx, const soap_dp_batch *in, const soap_dp_scoring
 // ---------------------------------------------------------------- batched
 
 // Classes a batch with these bounds can populate: a class receives reads
-// longer than the previous class of its precision, so classes starting at or
-// above max_n stay empty; int32 classes are needed only if some task (read
-// up to max_n, window up to max_m) falls outside the int16 range of its
-// int16 class.
+// longer than the previous class of its kind, so classes starting at or
+// above max_n stay empty.  A direct-form class is needed when some task of
+// its capacity (read up to max_n, window up to max_m) falls outside the
+// offset form's range and the direct form's static rule admits the class's
+// shortest read; int32 classes when the direct form's rule fails for some
+// read up to max_n.  The int32 re-run of flagged tasks is not a class (see
+// enqueue_batched).
 std::vector<int> live_classes(const soap_dp_ctx *ctx, int32_t max_n, int32_t max_m,
                               const soap_dp_scoring *sc, bool score) {
   std::vector<int> live;
+  const int32_t ma = sc->match, mi = sc->mismatch, go = sc->gap_open, ge = sc->gap_extend;
   bool need32 = false;
+  std::vector<int> direct_caps;   // capacities whose direct-form class is needed
   int prev16 = 0;
   for (size_t k = 0; k < ctx->classes.size(); ++k) {
     const ClassSpec &c = ctx->classes[k];
-    if (c.prec != 16) continue;
+    if (c.prec != kPrecI16) continue;
     if (prev16 < max_n) {
       live.push_back(int(k));
       const int32_t n_hi = std::min(c.cap, max_n);
       const Shape sh = shape_of(c, score);
-      if (!int16_fits(n_hi, max_m, sh.lanes * sh.cells, sc->match, sc->mismatch,
-                      sc->gap_open, sc->gap_extend))
-        need32 = true;
+      if (!int16_fits(n_hi, max_m, sh.lanes * sh.cells, ma, mi, go, ge)) {
+        if (int16_direct_fits(prev16 + 1, ma, mi, go, ge)) direct_caps.push_back(c.cap);
+        if (!int16_direct_fits(n_hi, ma, mi, go, ge)) need32 = true;
+      }
     }
     prev16 = c.cap;
+  }
+  for (size_t k = 0; k < ctx->classes.size(); ++k) {
+    const ClassSpec &c = ctx->classes[k];
+    if (c.prec == kPrecI16Direct &&
+        std::find(direct_caps.begin(), direct_caps.end(), c.cap) != direct_caps.end())
+      live.push_back(int(k));
   }
   if (need32) {
     int prev32 = 0;
     for (size_t k = 0; k < ctx->classes.size(); ++k) {
       const ClassSpec &c = ctx->classes[k];
-      if (c.prec != 32) continue;
+      if (c.prec != kPrecI32) continue;
       if (prev32 < max_n) live.push_back(int(k));
       prev32 = c.cap;
     }
   }
   return live;
+}
+
+bool any_direct(const soap_dp_ctx *ctx, const std::vector<int> &live) {
+  for (int k : live)
+    if (ctx->classes[size_t(k)].prec == kPrecI16Direct) return true;
+  return false;
 }
 
 // Scratch of the batched form.  The live classes run concurrently, each in
@@ -467,15 +523,22 @@ std::vector<int> live_classes(const soap_dp_ctx *ctx, int32_t max_n, int32_t max
 // the batch's longest window at deferral 1, whatever the split, and
 // otherwise room for every class to reach full deferral as if it held the
 // whole batch, up to the scratch cap; plus slack for region rounding.
+// When a direct-form class is live, the int32 re-run of its flagged tasks
+// follows the class kernels with the plain form's shape for the batch's
+// bounds and reuses the scratch from its start (the class kernels are done
+// by then), at deferral 1; the budget holds its full grid of slots too.
 struct BatchedPlan {
   bool score = false;   // score-only kernels: no decision scratch
   std::vector<int> grids;
   uint64_t budget_dwords = 0;
+  bool redo = false;
+  Shape redo_shape{0, 0};
+  LaunchPlan redo_plan;
   size_t bytes() const { return size_t(budget_dwords + 64 * kMaxClasses) * 4; }
 };
 
-BatchedPlan batched_plan(const soap_dp_ctx *ctx, int64_t n_tasks, int32_t max_m, Kind k,
-                         const std::vector<int> &live) {
+BatchedPlan batched_plan(const soap_dp_ctx *ctx, int64_t n_tasks, int32_t max_n, int32_t max_m,
+                         Kind k, const std::vector<int> &live, bool redo) {
   BatchedPlan bp;
   bp.score = k.score;
   uint64_t need = 0, want = 0;
@@ -486,13 +549,20 @@ BatchedPlan batched_plan(const soap_dp_ctx *ctx, int64_t n_tasks, int32_t max_m,
     need += round64(uint64_t(q.grid) * q.slot_dwords);
     want += round64(uint64_t(q.grid) * uint64_t(q.defer) * q.slot_dwords);
   }
+  bp.redo = redo;
+  if (redo) {
+    bp.redo_shape = plain_shape(max_n, max_m);
+    bp.redo_plan = plan_launch(ctx, kPrecI32, bp.redo_shape, n_tasks, max_m, k, 0);
+    bp.redo_plan.defer = 1;
+    need = std::max<uint64_t>(need, round64(uint64_t(bp.redo_plan.grid) * bp.redo_plan.slot_dwords));
+  }
   bp.budget_dwords = std::max<uint64_t>(need, std::min<uint64_t>(want, kScratchCap / 4));
   return bp;
 }
 
-size_t batched_scratch_bytes(const soap_dp_ctx *ctx, int64_t n_tasks, int32_t max_m, Kind k,
-                             const std::vector<int> &live) {
-  return batched_plan(ctx, n_tasks, max_m, k, live).bytes();
+size_t batched_scratch_bytes(const soap_dp_ctx *ctx, int64_t n_tasks, int32_t max_n, int32_t max_m,
+                             Kind k, const std::vector<int> &live, bool redo) {
+  return batched_plan(ctx, n_tasks, max_n, max_m, k, live, redo).bytes();
 }
 
 int ensure_class_streams(soap_dp_ctx *ctx, size_t n) {
@@ -530,7 +600,7 @@ ClassTable class_table(const soap_dp_ctx *ctx, const std::vector<int> &live,
     ct.lanes[k] = sh.lanes;
     ct.step_block[k] = step_block(sh.cells);
     ct.step_dwords[k] =
-        bp.score ? 0 : int32_t(uint64_t((sh.cells + 7) / 8) * kWave * (c.prec == 16 ? 2 : 1));
+        bp.score ? 0 : int32_t(uint64_t((sh.cells + 7) / 8) * kWave * (packed16(c.prec) ? 2 : 1));
     if (bp.score) ct.max_defer[k] = 1;
   }
   for (size_t li = 0; li < live.size(); ++li) ct.grid[live[li]] = bp.grids[li];
@@ -543,10 +613,12 @@ ClassTable class_table(const soap_dp_ctx *ctx, const std::vector<int> &live,
 // so the launch plans are computed beforehand: no runtime queries in between).
 hipError_t enqueue_batched(soap_dp_ctx *ctx, const soap_dp_batch *in, const soap_dp_scoring *sc,
                            const soap_dp_result *out, const std::vector<int> &live,
-                           const BatchedPlan &bp, hipStream_t stream) {
+                           const BatchedPlan &bp, const int32_t *order, hipStream_t stream) {
   DpParams p = make_params(in, sc, out);
   const BucketBuffers b = bucket_buffers(ctx);
-  hipError_t e = launch_bucketing(p, class_table(ctx, live, bp), b, stream);
+  p.redo_list = b.redo_list;
+  p.redo_count = b.redo_count;
+  hipError_t e = launch_bucketing(p, class_table(ctx, live, bp), b, order, stream);
   if (e != hipSuccess) return e;
   // fork: every class kernel waits for the bucketing only, then they run
   // concurrently; the caller's stream joins them all
@@ -569,27 +641,43 @@ hipError_t enqueue_batched(soap_dp_ctx *ctx, const soap_dp_batch *in, const soap
     q.defer_dev = b.defer + k;
     q.slot_dwords_dev = b.slot_dwords + k;
     q.scratch_off_dev = b.scratch_off + k;
-    q.ok_status = c.prec == 16 ? kTaskOk : kTaskRedone;
+    q.ok_status = packed16(c.prec) ? kTaskOk : kTaskRedone;
     q.score_only = bp.score;
     if ((e = launch_shape(c.prec, shape_of(c, bp.score), bp.grids[li], cs, q)) != hipSuccess) return e;
     if ((e = hipEventRecord(ctx->join_events[li], cs)) != hipSuccess) return e;
     if ((e = hipStreamWaitEvent(stream, ctx->join_events[li], 0)) != hipSuccess) return e;
   }
+  if (bp.redo) {
+    // the int32 re-run of the tasks the direct-form kernels flagged, after
+    // every class kernel, on the whole scratch
+    DpParams q = p;
+    q.task_list = b.redo_list;
+    q.task_count = b.redo_count;
+    q.work_counter = b.redo_work_counter;
+    q.scratch_off_dev = nullptr;
+    q.defer = 1;
+    q.slot_dwords = bp.redo_plan.slot_dwords;
+    q.ok_status = kTaskRedone;
+    q.score_only = bp.score;
+    if ((e = launch_dp_i32(bp.redo_shape, bp.redo_plan.grid, stream, q)) != hipSuccess) return e;
+  }
   return hipSuccess;
 }
 
 int align_batched(soap_dp_ctx *ctx, const soap_dp_batch *in, const soap_dp_scoring *sc,
-                  const soap_dp_result *out, hipStream_t stream, bool score) {
+                  const soap_dp_result *out, hipStream_t stream, bool score,
+                  const int32_t *order = nullptr) {
   const std::vector<int> live = live_classes(ctx, in->max_n, in->max_m, sc, score);
   int rc = ensure_task_buffers(ctx, in->n_tasks);
   if (rc) return rc;
   rc = ensure_class_streams(ctx, live.size());
   if (rc) return rc;
-  const BatchedPlan bp = batched_plan(ctx, in->n_tasks, in->max_m, kind_for(sc, score), live);
+  const BatchedPlan bp = batched_plan(ctx, in->n_tasks, in->max_n, in->max_m, kind_for(sc, score),
+                                      live, any_direct(ctx, live));
   rc = ensure_scratch(ctx, bp.bytes());
   if (rc) return rc;
   if (!ctx->use_graphs || ctx->frozen) {
-    const hipError_t e = enqueue_batched(ctx, in, sc, out, live, bp, stream);
+    const hipError_t e = enqueue_batched(ctx, in, sc, out, live, bp, order, stream);
     return e == hipSuccess ? SOAP_DP_OK : hip_fail(ctx, e);
   }
   GraphKey key;
@@ -597,6 +685,7 @@ int align_batched(soap_dp_ctx *ctx, const soap_dp_batch *in, const soap_dp_scori
   key.in = *in;
   key.sc = *sc;
   key.out = *out;
+  key.order = order;
   key.epoch = ctx->epoch;
   key.flags = score ? SOAP_DP_SCORE_ONLY : 0u;
   GraphEntry *hit = nullptr;
@@ -608,7 +697,7 @@ int align_batched(soap_dp_ctx *ctx, const soap_dp_batch *in, const soap_dp_scori
       return hip_fail(ctx, hipGetLastError());
     hipError_t e = hipStreamBeginCapture(ctx->capture_stream, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return hip_fail(ctx, e);
-    const hipError_t le = enqueue_batched(ctx, in, sc, out, live, bp, ctx->capture_stream);
+    const hipError_t le = enqueue_batched(ctx, in, sc, out, live, bp, order, ctx->capture_stream);
     hipGraph_t graph = nullptr;
     e = hipStreamEndCapture(ctx->capture_stream, &graph);
     if (le != hipSuccess || e != hipSuccess) {
@@ -738,6 +827,7 @@ bool load_cache(soap_dp_ctx *ctx, const char *path) {
     ++pos;
   }
   if (found == 0) return false;
+  mirror_direct_shapes(cls);
   ctx->classes = cls;
   return true;
 }
@@ -748,7 +838,11 @@ bool save_cache(const soap_dp_ctx *ctx, const char *path, const std::vector<doub
   FILE *f = std::fopen(tmp.c_str(), "w");
   if (!f) return false;
   std::fprintf(f, "{%s, \"classes\": [\n", cache_header(ctx).c_str());
-  for (size_t k = 0; k < ctx->classes.size(); ++k) {
+  std::vector<size_t> keep;
+  for (size_t k = 0; k < ctx->classes.size(); ++k)
+    if (ctx->classes[k].prec != kPrecI16Direct) keep.push_back(k);
+  for (size_t q = 0; q < keep.size(); ++q) {
+    const size_t k = keep[q];
     const ClassSpec &c = ctx->classes[k];
     const Shape ss = shape_of(c, true);
     std::fprintf(f,
@@ -756,7 +850,7 @@ bool save_cache(const soap_dp_ctx *ctx, const char *path, const std::vector<doub
                  "\"score_cells\": %d, \"gcups\": %.1f, \"score_gcups\": %.1f}%s\n",
                  c.prec, c.cap, c.shape.lanes, c.shape.cells, ss.lanes, ss.cells,
                  k < gcups.size() ? gcups[k] : 0.0, k < gcups_score.size() ? gcups_score[k] : 0.0,
-                 k + 1 < ctx->classes.size() ? "," : "");
+                 q + 1 < keep.size() ? "," : "");
   }
   std::fprintf(f, "]}\n");
   std::fclose(f);
@@ -818,6 +912,7 @@ int autotune(soap_dp_ctx *ctx, std::vector<double> &gcups, std::vector<double> &
   int rc = SOAP_DP_OK;
   for (size_t k = 0; k < ctx->classes.size() && rc == SOAP_DP_OK; ++k) {
     ClassSpec &c = ctx->classes[k];
+    if (c.prec == kPrecI16Direct) continue;   // runs its offset-form class's shapes
     const int32_t n = c.cap, m = n + 160;
     // about 1.2e10 cells (a few ms per launch, also for the faster
     // score-only kernels), and never fewer than 65,536 tasks: enough work
@@ -846,6 +941,7 @@ int autotune(soap_dp_ctx *ctx, std::vector<double> &gcups, std::vector<double> &
     }
   }
   (void)hipStreamDestroy(st);
+  mirror_direct_shapes(ctx->classes);
   clear_graphs(ctx);
   return rc;
 }
@@ -922,7 +1018,162 @@ int ensure_multi(soap_dp_ctx *ctx, size_t bytes) {
   return SOAP_DP_OK;
 }
 
+// Work arrays of a two-pass call over T tasks, laid out like multi_layout.
+size_t band_layout(int64_t T, char *base, BandWork *w) {
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    char *p = base ? base + off : nullptr;
+    off += (bytes + 255) & ~size_t(255);
+    return p;
+  };
+  BandWork b{};
+  const size_t n = size_t(std::max<int64_t>(T, 1));
+  b.p_score = reinterpret_cast<int32_t *>(take(n * 4));
+  b.p_begin = reinterpret_cast<int32_t *>(take(n * 4));
+  b.p_end = reinterpret_cast<int32_t *>(take(n * 4));
+  b.p_clen = reinterpret_cast<int32_t *>(take(n * 4));
+  b.p_status = reinterpret_cast<uint8_t *>(take(n));
+  b.b_rbo = reinterpret_cast<uint64_t *>(take(n * 8));
+  b.b_ml = reinterpret_cast<int32_t *>(take(n * 4));
+  b.b_i0 = reinterpret_cast<int32_t *>(take(n * 4));
+  b.order = reinterpret_cast<int32_t *>(take(n * 4));
+  b.bins = reinterpret_cast<int32_t *>(take(2 * kBandBins * 4));
+  if (w) *w = b;
+  return off;
+}
+
+int ensure_band(soap_dp_ctx *ctx, size_t bytes) {
+  if (bytes <= ctx->band_bytes) return SOAP_DP_OK;
+  if (ctx->frozen) return SOAP_DP_ENOMEM;
+  if (ctx->band) {
+    if (hipDeviceSynchronize() != hipSuccess) return SOAP_DP_EHIP;
+    (void)hipFree(ctx->band);
+    ctx->band = nullptr;
+    ctx->band_bytes = 0;
+  }
+  clear_graphs(ctx);   // graphs hold pointers into the old arrays
+  if (hipMalloc(&ctx->band, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    ctx->band = nullptr;
+    return SOAP_DP_ENOMEM;
+  }
+  ctx->band_bytes = bytes;
+  return SOAP_DP_OK;
+}
+
+// Alignment with traceback in two passes (band.h): score and end of every
+// task without decision bits, then decision bits and traceback only over
+// the window rows that can hold an optimal alignment, in an order that
+// groups tasks of similar band lengths.  Either form runs both passes.
+int align_two_pass(soap_dp_ctx *ctx, const soap_dp_batch *in, const soap_dp_scoring *sc,
+                   const soap_dp_result *out, hipStream_t stream, bool batched) {
+  int rc = ensure_band(ctx, band_layout(in->n_tasks, nullptr, nullptr));
+  if (rc) return rc;
+  BandWork w{};
+  band_layout(in->n_tasks, static_cast<char *>(ctx->band), &w);
+  const soap_dp_result r1{w.p_score, w.p_begin, w.p_end, nullptr, 0, w.p_clen, w.p_status};
+  rc = batched ? align_batched(ctx, in, sc, &r1, stream, true)
+               : align_plain(ctx, in, sc, &r1, stream, true);
+  if (rc) return rc;
+  const BandIn bi{in->ref_base_off, in->read_len, in->ref_len, in->n_tasks, in->max_m,
+                  sc->match, sc->gap_open, sc->gap_extend};
+  hipError_t e = launch_band(bi, w, stream);
+  if (e != hipSuccess) return hip_fail(ctx, e);
+  // pass 2 sees only tasks at or above any threshold: no cutoff there
+  soap_dp_scoring s2 = *sc;
+  s2.min_score = INT32_MIN;
+  const soap_dp_batch b2{in->read_codes, in->read_word_off, in->read_len, in->ref_codes, w.b_rbo,
+                         w.b_ml, in->n_tasks, in->max_n, in->max_m, in->read_words, in->ref_words};
+  rc = batched ? align_batched(ctx, &b2, &s2, out, stream, false, w.order)
+               : align_plain(ctx, &b2, &s2, out, stream, false, w.order);
+  if (rc) return rc;
+  const BandOut bo{out->score, out->ref_begin, out->ref_end, out->cigar_len, out->status};
+  if ((e = launch_band_fixup(in->n_tasks, w, bo, stream)) != hipSuccess) return hip_fail(ctx, e);
+  return SOAP_DP_OK;
+}
+
+// Flags of soap_dp_align_batch and soap_dp_mate_rescue to the path taken.
+int align_dispatch(soap_dp_ctx *ctx, const soap_dp_batch *in, const soap_dp_scoring *sc,
+                   const soap_dp_result *out, hipStream_t stream, uint32_t flags) {
+  const bool batched = (flags & SOAP_DP_BATCHED) != 0;
+  const bool score = (flags & SOAP_DP_SCORE_ONLY) != 0;
+  if (!score && (flags & SOAP_DP_FULL_WINDOW) == 0)
+    return align_two_pass(ctx, in, sc, out, stream, batched);
+  return batched ? align_batched(ctx, in, sc, out, stream, score)
+                 : align_plain(ctx, in, sc, out, stream, score);
+}
+
+// Classes a batched call with these bounds can populate: for a known
+// scoring exactly those live_classes gives for both kinds of kernel, else
+// every class of every kind up to max_n.
+std::vector<int> reserve_classes(const soap_dp_ctx *ctx, int32_t max_n, int32_t max_m,
+                                 const soap_dp_scoring *sc, bool *redo) {
+  std::vector<int> live;
+  if (sc) {
+    for (bool score : {false, true})
+      for (int k : live_classes(ctx, max_n, max_m, sc, score))
+        if (std::find(live.begin(), live.end(), k) == live.end()) live.push_back(k);
+    *redo = any_direct(ctx, live);
+    return live;
+  }
+  int prev[3] = {0, 0, 0};
+  for (size_t k = 0; k < ctx->classes.size(); ++k) {
+    const ClassSpec &c = ctx->classes[k];
+    int &pv = prev[c.prec == kPrecI16 ? 0 : (c.prec == kPrecI16Direct ? 1 : 2)];
+    if (pv < max_n) live.push_back(int(k));
+    pv = c.cap;
+  }
+  *redo = true;
+  return live;
+}
+
+size_t workspace_bytes_for(const soap_dp_ctx *ctx, int64_t n_tasks, int32_t max_n, int32_t max_m,
+                           uint32_t flags, const soap_dp_scoring *sc) {
+  if (!ctx || n_tasks <= 0 || max_n < 1 || max_n > SOAP_DP_MAX_READ || max_m < 1 ||
+      max_m > SOAP_DP_MAX_WINDOW)
+    return 0;
+  const size_t small = kSmallInts * sizeof(int32_t);
+  const bool score = (flags & SOAP_DP_SCORE_ONLY) != 0;
+  const Kind k = sc ? kind_for(sc, score) : Kind{kEither, score};
+  // two-pass work arrays
+  const size_t band = (flags & (SOAP_DP_SCORE_ONLY | SOAP_DP_FULL_WINDOW)) == 0
+                          ? band_layout(n_tasks, nullptr, nullptr)
+                          : 0;
+  if ((flags & SOAP_DP_BATCHED) == 0)
+    return plain_scratch_bytes(ctx, n_tasks, max_n, max_m, k) + small + band;
+  bool redo = false;
+  const std::vector<int> live = reserve_classes(ctx, max_n, max_m, sc, &redo);
+  return batched_scratch_bytes(ctx, n_tasks, max_n, max_m, k, live, redo) + size_t(n_tasks) * 9 +
+         small + band;
+}
+
 }  // namespace
+
+int soapdp::ctx_reserve_for(soap_dp_ctx *ctx, int64_t n_tasks, int32_t max_n, int32_t max_m,
+                            uint32_t flags, const soap_dp_scoring *sc) {
+  if (!ctx) return SOAP_DP_EINVAL;
+  const size_t b = workspace_bytes_for(ctx, n_tasks, max_n, max_m, flags, sc);
+  if (b == 0) return SOAP_DP_EINVAL;
+  DeviceGuard dg(ctx->device);
+  const size_t small = kSmallInts * sizeof(int32_t);
+  size_t scratch = b - small;
+  if ((flags & (SOAP_DP_SCORE_ONLY | SOAP_DP_FULL_WINDOW)) == 0) {
+    const size_t band = band_layout(n_tasks, nullptr, nullptr);
+    scratch -= band;
+    const int rc = ensure_band(ctx, band);
+    if (rc) return rc;
+  }
+  if (flags & SOAP_DP_BATCHED) {
+    scratch -= size_t(n_tasks) * 9;
+    int rc = ensure_task_buffers(ctx, n_tasks);
+    if (rc) return rc;
+    // one stream per class a call with these bounds can populate
+    bool redo = false;
+    const size_t n_live = reserve_classes(ctx, max_n, max_m, sc, &redo).size();
+    if ((rc = ensure_class_streams(ctx, n_live)) != SOAP_DP_OK) return rc;
+  }
+  return ensure_scratch(ctx, scratch);
+}
 
 extern "C" {
 
@@ -972,7 +1223,9 @@ int soap_dp_destroy(soap_dp_ctx *ctx) {
     if (ctx->small) (void)hipFree(ctx->small);
     if (ctx->task_list) (void)hipFree(ctx->task_list);
     if (ctx->task_class) (void)hipFree(ctx->task_class);
+    if (ctx->redo_list) (void)hipFree(ctx->redo_list);
     if (ctx->multi) (void)hipFree(ctx->multi);
+    if (ctx->band) (void)hipFree(ctx->band);
   }
   delete ctx;
   return SOAP_DP_OK;
@@ -1038,7 +1291,8 @@ int soap_dp_align_multi(soap_dp_ctx *ctx, const soap_dp_multi_batch *in, const s
 int soap_dp_mate_rescue(soap_dp_ctx *ctx, const soap_dp_mate_batch *in, const soap_dp_scoring *sc,
                         const soap_dp_mate_result *out, void *stream, uint32_t flags) {
   if (!ctx || !in || !out || !scoring_ok(sc)) return SOAP_DP_EINVAL;
-  if (flags & ~(SOAP_DP_BATCHED | SOAP_DP_SCORE_ONLY | SOAP_DP_MIN_SCORE)) return SOAP_DP_EINVAL;
+  if (flags & ~(SOAP_DP_BATCHED | SOAP_DP_SCORE_ONLY | SOAP_DP_MIN_SCORE | SOAP_DP_FULL_WINDOW))
+    return SOAP_DP_EINVAL;
   const bool score = (flags & SOAP_DP_SCORE_ONLY) != 0;
   if (in->n_reads < 0 || in->n_reads > (int64_t(1) << 31) - 1) return SOAP_DP_EINVAL;
   if (in->max_n < 1 || in->max_n > SOAP_DP_MAX_READ) return SOAP_DP_EINVAL;
@@ -1080,8 +1334,7 @@ int soap_dp_mate_rescue(soap_dp_ctx *ctx, const soap_dp_mate_batch *in, const so
                          out->cigar_len, out->status};
   if ((rc = batch_ok(&b, &r, score)) != SOAP_DP_OK) return rc;
   const soap_dp_scoring es = effective_scoring(sc, flags);
-  rc = (flags & SOAP_DP_BATCHED) ? align_batched(ctx, &b, &es, &r, st, score)
-                                 : align_plain(ctx, &b, &es, &r, st, score);
+  rc = align_dispatch(ctx, &b, &es, &r, st, flags);
   if (rc) return rc;
   if ((e = launch_mate_fixup(mi, w, mo, st)) != hipSuccess) return hip_fail(ctx, e);
   return SOAP_DP_OK;
@@ -1091,7 +1344,8 @@ int soap_dp_align_batch(soap_dp_ctx *ctx, const soap_dp_batch *in, const soap_dp
                         const soap_dp_result *out, void *stream, uint32_t flags) {
   if (!ctx) return SOAP_DP_EINVAL;
   if (!scoring_ok(sc)) return SOAP_DP_EINVAL;
-  if (flags & ~(SOAP_DP_BATCHED | SOAP_DP_SCORE_ONLY | SOAP_DP_MIN_SCORE)) return SOAP_DP_EINVAL;
+  if (flags & ~(SOAP_DP_BATCHED | SOAP_DP_SCORE_ONLY | SOAP_DP_MIN_SCORE | SOAP_DP_FULL_WINDOW))
+    return SOAP_DP_EINVAL;
   const bool score = (flags & SOAP_DP_SCORE_ONLY) != 0;
   const int rc = batch_ok(in, out, score);
   if (rc) return rc;
@@ -1099,53 +1353,18 @@ int soap_dp_align_batch(soap_dp_ctx *ctx, const soap_dp_batch *in, const soap_dp
   DeviceGuard dg(ctx->device);
   const hipStream_t st = static_cast<hipStream_t>(stream);
   const soap_dp_scoring es = effective_scoring(sc, flags);
-  return (flags & SOAP_DP_BATCHED) ? align_batched(ctx, in, &es, out, st, score)
-                                   : align_plain(ctx, in, &es, out, st, score);
+  return align_dispatch(ctx, in, &es, out, st, flags);
 }
+
 
 size_t soap_dp_workspace_bytes(const soap_dp_ctx *ctx, int64_t n_tasks, int32_t max_n,
                                int32_t max_m, uint32_t flags) {
-  if (!ctx || n_tasks <= 0 || max_n < 1 || max_n > SOAP_DP_MAX_READ || max_m < 1 ||
-      max_m > SOAP_DP_MAX_WINDOW)
-    return 0;
-  const size_t small = kSmallInts * sizeof(int32_t);
-  const Kind k{kEither, (flags & SOAP_DP_SCORE_ONLY) != 0};
-  if ((flags & SOAP_DP_BATCHED) == 0) return plain_scratch_bytes(ctx, n_tasks, max_n, max_m, k) + small;
-  // the int32 classes are counted too: the scoring is not known here
-  std::vector<int> live;
-  int prev16 = 0, prev32 = 0;
-  for (size_t k = 0; k < ctx->classes.size(); ++k) {
-    const ClassSpec &c = ctx->classes[k];
-    int &prev = c.prec == 16 ? prev16 : prev32;
-    if (prev < max_n) live.push_back(int(k));
-    prev = c.cap;
-  }
-  return batched_scratch_bytes(ctx, n_tasks, max_m, k, live) + size_t(n_tasks) * 5 + small;
+  return workspace_bytes_for(ctx, n_tasks, max_n, max_m, flags, nullptr);
 }
 
 int soap_dp_reserve(soap_dp_ctx *ctx, int64_t n_tasks, int32_t max_n, int32_t max_m,
                     uint32_t flags) {
-  if (!ctx) return SOAP_DP_EINVAL;
-  const size_t b = soap_dp_workspace_bytes(ctx, n_tasks, max_n, max_m, flags);
-  if (b == 0) return SOAP_DP_EINVAL;
-  DeviceGuard dg(ctx->device);
-  const size_t small = kSmallInts * sizeof(int32_t);
-  size_t scratch = b - small;
-  if (flags & SOAP_DP_BATCHED) {
-    scratch -= size_t(n_tasks) * 5;
-    int rc = ensure_task_buffers(ctx, n_tasks);
-    if (rc) return rc;
-    // one stream per class a call with these bounds can populate
-    size_t n_live = 0;
-    int prev16 = 0, prev32 = 0;
-    for (const ClassSpec &c : ctx->classes) {
-      int &prev = c.prec == 16 ? prev16 : prev32;
-      if (prev < max_n) ++n_live;
-      prev = c.cap;
-    }
-    if ((rc = ensure_class_streams(ctx, n_live)) != SOAP_DP_OK) return rc;
-  }
-  return ensure_scratch(ctx, scratch);
+  return soapdp::ctx_reserve_for(ctx, n_tasks, max_n, max_m, flags, nullptr);
 }
 
 int soap_dp_autotune(soap_dp_ctx *ctx, const char *cache_path, int force) {
@@ -1164,12 +1383,13 @@ int soap_dp_autotune(soap_dp_ctx *ctx, const char *cache_path, int force) {
 
 int soap_dp_get_classes(const soap_dp_ctx *ctx, soap_dp_class_info *out, int32_t n_max) {
   if (!ctx) return SOAP_DP_EINVAL;
-  const int32_t cnt = int32_t(ctx->classes.size());
-  for (int32_t k = 0; out && k < cnt && k < n_max; ++k) {
-    out[k].precision = ctx->classes[size_t(k)].prec;
-    out[k].capacity = ctx->classes[size_t(k)].cap;
-    out[k].lanes = ctx->classes[size_t(k)].shape.lanes;
-    out[k].cells = ctx->classes[size_t(k)].shape.cells;
+  // the direct-form classes run their int16 class's shapes and are not listed
+  int32_t cnt = 0;
+  for (const ClassSpec &c : ctx->classes) {
+    if (c.prec == kPrecI16Direct) continue;
+    if (out && cnt < n_max)
+      out[cnt] = soap_dp_class_info{c.prec, c.cap, c.shape.lanes, c.shape.cells};
+    ++cnt;
   }
   return cnt;
 }
@@ -1185,6 +1405,7 @@ int soap_dp_set_class_shape(soap_dp_ctx *ctx, int32_t precision, int32_t capacit
     if (c.prec == precision && c.cap == capacity) {
       c.shape = s;
       c.score_shape = s;
+      mirror_direct_shapes(ctx->classes);
       clear_graphs(ctx);
       return SOAP_DP_OK;
     }
@@ -1211,6 +1432,8 @@ const char *soap_dp_strerror(int code) {
     case SOAP_DP_ENOMEM: return "device workspace allocation failed";
     case SOAP_DP_EHIP: return "HIP runtime error";
     case SOAP_DP_ENODEV: return "no usable gfx950 device";
+    case SOAP_DP_E2BIG: return "request larger than a slot, the device budget or the fixed scratch";
+    case SOAP_DP_ESTOPPED: return "server is shutting down";
     default: return "unknown error";
   }
 }

@@ -5,10 +5,18 @@
 
 namespace soapdp {
 
-constexpr int kMaxClasses = 32;
+constexpr int kMaxClasses = 48;
 
-// Classes in the order tried: int16 classes by ascending capacity, then
-// int32 classes by ascending capacity.  A class's capacity is its upper
+// Class kinds (ClassTable::prec): packed int16 in the offset form, packed
+// int16 in the direct form (saturating, with the int32 re-run of tasks too
+// close to the floor), int32.
+constexpr int kPrecI16 = 16;
+constexpr int kPrecI16Direct = 17;
+constexpr int kPrecI32 = 32;
+__host__ __device__ inline bool packed16(int prec) { return prec == kPrecI16 || prec == kPrecI16Direct; }
+
+// Classes in the order tried: int16 classes (offset form) by ascending
+// capacity, then int16 classes in the direct form, then int32 classes.  A class's capacity is its upper
 // bound on read length; `cols` is lanes * cells of its current shape.
 //
 // The launch fields describe each class kernel as the host enqueues it:
@@ -44,15 +52,19 @@ struct BucketBuffers {
   int32_t *defer;         // kMaxClasses: deferral of each class kernel
   uint64_t *slot_dwords;  // kMaxClasses: decision-slot size of each class
   uint64_t *scratch_off;  // kMaxClasses: scratch region of each class (dwords)
+  int32_t *redo_list;     // n_tasks: tasks the direct-form kernels flag
+  int32_t *redo_count;    // their count (cleared by the bucketing)
+  int32_t *redo_work_counter;   // work queue of the int32 re-run (cleared likewise)
 };
 
 // Round a region to 64 dwords (256 bytes).
 __host__ __device__ inline uint64_t round64(uint64_t dwords) { return (dwords + 63) & ~uint64_t(63); }
 
 // Enqueue: zero the histogram, classify (invalid tasks get their outputs),
-// scan and plan, scatter.  `p` carries the batch, scoring and outputs.
+// scan and plan, scatter.  `p` carries the batch, scoring and outputs.  The
+// class lists take the tasks in `order` (nullptr: index order).
 hipError_t launch_bucketing(const DpParams &p, const ClassTable &ct, const BucketBuffers &b,
-                            hipStream_t stream);
+                            const int32_t *order, hipStream_t stream);
 hipError_t launch_zero(int32_t *a, int n, hipStream_t stream);
 // First CIGAR words of every task, gathered densely for one small copy back
 // to the host: head[t * kCigarHeadWords + k] = word k of task t's row for

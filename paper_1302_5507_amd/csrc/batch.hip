@@ -1,7 +1,9 @@
 // Device-side length bucketing for the batched form.  Every task is put in
 // the smallest length class whose kernel shape holds its read: a packed
-// int16 class when the task's values stay inside int16 (int16_fits), else
-// an int32 class.  Invalid tasks get their status and zero outputs here.
+// int16 class in the offset form when the task's values stay inside int16
+// (int16_fits), else one in the direct form when its read keeps every value
+// below the int16 ceiling (int16_direct_fits), else an int32 class.
+// Invalid tasks get their status and zero outputs here.
 // The class segments of one task list are built with per-workgroup
 // histograms and one atomic per class and workgroup, so nothing depends on
 // the host and the whole sequence can be replayed as a graph.
@@ -16,14 +18,18 @@ constexpr int kBlock = 256;
 
 __device__ int class_of(const ClassTable &ct, int32_t n, int32_t m, int32_t ma, int32_t mi,
                         int32_t go, int32_t ge) {
-  // int16 classes first (ascending capacity), then int32 classes
+  // int16 offset-form classes first (ascending capacity), then the direct
+  // form, then int32 classes
   for (int k = 0; k < ct.count; ++k) {
-    if (ct.prec[k] != 16 || ct.cap[k] < n) continue;
+    if (ct.prec[k] != kPrecI16 || ct.cap[k] < n) continue;
     if (int16_fits(n, m, ct.cols[k], ma, mi, go, ge)) return k;
-    break;   // a wider int16 shape only narrows the range; go to int32
+    break;   // a wider int16 shape only narrows the range
   }
+  if (int16_direct_fits(n, ma, mi, go, ge))
+    for (int k = 0; k < ct.count; ++k)
+      if (ct.prec[k] == kPrecI16Direct && ct.cap[k] >= n) return k;
   for (int k = 0; k < ct.count; ++k)
-    if (ct.prec[k] == 32 && ct.cap[k] >= n) return k;
+    if (ct.prec[k] == kPrecI32 && ct.cap[k] >= n) return k;
   return -1;
 }
 
@@ -123,14 +129,19 @@ __global__ void scan_kernel(ClassTable ct, const int32_t *hist, const int32_t *m
   }
 }
 
+// Class lists follow `order` (nullptr: task index order) up to the
+// interleaving of workgroups.
 __global__ __launch_bounds__(kBlock) void scatter_kernel(const uint8_t *task_class, int64_t n_tasks,
-                                                         int32_t *cursor, int32_t *task_list) {
+                                                         const int32_t *order, int32_t *cursor,
+                                                         int32_t *task_list) {
   __shared__ int32_t s_cnt[kMaxClasses], s_base[kMaxClasses];
   for (int k = threadIdx.x; k < kMaxClasses; k += kBlock) s_cnt[k] = 0;
   __syncthreads();
-  const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t x = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  int64_t t = -1;
   int k = 0xff, rank = 0;
-  if (t < n_tasks) {
+  if (x < n_tasks) {
+    t = order ? (int64_t)order[x] : x;
     k = task_class[t];
     if (k != 0xff) rank = atomicAdd(&s_cnt[k], 1);
   }
@@ -138,7 +149,7 @@ __global__ __launch_bounds__(kBlock) void scatter_kernel(const uint8_t *task_cla
   for (int c = threadIdx.x; c < kMaxClasses; c += kBlock)
     s_base[c] = s_cnt[c] ? atomicAdd(&cursor[c], s_cnt[c]) : 0;
   __syncthreads();
-  if (t < n_tasks && k != 0xff) task_list[s_base[k] + rank] = (int32_t)t;
+  if (x < n_tasks && k != 0xff) task_list[s_base[k] + rank] = (int32_t)t;
 }
 
 __global__ __launch_bounds__(kBlock) void gather_cigar_head_kernel(const uint32_t *cigar,
@@ -165,15 +176,16 @@ hipError_t launch_gather_cigar_head(const uint32_t *cigar, int32_t stride, const
 }
 
 hipError_t launch_bucketing(const DpParams &p, const ClassTable &ct, const BucketBuffers &b,
-                            hipStream_t stream) {
+                            const int32_t *order, hipStream_t stream) {
   const int64_t blocks = (p.n_tasks + kBlock - 1) / kBlock;
   hipLaunchKernelGGL(zero_kernel, dim3(1), dim3(64), 0, stream, b.hist, 2 * kMaxClasses);
+  hipLaunchKernelGGL(zero_kernel, dim3(1), dim3(64), 0, stream, b.redo_count, 2);
   hipLaunchKernelGGL(classify_kernel, dim3((uint32_t)blocks), dim3(kBlock), 0, stream, p, ct,
                      b.task_class, b.hist, b.max_m);
   hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(64), 0, stream, ct, b.hist, b.max_m, b.offset,
                      b.cursor, b.work_counter, b.defer, b.slot_dwords, b.scratch_off);
   hipLaunchKernelGGL(scatter_kernel, dim3((uint32_t)blocks), dim3(kBlock), 0, stream, b.task_class,
-                     p.n_tasks, b.cursor, b.task_list);
+                     p.n_tasks, order, b.cursor, b.task_list);
   return hipGetLastError();
 }
 

@@ -14,4 +14,10 @@ namespace soapdp {
 // memory or captures a graph while other slots' work runs.
 void ctx_set_frozen(soap_dp_ctx *ctx, bool frozen);
 
+// soap_dp_reserve for calls with this scoring only: the workspace covers the
+// length classes those calls can populate (soap_dp_reserve, which does not
+// know the scoring, covers every class kind).
+int ctx_reserve_for(soap_dp_ctx *ctx, int64_t n_tasks, int32_t max_n, int32_t max_m,
+                    uint32_t flags, const soap_dp_scoring *sc);
+
 }  // namespace soapdp

@@ -4,6 +4,17 @@
 // different tasks that share the lane geometry, so each packed VALU
 // instruction advances two cells.
 //
+// Two forms.  The offset form (below) is the cheaper one and serves every
+// task whose values provably stay inside int16.  The direct form (kDirect)
+// keeps the true values, so nothing drifts with the window length, and lets
+// low values saturate: it serves tasks the offset form's rule excludes,
+// flags those whose score lies too close to the saturation floor to be
+// exact (int16_direct_fits, direct_floor) and appends them to a list the
+// int32 kernel re-runs.  It differs from the offset form in four places:
+// gap extensions add S_GE, M is carried as G = M + S_GO, the left boundary
+// is the constant M = 0, and the diagonal constant of a column pair is
+// e * g + b from a byte table (one v_perm_b32 and one v_pk_mad_u16).
+//
 // Same offset form as the int32 kernel, X^(i,j) = X(i,j) - (i+j)*S_GE, so
 // gap extension adds nothing.  Differences from the int32 kernel, all exact:
 //  * The diagonal adds delta - 2 S_GE: S_MA - 2 S_GE on a match and
@@ -43,6 +54,14 @@ __device__ __forceinline__ uint32_t max16(uint32_t a, uint32_t b) {
 __device__ __forceinline__ uint32_t pack16(int32_t lo, int32_t hi) {
   return ((uint32_t)lo & 0xffffu) | ((uint32_t)hi << 16);
 }
+__device__ __forceinline__ int32_t clamp16(int32_t v) { return v < -32768 ? -32768 : (v > 32767 ? 32767 : v); }
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+// e * g + b on both halves, modulo 2^16 (the exact 16-bit pattern of a
+// constant inside int16)
+__device__ __forceinline__ uint32_t mad16(uint32_t e, uint32_t g, uint32_t b) {
+  return __builtin_bit_cast(uint32_t, __builtin_bit_cast(u16x2, e) * __builtin_bit_cast(u16x2, g) +
+                                          __builtin_bit_cast(u16x2, b));
+}
 
 constexpr uint32_t kNeg16x2 = 0x80008000u;   // (-32768, -32768)
 constexpr uint32_t kSignSel = 0x0b0a0908u;   // v_perm: replicate the four sign bits
@@ -53,7 +72,7 @@ constexpr uint32_t kSignSel = 0x0b0a0908u;   // v_perm: replicate the four sign 
 // VGPRs) without spilling once the compiler is asked to; wider ones would
 // spill and keep the default.
 // kScore: score and end only -- no decision bits, no scratch, no traceback.
-template <int L, int K, bool kScore>
+template <int L, int K, bool kScore, bool kDirect>
 __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(K <= 8 ? 5 : 1)))
 void dp_i16_kernel(DpParams p) {
   static_assert(kWave % L == 0, "lanes per task must divide the wavefront");
@@ -91,16 +110,32 @@ void dp_i16_kernel(DpParams p) {
 
   const int32_t ma = p.ma, mi = p.mi, go = p.go, ge = p.ge;
   const int32_t go1 = go - ge;                        // gap open, offset form
-  const uint32_t c_go = pack16(go1, go1);
+  // H holds G = M^ + (S_GO - S_GE) (offset form) or G = M + S_GO (direct
+  // form): the gap-open candidate of the cell to the right (same row) and
+  // of the cell below (next row) without another add.
+  const int32_t gadd = kDirect ? go : go1;
+  const uint32_t c_go = pack16(gadd, gadd);
   const uint32_t c_ge = pack16(ge, ge);
   const uint32_t c_nge = pack16(-ge, -ge);
-  // H holds G = M^ + (S_GO - S_GE): the gap-open candidate of the cell to the
-  // right (same row) and of the cell below (next row) without another add.
-  // Diagonal constants relative to it, x = 0 match, 1..3 mismatch, 4..7
-  // virtual: delta - 2 S_GE - (S_GO - S_GE).
-  const uint32_t tab_lo = ((uint32_t)(ma - 2 * ge - go1) & 0xffu) |
-                          ((uint32_t)(mi - 2 * ge - go1) & 0xffu) * 0x01010100u;
-  const uint32_t tab_hi = ((uint32_t)(-2 * ge - go1) & 0xffu) * 0x01010101u;
+  // Diagonal constants relative to G, byte x = (read code XOR window base):
+  // x = 0 match, 1..3 mismatch, 4..7 left of the read.  Offset form: the
+  // constants themselves, delta - 2 S_GE - (S_GO - S_GE).  Direct form: the
+  // multipliers e of e * g + b for delta - S_GO (0 - S_GO left of the read).
+  DirectDelta dd{1, 0, 0, 0, 0};
+  if constexpr (kDirect) direct_delta(ma, mi, go, &dd);
+  const uint32_t tab_lo =
+      kDirect ? ((uint32_t)dd.e_ma & 0xffu) | ((uint32_t)dd.e_mi & 0xffu) * 0x01010100u
+              : ((uint32_t)(ma - 2 * ge - go1) & 0xffu) |
+                    ((uint32_t)(mi - 2 * ge - go1) & 0xffu) * 0x01010100u;
+  const uint32_t tab_hi = kDirect ? ((uint32_t)dd.e_v & 0xffu) * 0x01010101u
+                                  : ((uint32_t)(-2 * ge - go1) & 0xffu) * 0x01010101u;
+  const uint32_t c_dg = pack16(dd.g, dd.g), c_db = pack16(dd.b, dd.b);
+  // diagonal constants of a column pair from the selector (code ^ base)
+  auto dconst = [&](uint32_t sel) {
+    const uint32_t e = __builtin_amdgcn_perm(tab_hi, tab_lo, sel);
+    if constexpr (kDirect) return mad16(e, c_dg, c_db);
+    else return e;
+  };
 
   int64_t item = blockIdx.x;
   while (item < n_items) {
@@ -125,8 +160,9 @@ void dp_i16_kernel(DpParams p) {
         else if (rwo[h] + (uint64_t)((n[h] + 15) >> 4) > p.read_words ||
                  rbo[h] + (uint64_t)m[h] > p.ref_words * 16)
           st[h] = kTaskInvalidOffset;
-        else if (!int16_fits(n[h], m[h], L * K, ma, mi, go, ge))
-          task[h] = -1;   // outside the int16 range: the int32 kernel owns it
+        else if (kDirect ? !int16_direct_fits(n[h], ma, mi, go, ge)
+                         : !int16_fits(n[h], m[h], L * K, ma, mi, go, ge))
+          task[h] = -1;   // outside this form's range: another kernel owns it
       }
       const bool valid = task[h] >= 0 && st[h] == kTaskOk;
       mg[h] = valid ? m[h] : 0;
@@ -161,9 +197,12 @@ void dp_i16_kernel(DpParams p) {
         const int32_t q = lg * K + c - pad[h];   // 0-based read index of this column
         const bool real = mg[h] > 0 && q >= 0;
         code[h] = real ? rw[h].code(q) : 4u;     // virtual: table entries 4..7
-        // M^(0, j), j = q + 1: S_GO + (j-1) S_GE - j S_GE, or 0 - j S_GE left
-        // of the read; held as G = M^ + (S_GO - S_GE)
-        hv[h] = (real ? go1 : -(q + 1) * ge) + go1;
+        // offset form: M^(0, j), j = q + 1: S_GO + (j-1) S_GE - j S_GE, or
+        // 0 - j S_GE left of the read, held as G = M^ + (S_GO - S_GE);
+        // direct form: M(0, j) = S_GO + (j-1) S_GE (0 left of the read) as
+        // G = M + S_GO, saturated
+        hv[h] = kDirect ? clamp16((real ? go + q * ge : 0) + go)
+                        : (real ? go1 : -(q + 1) * ge) + go1;
       }
       Rc[c] = (code[0] | 0x0c00u) | ((code[1] | 0x0c00u) << 16);
       H[c] = pack16(hv[0], hv[1]);
@@ -174,9 +213,11 @@ void dp_i16_kernel(DpParams p) {
     }
     // left boundary M^(i, -pad) = -(i - pad) S_GE (true value 0), as G: row 0
     // is the first lane's first diagonal, row 1 its first left neighbour
-    uint32_t bnd = pack16((pad[0] - 1) * ge + go1, (pad[1] - 1) * ge + go1);
-    // i * S_GE of this lane's row, minus (S_GO - S_GE)
-    uint32_t rge = pack16((1 - lg) * ge - go1, (1 - lg) * ge - go1);
+    // (direct form: the constant M = 0 as G = S_GO)
+    uint32_t bnd = kDirect ? pack16(go, go) : pack16((pad[0] - 1) * ge + go1, (pad[1] - 1) * ge + go1);
+    // i * S_GE of this lane's row, minus (S_GO - S_GE) (direct form: -S_GO,
+    // so that G + rge is M)
+    uint32_t rge = kDirect ? pack16(-go, -go) : pack16((1 - lg) * ge - go1, (1 - lg) * ge - go1);
 
     // window bases, 16 at a time per task, realigned from the base offset
     const uint64_t wlim = p.ref_words - 1;
@@ -189,7 +230,7 @@ void dp_i16_kernel(DpParams p) {
     uint32_t hl_out = H[K - 1];
     uint32_t el_out = kNeg16x2;
     uint32_t t_out = 0;
-    uint32_t hl_prev = pack16(pad[0] * ge + go1, pad[1] * ge + go1);
+    uint32_t hl_prev = kDirect ? pack16(go, go) : pack16(pad[0] * ge + go1, pad[1] * ge + go1);
     int32_t best0 = INT32_MIN, best1 = INT32_MIN;
     uint32_t accA[W], accB[W];
 #pragma unroll
@@ -218,15 +259,16 @@ void dp_i16_kernel(DpParams p) {
       if ((uint32_t)(t - lg) < (uint32_t)mlane) {   // 1 <= i <= mlane
         // The diagonal candidate of column c+1 is formed from the old H[c]
         // before H[c] is overwritten, so every update happens in place.
-        uint32_t diag = add16(hd, __builtin_amdgcn_perm(tab_hi, tab_lo, Rc[0] ^ T));
+        uint32_t diag = add16(hd, dconst(Rc[0] ^ T));
 #pragma unroll
         for (int c = 0; c < K; ++c) {
           const uint32_t ad = H[c];   // G of the cell above: D-open candidate
           uint32_t diag_next = 0;
-          if (c + 1 < K) diag_next = add16(H[c], __builtin_amdgcn_perm(tab_hi, tab_lo, Rc[c + 1] ^ T));
+          if (c + 1 < K) diag_next = add16(H[c], dconst(Rc[c + 1] ^ T));
           const uint32_t ai = hl;     // G of the cell to the left: I-open candidate
-          el = max16(ai, el);
-          const uint32_t f = max16(ad, F[c]);
+          // gap extension: free in the offset form, + S_GE in the direct form
+          el = max16(ai, kDirect ? add16(el, c_ge) : el);
+          const uint32_t f = max16(ad, kDirect ? add16(F[c], c_ge) : F[c]);
           const uint32_t hv = max16(max16(diag, el), f);
           // differences against the maxima, so the old I and D die at the max
           // and the new values take their registers
@@ -280,8 +322,10 @@ void dp_i16_kernel(DpParams p) {
           __syncthreads();
         }
       }
-      bnd = add16(bnd, c_nge);
-      rge = add16(rge, c_ge);
+      if constexpr (!kDirect) {
+        bnd = add16(bnd, c_nge);
+        rge = add16(rge, c_ge);
+      }
     }
 
 #pragma unroll
@@ -310,11 +354,18 @@ void dp_i16_kernel(DpParams p) {
           const int rs = lane / TPW, ui = lane % TPW;
           const int h = ui / G, gq = ui % G;
           const int32_t tn = s_n[lane], tpad = s_pad[lane], tend = s_end[lane];
-          const int32_t tscore = s_score[lane] + tn * ge;
+          const int32_t tscore = kDirect ? s_score[lane] : s_score[lane] + tn * ge;
           p.score[tk] = tscore;
           p.ref_end[tk] = tend;
           p.status[tk] = tscore < p.min_score ? kTaskBelowCutoff : p.ok_status;
-          if (tscore < p.min_score) {   // below the cutoff: no traceback
+          if (kDirect && tscore <= direct_floor(tn, ma, go)) {
+            // too close to the saturation floor to be exact: int32 re-run
+            (void)tpad;
+            p.status[tk] = kTaskNeedsRedo;
+            p.ref_begin[tk] = -1;
+            p.cigar_len[tk] = 0;
+            p.redo_list[atomicAdd(p.redo_count, 1)] = (int32_t)tk;
+          } else if (tscore < p.min_score) {   // below the cutoff: no traceback
             (void)tpad;
             p.ref_begin[tk] = -1;
             p.cigar_len[tk] = 0;
@@ -366,31 +417,46 @@ uint64_t slot_dwords_i16(Shape s, int32_t max_m) {
   return steps * uint64_t((s.cells + 7) / 8) * kWave * 2;
 }
 
-hipError_t launch_dp_i16(Shape s, int grid, hipStream_t stream, const DpParams &p) {
-#define X(l, k)                                                                                \
-  if (s.lanes == l && s.cells == k) {                                                          \
-    if (p.score_only)                                                                          \
-      hipLaunchKernelGGL((dp_i16_kernel<l, k, true>), dim3(grid), dim3(kWave), 0, stream, p);  \
-    else                                                                                       \
-      hipLaunchKernelGGL((dp_i16_kernel<l, k, false>), dim3(grid), dim3(kWave), 0, stream, p); \
-    return hipGetLastError();                                                                  \
-  }
+template <int L, int K>
+hipError_t launch_i16(int grid, hipStream_t stream, const DpParams &p, bool direct) {
+  const bool score = p.score_only != 0;
+  if (score && direct)
+    hipLaunchKernelGGL((dp_i16_kernel<L, K, true, true>), dim3(grid), dim3(kWave), 0, stream, p);
+  else if (score)
+    hipLaunchKernelGGL((dp_i16_kernel<L, K, true, false>), dim3(grid), dim3(kWave), 0, stream, p);
+  else if (direct)
+    hipLaunchKernelGGL((dp_i16_kernel<L, K, false, true>), dim3(grid), dim3(kWave), 0, stream, p);
+  else
+    hipLaunchKernelGGL((dp_i16_kernel<L, K, false, false>), dim3(grid), dim3(kWave), 0, stream, p);
+  return hipGetLastError();
+}
+
+template <int L, int K>
+int occupancy_i16(bool score, bool direct) {
+  int blocks = 0;
+  hipError_t e;
+  if (score && direct)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, dp_i16_kernel<L, K, true, true>, kWave, 0);
+  else if (score)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, dp_i16_kernel<L, K, true, false>, kWave, 0);
+  else if (direct)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, dp_i16_kernel<L, K, false, true>, kWave, 0);
+  else
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, dp_i16_kernel<L, K, false, false>, kWave, 0);
+  return e == hipSuccess ? blocks : 0;
+}
+
+hipError_t launch_dp_i16(Shape s, int grid, hipStream_t stream, const DpParams &p, bool direct) {
+#define X(l, k) \
+  if (s.lanes == l && s.cells == k) return launch_i16<l, k>(grid, stream, p, direct);
   SOAPDP_I16_SHAPES(X)
 #undef X
   return hipErrorInvalidValue;
 }
 
-int occupancy_dp_i16(Shape s, bool score_only) {
-  int blocks = 0;
-  hipError_t e = hipErrorInvalidValue;
-#define X(l, k)                                                                          \
-  if (s.lanes == l && s.cells == k) {                                                    \
-    e = score_only ? hipOccupancyMaxActiveBlocksPerMultiprocessor(                       \
-                         &blocks, dp_i16_kernel<l, k, true>, kWave, 0)                   \
-                   : hipOccupancyMaxActiveBlocksPerMultiprocessor(                       \
-                         &blocks, dp_i16_kernel<l, k, false>, kWave, 0);                 \
-    return e == hipSuccess ? blocks : 0;                                                 \
-  }
+int occupancy_dp_i16(Shape s, bool score_only, bool direct) {
+#define X(l, k) \
+  if (s.lanes == l && s.cells == k) return occupancy_i16<l, k>(score_only, direct);
   SOAPDP_I16_SHAPES(X)
 #undef X
   return 0;

@@ -16,6 +16,10 @@ constexpr uint8_t kTaskInvalidLen = 1;
 constexpr uint8_t kTaskRedone = 2;
 constexpr uint8_t kTaskInvalidOffset = 3;
 constexpr uint8_t kTaskBelowCutoff = 5;
+// Internal: an int16 kernel in the direct form found the task's score too
+// close to the saturation floor for its outputs to be exact; the int32
+// re-run overwrites this status.
+constexpr uint8_t kTaskNeedsRedo = 0xfe;
 
 // Arguments of every DP kernel, passed by value.
 struct DpParams {
@@ -67,6 +71,10 @@ struct DpParams {
   // Tasks scoring below this get kTaskBelowCutoff and no traceback
   // (INT32_MIN: no cutoff).
   int32_t min_score;
+  // int16 direct form: tasks whose score lies too close to the saturation
+  // floor are appended here (atomically counted) for the int32 re-run.
+  int32_t *redo_list;
+  int32_t *redo_count;
 };
 
 // Decision words are stored in blocks of `step_block(K)` sweep steps: within
@@ -115,6 +123,62 @@ __host__ __device__ inline bool int16_fits(int32_t n, int32_t m, int32_t cols, i
   return lo - 2 * s > -32000 && hi + 2 * s < 32000;
 }
 
+// The int16 direct form keeps the true values, with M carried as
+// G = M + S_GO, and saturates.  Its diagonal constants relative to G are
+// S_MA - S_GO (match), S_MI - S_GO (mismatch) and -S_GO (left of the read,
+// where M stays 0).  They are formed as e * g + b from a byte e looked up
+// per column pair (one byte permute, one packed multiply-add): b is the
+// smallest constant, g the greatest common divisor of the others' distances
+// to it, and every e must fit a byte.
+struct DirectDelta {
+  int32_t g, b, e_ma, e_mi, e_v;
+};
+
+__host__ __device__ inline int64_t gcd64(int64_t a, int64_t b) {
+  while (b) {
+    const int64_t t = a % b;
+    a = b;
+    b = t;
+  }
+  return a < 0 ? -a : a;
+}
+
+__host__ __device__ inline bool direct_delta(int32_t ma, int32_t mi, int32_t go, DirectDelta *d) {
+  const int64_t c_ma = int64_t(ma) - go, c_mi = int64_t(mi) - go, c_v = -int64_t(go);
+  int64_t b = c_ma < c_mi ? c_ma : c_mi;
+  b = b < c_v ? b : c_v;
+  const int64_t g0 = gcd64(gcd64(c_ma - b, c_mi - b), c_v - b);
+  const int64_t g = g0 ? g0 : 1;
+  const int64_t e_ma = (c_ma - b) / g, e_mi = (c_mi - b) / g, e_v = (c_v - b) / g;
+  if (d) *d = DirectDelta{int32_t(g), int32_t(b), int32_t(e_ma), int32_t(e_mi), int32_t(e_v)};
+  auto in16 = [](int64_t v) { return v >= -32000 && v <= 32000; };
+  return e_ma <= 255 && e_mi <= 255 && e_v <= 255 && in16(c_ma) && in16(c_mi) && in16(c_v) &&
+         in16(g) && in16(b);
+}
+
+// int16 direct form: a task runs there when the offset form's rule
+// (int16_fits) fails but its read cannot push any value above int16: every
+// value is at most n S_MA (plus the constants added on the way, bounded by
+// |S_GO| + |S_GE|).  Low values saturate at -32768 instead of being ruled
+// out: a saturated value only ever rises, and by at most S_MA per read
+// column, so every value of column j that is wrong stays at or below
+// B_j = -32768 + |S_GO| + j S_MA.  A cell of an optimal alignment of score
+// S lies at or above S - (n - j) S_MA, so when S > B_n every such cell, and
+// every comparison it wins or ties, is exact, and so are the score, the end
+// and the traceback; tasks with S <= B_n (decided on the computed score,
+// which exceeds B_n exactly when the true one does) are re-run in int32.
+__host__ __device__ inline bool int16_direct_fits(int32_t n, int32_t ma, int32_t mi, int32_t go,
+                                                  int32_t ge) {
+  if (!direct_delta(ma, mi, go, nullptr)) return false;
+  const int64_t hi = int64_t(n) * ma - int64_t(go) - int64_t(ge);
+  return hi < 32000;
+}
+
+// The saturation floor of the direct form's result column, B_n above.
+__host__ __device__ inline int32_t direct_floor(int32_t n, int32_t ma, int32_t go) {
+  return -32768 - go + n * ma;
+}
+
 // Launch the int32 kernel of shape `s` (must be one of the compiled shapes);
 // the variant with the byte-table diagonal runs when the scoring allows it
 // (byte_delta_fits).
@@ -125,9 +189,10 @@ int occupancy_dp_i32(Shape s, bool byte_delta, bool score_only);
 // The compiled int32 shapes.
 const Shape *shapes_i32(int *count);
 
-// Same for the packed int16 kernel (two tasks per lane, lo and hi halves).
-hipError_t launch_dp_i16(Shape s, int grid, hipStream_t stream, const DpParams &p);
-int occupancy_dp_i16(Shape s, bool score_only);
+// Same for the packed int16 kernel (two tasks per lane, lo and hi halves),
+// offset form or direct form.
+hipError_t launch_dp_i16(Shape s, int grid, hipStream_t stream, const DpParams &p, bool direct);
+int occupancy_dp_i16(Shape s, bool score_only, bool direct);
 const Shape *shapes_i16(int *count);
 // Decision-scratch dwords of one workgroup slot.
 uint64_t slot_dwords_i32(Shape s, int32_t max_m);

@@ -464,7 +464,8 @@ int soap_dp_server_create(soap_dp_server **out, const soap_dp_server_config *cfg
     }
   }
   for (size_t k = 0; k < srv->slots.size() && !rc; ++k)
-    rc = soap_dp_reserve(srv->slots[k].ctx, cfg->max_tasks, cfg->max_n, cfg->max_m, SOAP_DP_BATCHED);
+    rc = soapdp::ctx_reserve_for(srv->slots[k].ctx, cfg->max_tasks, cfg->max_n, cfg->max_m,
+                                 SOAP_DP_BATCHED, &cfg->scoring);
   for (size_t k = 0; k < srv->slots.size() && !rc; ++k) {
     soapdp::ctx_set_frozen(srv->slots[k].ctx, true);
     rc = warm_up(srv, srv->slots[k]);

@@ -47,7 +47,7 @@ def test_library_contains_gfx950_code():
 def test_strerror_and_null_arguments():
     lib = binding.lib()
     assert binding.soap_dp_strerror(0) == "ok"
-    for code in (-1, -2, -3, -4):
+    for code in (-1, -2, -3, -4, -5, -6):
         assert binding.soap_dp_strerror(code) != "unknown error"
     assert lib.soap_dp_align_batch(None, None, None, None, None, 0) == binding.SOAP_DP_EINVAL
     assert lib.soap_dp_create(None, 0) == binding.SOAP_DP_EINVAL

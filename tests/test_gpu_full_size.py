@@ -1,8 +1,10 @@
 """Every task of the benchmark workloads at full size, in both forms (the
-plain one-launch kernel and the batched form, in the launch configuration
-bench.py times), compared with the CPU oracle element by element: score,
-begin, end, status and every CIGAR word.  The oracle runs over chunks of the
-batch so that host memory stays bounded."""
+plain int32 form and the batched form, in the launch configuration bench.py
+times: two passes, score first and traceback over the band), and in both
+forms again with one pass over the whole window (SOAP_DP_FULL_WINDOW),
+compared with the CPU oracle element by element: score, begin, end, status
+and every CIGAR word.  The oracle runs over chunks of the batch so that host
+memory stays bounded."""
 import numpy as np
 import pytest
 
@@ -40,7 +42,9 @@ def test_every_task_both_forms(name):
     al.autotune(None)
     dw = binding.DeviceWorkload(w)
     forms = {}
-    for form, flags in (("plain", binding.PLAIN), ("batched", binding.BATCHED)):
+    for form, flags in (("plain", binding.PLAIN), ("batched", binding.BATCHED),
+                        ("plain one-pass", binding.PLAIN | binding.FULL_WINDOW),
+                        ("batched one-pass", binding.BATCHED | binding.FULL_WINDOW)):
         res = binding.DeviceResult(w.n_tasks, 2 * dw.max_n)
         al.align(dw, CONFIG_SCORING, flags=flags, res=res)
         forms[form] = res

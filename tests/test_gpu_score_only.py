@@ -1,9 +1,10 @@
 """GPU: the score-only flag (SOAP_DP_SCORE_ONLY) gives exactly the score,
 end and status of the full call, in both forms and for every kernel path
-(int16, the int32 byte-table and general variants; x30 scoring, where the
-150 and 250 bp reads leave the int16 range and one batch runs both int16
-and int32 class kernels; x50 scoring, where every task runs in int32),
-writes ref_begin -1 and cigar_len 0, and accepts a NULL CIGAR buffer."""
+(int16 offset form, the int32 byte-table and general variants; x30
+scoring, where the 150 and 250 bp reads leave the offset form and one batch
+runs both int16 forms; x128 scoring, where the 250 bp reads run in the
+int32 classes, the others in the direct int16 form), writes ref_begin -1
+and cigar_len 0, and accepts a NULL CIGAR buffer."""
 import numpy as np
 import pytest
 
@@ -24,7 +25,7 @@ def _run(w, sc, flags, cigar=True):
 
 
 @pytest.mark.parametrize("form", [binding.PLAIN, binding.BATCHED])
-@pytest.mark.parametrize("sc", SCORING_SETS + [tuple(k * x for x in CONFIG_SCORING) for k in (30, 50)])
+@pytest.mark.parametrize("sc", SCORING_SETS + [tuple(k * x for x in CONFIG_SCORING) for k in (30, 128)])
 def test_score_only_equals_full(form, sc):
     w = workloads.config3(n_reads=4000, seed=31)
     ref = oracle_align(w, sc)
