@@ -1,15 +1,18 @@
 """Benchmark: GCUPS with traceback of batched read-vs-window affine-gap
 alignment on one MI355X (seeded synthetic data).
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload config2|config3|config5|config4|multi|mate]
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+                    [--workload config5|config2|config3|config4|multi|mate]
 
-Default workload: the mate-rescue batch, 1,000,000 reads x 100 bp against
-250 bp windows, aligned by the plain one-launch int32 kernel (`value`); the
-batched form (length classes, packed int16 with int32 re-run, persistent
-kernels, graph replay, autotuned shapes) runs on the same data and is
-reported beside it.  A step is one soap_dp_align_batch call over the whole
-batch (fill, traceback and CIGAR of every task), inputs resident in device
-memory.  Prints one JSON line.
+Default workload: the low-similarity batch, 500,000 reads x 150 bp at
+60-75% identity against 1,000 bp windows.  `value` is the plain int32
+form's GCUPS; the batched form (length classes, packed int16 with int32
+re-run, persistent kernels, graph replay, autotuned shapes) runs on the same
+data and is reported beside it with its own roofline.  A step is one
+soap_dp_align_batch call over the whole batch (fill, traceback and CIGAR of
+every task), inputs resident in device memory.  The default run adds the
+uneven batch (2,000,000 reads of 36-250 bp) in both forms and a served leg
+at the frozen arrival rate with its p50/p99 latency.  Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -29,6 +32,9 @@ METRIC = "GCUPS w/ traceback, batched vs plain kernel; p50/p99 latency at fixed 
 SCORING = (1, -3, -5, -2)
 OPS_PER_CELL = 14            # 10 score operations + 4 decision comparisons per cell
 OPS_PER_CELL_SCORE = 10      # score-only pass: no decision comparisons
+# Calls with traceback run two passes: the score recurrences over every
+# window cell, then recurrences and decisions over the band cells only, so
+# their algorithmic count is 10 per window cell plus 14 per band cell.
 PEAK_INT32_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12   # CUs x SIMDs x lanes x clock = 39.3 T lane-ops/s
 PEAK_INT16_TOPS = 2 * PEAK_INT32_TOPS            # packed 2 x int16 per lane
 
@@ -64,30 +70,46 @@ def traffic_bytes(workload: str, form: str):
     return int(round((t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"]) * 1024))
 
 
+# VALU wave-instructions per dispatch of the dominant kernel (rocprofv3
+# --pmc SQ_INSTS_VALU), same keying and fingerprint rule as TRAFFIC.  The
+# issue fraction divides them by what the chip can issue in the measured
+# kernel time: one wave64 VALU instruction per SIMD every 4 cycles.
+VALU_ISSUE_PER_S = 256 * 4 * 2.4e9 / 4
+VALU_INSTS = {}
+
+
+def valu_issue_frac(workload: str, form: str, kernel_ms: float):
+    t = VALU_INSTS.get((workload, form))
+    if t is None or t["fingerprint"] != kernel_fingerprint():
+        return None
+    return round(t["sq_insts_valu"] / (kernel_ms * 1e-3 * VALU_ISSUE_PER_S), 4)
+
+
 WORKLOADS = {
     "config2": ("mate-rescue: 1,000,000 reads x 100 bp vs 250 bp windows from a 1 Mbp random "
                 "genome (2% subs, 0.5% indels, 10% random reads)", "config2", "plain"),
     "config3": ("uneven: 2,000,000 reads, n uniform over {36,50,75,100,150,250}, m = n + 160 "
                 "(4% subs, 0.5% indels up to 30 bp)", "config3", "batched"),
-    "config5": ("low-similarity: 500,000 reads x 150 bp at 60-75% identity vs 1,000 bp windows",
-                "config5", "batched"),
+    "config5": ("low-similarity: 500,000 reads x 150 bp at 60-75% identity vs 1,000 bp windows "
+                "from a 1 Mbp random genome (substitutions 0.75 d, indel events 0.05 d of "
+                "geometric length <= 50, d = 1 - identity)", "config5", "plain"),
 }
 
 
-def cpu_baseline(w, tasks: int):
+def cpu_baseline(w, tasks: int, scoring=SCORING):
     import oracle
     idx = np.arange(min(tasks, w.n_tasks))
     cells = int(np.dot(w.read_len[idx].astype(np.int64), w.ref_len[idx].astype(np.int64)))
     threads = oracle.default_threads()
     t0 = time.perf_counter()
-    oracle.align_workload(w, oracle.scoring(*SCORING), idx=idx, n_threads=threads)
+    oracle.align_workload(w, oracle.scoring(*scoring), idx=idx, n_threads=threads)
     dt = time.perf_counter() - t0
     what = "all" if idx.size == w.n_tasks else f"first {idx.size:,}"
     # one core on a fixed 20,000-task prefix
     idx1 = np.arange(min(20_000, w.n_tasks))
     cells1 = int(np.dot(w.read_len[idx1].astype(np.int64), w.ref_len[idx1].astype(np.int64)))
     t1 = time.perf_counter()
-    oracle.align_workload(w, oracle.scoring(*SCORING), idx=idx1, n_threads=1)
+    oracle.align_workload(w, oracle.scoring(*scoring), idx=idx1, n_threads=1)
     dt1 = time.perf_counter() - t1
     return {"value": round(cells / dt / 1e9, 4), "unit": "GCUPS", "cores": threads,
             "kind": "oracle",
@@ -104,9 +126,14 @@ SERVE_QPS = 72000.0
 
 
 def serve_bench(args):
+    print(json.dumps(serve_run(args, args.qps if args.qps is not None else SERVE_QPS)), flush=True)
+
+
+def serve_run(args, qps):
     """Served workload: Poisson arrivals of requests of 1..4096 reads
     (log-uniform), reads 50-250 bp over a device-resident 100 Mbp genome.
-    With --qps 0 the requests all arrive at once, which measures capacity."""
+    With qps 0 the requests all arrive at once, which measures capacity.
+    Returns the JSON line as a dict."""
     import torch
     from paper_1302_5507_amd import binding, serving, workloads
     import oracle
@@ -119,7 +146,6 @@ def serve_bench(args):
     reqs = serving.requests_from_pool(pool, sizes)
     srv = serving.Server(gw, n_slots=args.slots, max_tasks=args.slot_tasks, max_n=250, max_m=410,
                          autotune=True, device_bytes=args.device_bytes)
-    qps = args.qps if args.qps is not None else SERVE_QPS
     # the whole schedule is submitted ahead; the server admits each request
     # at its arrival time (all at once when measuring capacity)
     arr, done, lag = serving.run_open_loop(srv, reqs, qps, seed=104)
@@ -189,7 +215,7 @@ def serve_bench(args):
         "server": {k: (round(v, 4) if isinstance(v, float) else v) for k, v in st.items()},
         "oracle_checked_requests": checked,
     }
-    print(json.dumps(line), flush=True)
+    return line
 
 
 MULTI_DESC = ("multi-candidate: 200,000 reads of 100 or 150 bp, 1 + Poisson(11) candidate "
@@ -351,11 +377,14 @@ def mate_bench(args):
     al.close()
 
 
-def time_form(al, dw, res, flags, steps, warmup):
+def time_form(al, dw, res, flags, steps, warmup, scoring):
+    """Warm up, then time `steps` calls back to back on the current stream:
+    (host seconds per call, mean device ms per call from HIP events on the
+    stream the library's work is enqueued on, host copy of the outputs)."""
     import torch
     stream = torch.cuda.current_stream()
     for _ in range(warmup):
-        al.align(dw, SCORING, flags=flags, res=res)
+        al.align(dw, scoring, flags=flags, res=res)
     torch.cuda.synchronize()
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
           for _ in range(steps)]
@@ -363,14 +392,79 @@ def time_form(al, dw, res, flags, steps, warmup):
     t0 = time.perf_counter()
     for k in range(steps):
         ev[k][0].record(stream)
-        al.align(dw, SCORING, flags=flags, res=res)
+        al.align(dw, scoring, flags=flags, res=res)
         ev[k][1].record(stream)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     out = res.to_host()
     assert (out["status"] != 1).all() and (out["status"] != 3).all(), "invalid tasks in bench"
-    time_form.redone = float(np.mean(out["status"] == 2))
-    return elapsed / steps, float(np.mean([a.elapsed_time(b) for a, b in ev]))
+    return elapsed / steps, float(np.mean([a.elapsed_time(b) for a, b in ev])), out
+
+
+def band_cells(w, out, scoring):
+    """Cells of the decision pass: each aligned task's read length times the
+    window rows [i0, end) that can hold an optimal alignment of score S,
+    i0 = max(0, end - n - Dmax), Dmax = 1 + (n S_MA + S_GO - S) // |S_GE|
+    (0 when negative); the whole window when S_GE = 0."""
+    ma, mi, go, ge = scoring
+    n = w.read_len.astype(np.int64)
+    ok = np.isin(out["status"], (0, 2))
+    S = out["score"].astype(np.int64)
+    e = out["ref_end"].astype(np.int64)
+    if ge == 0:
+        i0 = np.zeros_like(e)
+    else:
+        x = n * ma + go - S
+        dmax = np.where(x < 0, 0, 1 + np.maximum(x, 0) // (-ge))
+        i0 = np.maximum(0, e - n - dmax)
+    return int(np.sum(np.where(ok, n * (e - i0), 0)))
+
+
+def align_legs(args, al, w, forms, scoring, score_only=False, full_window=False):
+    """Time the requested forms on one workload.  Returns {form: summary}."""
+    from paper_1302_5507_amd import binding
+    dw = binding.DeviceWorkload(w)
+    extra = (binding.SCORE_ONLY if score_only else 0) | (binding.FULL_WINDOW if full_window else 0)
+    res = binding.DeviceResult(w.n_tasks, 0 if score_only else 2 * dw.max_n)
+    cells_t = w.read_len.astype(np.int64) * w.ref_len.astype(np.int64)
+    out = {}
+    for form in forms:
+        flags = (binding.BATCHED if form == "batched" else binding.PLAIN) | extra
+        s, k, host = time_form(al, dw, res, flags, args.steps, args.warmup, scoring)
+        redone = host["status"] == binding.TASK_OK_REDONE_INT32
+        if form == "plain":
+            peak, f32 = PEAK_INT32_TOPS, 1.0
+        else:
+            # int16 classes at the packed peak, re-run tasks at the int32 one,
+            # weighted by their share of the cells
+            f32 = float(cells_t[redone].sum() / max(cells_t.sum(), 1))
+            peak = 1.0 / ((1.0 - f32) / PEAK_INT16_TOPS + f32 / PEAK_INT32_TOPS)
+        if score_only:
+            ops, bc = OPS_PER_CELL_SCORE * w.cells, 0
+        elif full_window:
+            ops, bc = OPS_PER_CELL * w.cells, w.cells
+        else:
+            bc = band_cells(w, host, scoring)
+            ops = OPS_PER_CELL_SCORE * w.cells + OPS_PER_CELL * bc
+        achieved = ops / (k * 1e-3) / 1e12
+        d = {"gcups": round(w.cells / s / 1e9, 2), "ms_per_step": round(s * 1e3, 3),
+             "device_ms": round(k, 3), "achieved_tops": round(achieved, 3),
+             "ops_per_step": ops, "band_cells": bc,
+             "peak_tops": round(peak, 2), "valu_frac": round(achieved / peak, 4),
+             "redone_int32": round(float(redone.mean()), 4),
+             "int32_cell_share": round(f32, 4)}
+        if form == "batched":
+            lengths = sorted(set(int(x) for x in np.unique(w.read_len)))
+            shapes = {}
+            for prec, cap, lanes, cls_cells in al.classes():
+                hit = [n for n in lengths if n <= cap and not any(
+                    n <= c for p2, c, _, _ in al.classes() if p2 == prec and c < cap)]
+                if hit:
+                    shapes[f"i{prec}/{cap}"] = f"{lanes}x{cls_cells}"
+            d["shapes"] = shapes
+        out[form] = (s, k, d)
+    del dw, res
+    return out
 
 
 def main():
@@ -379,7 +473,9 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", choices=sorted(WORKLOADS) + ["config4", "multi", "mate"],
-                    default="config2")
+                    default="config5")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="default workload only: skip the uneven batch and the served leg")
     ap.add_argument("--ceiling", type=int, default=30, help="multi workload: candidates aligned per read")
     ap.add_argument("--cpu-reads", type=int, default=160_000, help="multi workload: oracle sample")
     ap.add_argument("--cpu-pairs", type=int, default=1_000_000, help="mate workload: oracle sample")
@@ -393,10 +489,14 @@ def main():
     ap.add_argument("--serve-warmup", type=int, default=1000)
     ap.add_argument("--serve-requests", type=int, default=20000)
     ap.add_argument("--form", choices=["plain", "batched", "both"], default="both")
-    ap.add_argument("--cpu-tasks", type=int, default=1_000_000)
+    ap.add_argument("--cpu-tasks", type=int, default=250_000,
+                    help="oracle sample: the first tasks of the workload (all threads)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--score-only", action="store_true",
                     help="score and end only (SOAP_DP_SCORE_ONLY), no traceback")
+    ap.add_argument("--full-window", action="store_true",
+                    help="one pass with decision bits over the whole window "
+                         "(SOAP_DP_FULL_WINDOW) instead of score pass + band pass")
     ap.add_argument("--score-scale", type=int, default=1,
                     help="multiply every score by K (the overflow runs: x100 on config3, "
                          "x128 on config5)")
@@ -433,37 +533,25 @@ def main():
     if args.workload == "mate":
         mate_bench(args)
         return
-    global SCORING
-    if args.score_scale != 1:
-        SCORING = tuple(args.score_scale * x for x in SCORING)
+    scoring = tuple(args.score_scale * x for x in SCORING)
     desc, gen, headline = WORKLOADS[args.workload]
+    print(f"bench: generating {args.workload}", file=sys.stderr, flush=True)
     w = getattr(workloads, gen)()
     al = binding.Aligner(0)
-    dw = binding.DeviceWorkload(w)
-    # --score-only: score and end of every task, no traceback (its own
-    # kernels and shapes); reported at 10 ops per cell
-    extra = binding.SCORE_ONLY if args.score_only else 0
-    ops = OPS_PER_CELL_SCORE if args.score_only else OPS_PER_CELL
-    res = binding.DeviceResult(w.n_tasks, 0 if args.score_only else 2 * dw.max_n)
-
-    forms = {}
-    if args.form in ("batched", "both"):
+    forms = ["batched", "plain"] if args.form == "both" else [args.form]
+    if "batched" in forms:
         al.autotune(args.tune_cache)
-        s, k = time_form(al, dw, res, binding.BATCHED | extra, args.steps, args.warmup)
-        forms["batched"] = (s, k)
-        redone = time_form.redone
-    if args.form in ("plain", "both"):
-        s, k = time_form(al, dw, res, binding.PLAIN | extra, args.steps, args.warmup)
-        forms["plain"] = (s, k)
-    main_form = headline if headline in forms else next(iter(forms))
-
-    def summary(form):
-        s, k = forms[form]
-        peak = PEAK_INT32_TOPS if form == "plain" else PEAK_INT16_TOPS
-        achieved = ops * w.cells / (k * 1e-3) / 1e12
-        return s, k, peak, achieved
-
-    s, k, peak, achieved = summary(main_form)
+    print(f"bench: timing {args.workload} ({', '.join(forms)})", file=sys.stderr, flush=True)
+    legs = align_legs(args, al, w, forms, scoring, args.score_only, args.full_window)
+    main_form = headline if headline in legs else forms[0]
+    s, k, d = legs[main_form]
+    if args.score_only:
+        ops_model = f"{OPS_PER_CELL_SCORE} per window cell"
+    elif args.full_window:
+        ops_model = f"{OPS_PER_CELL} per window cell"
+    else:
+        ops_model = (f"{OPS_PER_CELL_SCORE} per window cell (score pass) + {OPS_PER_CELL} per "
+                     f"band cell (decision pass)")
     line = {
         "metric": METRIC if not args.score_only else "GCUPS score only (no traceback), batched vs plain kernel",
         "value": round(w.cells / s / 1e9, 2),
@@ -478,38 +566,58 @@ def main():
         "dtype": "int32" if main_form == "plain" else "int16+int32",
         "data": "synthetic",
         "config": {"workload": desc, "form": main_form, "n_tasks": w.n_tasks, "cells": w.cells,
-                   "scoring": list(SCORING)},
+                   "scoring": list(scoring)},
         "roofline": {
             "bound": "alu",
-            "achieved": round(achieved, 3),
-            "peak": round(peak, 1),
+            "achieved": d["achieved_tops"],
+            "peak": round(d["peak_tops"], 1),
             "unit": "TOP/s",
-            "frac": round(achieved / peak, 4),
-            "traffic": None if args.score_only else traffic_bytes(args.workload, main_form),
-            "ops_per_cell": ops,
-            "kernel_ms": round(k, 3),
+            "frac": d["valu_frac"],
+            "traffic": None if args.score_only or args.full_window or args.score_scale != 1
+                       else traffic_bytes(args.workload, main_form),
+            "ops_model": ops_model,
+            "kernel_ms": d["device_ms"],
         },
-        "forms": {},
+        "forms": {f: v[2] for f, v in legs.items()},
     }
-    for form in forms:
-        fs, fk, fpeak, fach = summary(form)
-        line["forms"][form] = {"gcups": round(w.cells / fs / 1e9, 2), "ms_per_step": round(fs * 1e3, 3),
-                               "device_ms": round(fk, 3), "valu_frac": round(fach / fpeak, 4),
-                               "peak_tops": round(fpeak, 1)}
-    if "batched" in forms:
-        lengths = sorted(set(int(x) for x in np.unique(w.read_len)))
-        shapes = {}
-        for prec, cap, lanes, cells in al.classes():
-            hit = [n for n in lengths if n <= cap and not any(n <= c for p2, c, _, _ in al.classes()
-                                                                if p2 == prec and c < cap)]
-            if prec == 16 and hit:
-                shapes[str(cap)] = f"{lanes}x{cells}"
-        line["forms"]["batched"]["shapes"] = shapes
-        line["forms"]["batched"]["redone_int32"] = round(redone, 4)
+    default_run = not (args.score_only or args.full_window or args.score_scale != 1)
+    issue = valu_issue_frac(args.workload, main_form, d["device_ms"])
+    if issue is not None and default_run:
+        line["roofline"]["valu_issue_frac"] = issue
+    for f in legs:
+        fi = valu_issue_frac(args.workload, f, legs[f][2]["device_ms"])
+        if fi is not None and default_run:
+            line["forms"][f]["valu_issue_frac"] = fi
+    if args.workload == "config5" and not args.no_extra and default_run:
+        del w
+        print("bench: generating config3", file=sys.stderr, flush=True)
+        w3 = workloads.config3()
+        print("bench: timing config3", file=sys.stderr, flush=True)
+        legs3 = align_legs(args, al, w3, forms, scoring)
+        line["uneven"] = {"workload": WORKLOADS["config3"][0], "cells": w3.cells,
+                          "forms": {f: v[2] for f, v in legs3.items()}}
+        del w3
+        al.close()
+        al = None
+        torch.cuda.empty_cache()
+        print(f"bench: served leg at {SERVE_QPS:.0f} requests/s", file=sys.stderr, flush=True)
+        sv = serve_run(args, SERVE_QPS)
+        line["served"] = {"workload": sv["config"]["workload"], "qps": SERVE_QPS,
+                          "gcups": sv["value"], "latency_ms": sv["latency_ms"],
+                          "latency_phases_ms": sv["latency_phases_ms"],
+                          "achieved_qps": sv["achieved_qps"],
+                          "slots": sv["config"]["slots"], "slot_tasks": sv["config"]["slot_tasks"],
+                          "requests": sv["steps"],
+                          "oracle_checked_requests": sv["oracle_checked_requests"]}
+        line["latency_ms"] = {"p50": sv["latency_ms"]["p50"], "p99": sv["latency_ms"]["p99"],
+                              "qps": SERVE_QPS}
+        w = getattr(workloads, gen)()
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(w, args.cpu_tasks)
+        print("bench: oracle sample on the host", file=sys.stderr, flush=True)
+        line["cpu_baseline"] = cpu_baseline(w, args.cpu_tasks, scoring)
     print(json.dumps(line), flush=True)
-    al.close()
+    if al is not None:
+        al.close()
 
 
 if __name__ == "__main__":
