@@ -145,7 +145,8 @@ def serve_run(args, qps):
     sizes = workloads.request_sizes(n_total, seed=104)
     reqs = serving.requests_from_pool(pool, sizes)
     srv = serving.Server(gw, n_slots=args.slots, max_tasks=args.slot_tasks, max_n=250, max_m=410,
-                         autotune=True, device_bytes=args.device_bytes)
+                         autotune=True, device_bytes=args.device_bytes,
+                         align_flags=binding.FULL_WINDOW if args.serve_one_pass else 0)
     # the whole schedule is submitted ahead; the server admits each request
     # at its arrival time (all at once when measuring capacity)
     arr, done, lag = serving.run_open_loop(srv, reqs, qps, seed=104)
@@ -204,6 +205,7 @@ def serve_run(args, qps):
         "config": {"workload": "served: Poisson arrivals of 1-4096-read requests (log-uniform), "
                                "reads 50-250 bp vs n+160 windows in a resident 100 Mbp genome",
                    "qps": qps if qps > 0 else "saturation", "slots": args.slots,
+                   "passes": 1 if args.serve_one_pass else 2,
                    "slot_tasks": args.slot_tasks,
                    "requests": args.serve_requests, "mean_cells_per_request": round(mean_cells)},
         "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3),
@@ -486,6 +488,8 @@ def main():
     ap.add_argument("--device-bytes", type=int, default=0,
                     help="served workload: device memory the batches in flight share (0: one "
                          "full batch per slot)")
+    ap.add_argument("--serve-one-pass", action="store_true",
+                    help="served workload: one pass per batch (SOAP_DP_FULL_WINDOW)")
     ap.add_argument("--serve-warmup", type=int, default=1000)
     ap.add_argument("--serve-requests", type=int, default=20000)
     ap.add_argument("--form", choices=["plain", "batched", "both"], default="both")

@@ -418,6 +418,9 @@ typedef struct {
                                   slots; 0: room for n_slots batches at the slot limits.
                                   It must hold at least one batch of one largest request;
                                   the contexts' decision scratch is reserved apart from it */
+  uint32_t align_flags;        /* OR-ed into every batch's SOAP_DP_BATCHED call: 0 or
+                                  SOAP_DP_FULL_WINDOW (one pass per batch); other bits are
+                                  SOAP_DP_EINVAL */
 } soap_dp_server_config;
 
 /* HOST results of one served request.  CIGARs are packed: task t's runs

@@ -47,6 +47,22 @@ Shape shape_of(const ClassSpec &c, bool score) {
   return score && c.score_shape.lanes ? c.score_shape : c.shape;
 }
 
+// What the class kernels of one batched call compute: everything, score and
+// end only, or -- the first pass of a two-pass call -- per class: score and
+// end where the windows are long against the class's reads (the band pass
+// will then trace back over a fraction of them), everything where they are
+// not (the band would cover most of the window, so one pass is cheaper).
+enum Mode { kModeFull = 0, kModeScore = 1, kModeMixed = 2 };
+// A class takes two passes when the batch's windows reach this many times
+// its longest read.  The score pass costs about half a decision pass per
+// cell, so two passes pay off while the band is under about half the
+// window; with the band about n + a few dozen rows, that is m >= 3 n or so.
+constexpr int32_t kBandRatio = 3;
+
+bool class_score(const ClassSpec &c, int32_t max_m, Mode mode) {
+  return mode == kModeScore || (mode == kModeMixed && int64_t(max_m) >= int64_t(kBandRatio) * c.cap);
+}
+
 // Default classes: int16 in the offset form by ascending capacity, the same
 // capacities and shapes in the direct form (tasks the offset form's range
 // rule excludes), then the int32 classes for tasks neither int16 form
@@ -250,7 +266,11 @@ uint64_t slot_dwords(int prec, Shape s, int32_t max_m) {
 
 // Plain form: the compiled int32 shape covering max_n with the least work
 // per task (columns times sweep steps, the anti-diagonal skew included).
-Shape plain_shape(int32_t max_n, int32_t max_m) {
+// Kernels with decision bits keep to at most 25 columns per lane (their
+// decision words and staging grow with the columns); the score-only
+// kernels may take the wider strips, which spread each step's fixed work
+// (neighbour shifts, table, end tracking) over more columns.
+Shape plain_shape(int32_t max_n, int32_t max_m, bool score = false) {
   int cnt = 0;
   const Shape *all = shapes_i32(&cnt);
   Shape best{0, 0};
@@ -259,6 +279,7 @@ Shape plain_shape(int32_t max_n, int32_t max_m) {
     const Shape s = all[k];
     if (s.lanes * s.cells < max_n) continue;
     if (s.lanes == 1 && max_n > 8) continue;
+    if (!score && s.cells > 25) continue;
     const double cost = double(s.lanes) * s.cells * double(max_m + s.lanes - 1);
     if (best.lanes == 0 || cost < best_cost) { best = s; best_cost = cost; }
   }
@@ -433,7 +454,7 @@ BucketBuffers bucket_buffers(const soap_dp_ctx *ctx) {
 
 size_t plain_scratch_bytes(const soap_dp_ctx *ctx, int64_t n_tasks, int32_t max_n, int32_t max_m,
                            Kind k) {
-  const Shape s = plain_shape(max_n, max_m);
+  const Shape s = plain_shape(max_n, max_m, k.score);
   if (s.lanes == 0) return 0;
   return plan_launch(ctx, 32, s, n_tasks, max_m, k, kScratchCap).bytes();
 }
@@ -441,7 +462,7 @@ size_t plain_scratch_bytes(const soap_dp_ctx *ctx, int64_t n_tasks, int32_t max_
 int align_plain(soap_dp_ctx *ctx, const soap_dp_batch *in, const soap_dp_scoring *sc,
                 const soap_dp_result *out, hipStream_t stream, bool score,
                 const int32_t *order = nullptr) {
-  const Shape s = plain_shape(in->max_n, in->max_m);
+  const Shape s = plain_shape(in->max_n, in->max_m, score);
   if (s.lanes == 0) return SOAP_DP_EINVAL;
   const LaunchPlan q = plan_launch(ctx, 32, s, in->n_tasks, in->max_m, kind_for(sc, score), kScratchCap);
   const int rc = ensure_scratch(ctx, q.bytes());
@@ -472,7 +493,7 @@ int align_plain(soap_dp_ctx *ctx, const soap_dp_batch *in, const soap_dp_scoring
 // read up to max_n.  The int32 re-run of flagged tasks is not a class (see
 // enqueue_batched).
 std::vector<int> live_classes(const soap_dp_ctx *ctx, int32_t max_n, int32_t max_m,
-                              const soap_dp_scoring *sc, bool score) {
+                              const soap_dp_scoring *sc, Mode mode) {
   std::vector<int> live;
   const int32_t ma = sc->match, mi = sc->mismatch, go = sc->gap_open, ge = sc->gap_extend;
   bool need32 = false;
@@ -484,7 +505,7 @@ std::vector<int> live_classes(const soap_dp_ctx *ctx, int32_t max_n, int32_t max
     if (prev16 < max_n) {
       live.push_back(int(k));
       const int32_t n_hi = std::min(c.cap, max_n);
-      const Shape sh = shape_of(c, score);
+      const Shape sh = shape_of(c, class_score(c, max_m, mode));
       if (!int16_fits(n_hi, max_m, sh.lanes * sh.cells, ma, mi, go, ge)) {
         if (int16_direct_fits(prev16 + 1, ma, mi, go, ge)) direct_caps.push_back(c.cap);
         if (!int16_direct_fits(n_hi, ma, mi, go, ge)) need32 = true;
@@ -528,31 +549,36 @@ bool any_direct(const soap_dp_ctx *ctx, const std::vector<int> &live) {
 // bounds and reuses the scratch from its start (the class kernels are done
 // by then), at deferral 1; the budget holds its full grid of slots too.
 struct BatchedPlan {
-  bool score = false;   // score-only kernels: no decision scratch
+  std::vector<char> cls_score;   // per class: score-only kernel (no decision scratch)
   std::vector<int> grids;
   uint64_t budget_dwords = 0;
   bool redo = false;
+  bool redo_score = false;
   Shape redo_shape{0, 0};
   LaunchPlan redo_plan;
   size_t bytes() const { return size_t(budget_dwords + 64 * kMaxClasses) * 4; }
 };
 
 BatchedPlan batched_plan(const soap_dp_ctx *ctx, int64_t n_tasks, int32_t max_n, int32_t max_m,
-                         Kind k, const std::vector<int> &live, bool redo) {
+                         Variant v, Mode mode, const std::vector<int> &live, bool redo) {
   BatchedPlan bp;
-  bp.score = k.score;
+  for (const ClassSpec &c : ctx->classes) bp.cls_score.push_back(class_score(c, max_m, mode));
   uint64_t need = 0, want = 0;
   for (int cls : live) {
     const ClassSpec &c = ctx->classes[size_t(cls)];
+    const Kind k{v, bp.cls_score[size_t(cls)] != 0};
     const LaunchPlan q = plan_launch(ctx, c.prec, shape_of(c, k.score), n_tasks, max_m, k, SIZE_MAX);
     bp.grids.push_back(q.grid);
     need += round64(uint64_t(q.grid) * q.slot_dwords);
     want += round64(uint64_t(q.grid) * uint64_t(q.defer) * q.slot_dwords);
   }
   bp.redo = redo;
+  // the re-run traces back unless every class of the call is score-only
+  bp.redo_score = mode == kModeScore;
   if (redo) {
     bp.redo_shape = plain_shape(max_n, max_m);
-    bp.redo_plan = plan_launch(ctx, kPrecI32, bp.redo_shape, n_tasks, max_m, k, 0);
+    bp.redo_plan = plan_launch(ctx, kPrecI32, bp.redo_shape, n_tasks, max_m,
+                               Kind{v, bp.redo_score}, 0);
     bp.redo_plan.defer = 1;
     need = std::max<uint64_t>(need, round64(uint64_t(bp.redo_plan.grid) * bp.redo_plan.slot_dwords));
   }
@@ -562,7 +588,8 @@ BatchedPlan batched_plan(const soap_dp_ctx *ctx, int64_t n_tasks, int32_t max_n,
 
 size_t batched_scratch_bytes(const soap_dp_ctx *ctx, int64_t n_tasks, int32_t max_n, int32_t max_m,
                              Kind k, const std::vector<int> &live, bool redo) {
-  return batched_plan(ctx, n_tasks, max_n, max_m, k, live, redo).bytes();
+  return batched_plan(ctx, n_tasks, max_n, max_m, k.v, k.score ? kModeScore : kModeFull, live, redo)
+      .bytes();
 }
 
 int ensure_class_streams(soap_dp_ctx *ctx, size_t n) {
@@ -590,7 +617,8 @@ ClassTable class_table(const soap_dp_ctx *ctx, const std::vector<int> &live,
   ct.count = int32_t(ctx->classes.size());
   for (size_t k = 0; k < ctx->classes.size(); ++k) {
     const ClassSpec &c = ctx->classes[k];
-    const Shape sh = shape_of(c, bp.score);
+    const bool score = bp.cls_score[k] != 0;
+    const Shape sh = shape_of(c, score);
     ct.cap[k] = c.cap;
     ct.cols[k] = sh.lanes * sh.cells;
     ct.prec[k] = c.prec;
@@ -600,8 +628,8 @@ ClassTable class_table(const soap_dp_ctx *ctx, const std::vector<int> &live,
     ct.lanes[k] = sh.lanes;
     ct.step_block[k] = step_block(sh.cells);
     ct.step_dwords[k] =
-        bp.score ? 0 : int32_t(uint64_t((sh.cells + 7) / 8) * kWave * (packed16(c.prec) ? 2 : 1));
-    if (bp.score) ct.max_defer[k] = 1;
+        score ? 0 : int32_t(uint64_t((sh.cells + 7) / 8) * kWave * (packed16(c.prec) ? 2 : 1));
+    if (score) ct.max_defer[k] = 1;
   }
   for (size_t li = 0; li < live.size(); ++li) ct.grid[live[li]] = bp.grids[li];
   ct.budget_dwords = bp.budget_dwords;
@@ -642,8 +670,9 @@ hipError_t enqueue_batched(soap_dp_ctx *ctx, const soap_dp_batch *in, const soap
     q.slot_dwords_dev = b.slot_dwords + k;
     q.scratch_off_dev = b.scratch_off + k;
     q.ok_status = packed16(c.prec) ? kTaskOk : kTaskRedone;
-    q.score_only = bp.score;
-    if ((e = launch_shape(c.prec, shape_of(c, bp.score), bp.grids[li], cs, q)) != hipSuccess) return e;
+    q.score_only = bp.cls_score[size_t(k)];
+    if ((e = launch_shape(c.prec, shape_of(c, q.score_only != 0), bp.grids[li], cs, q)) != hipSuccess)
+      return e;
     if ((e = hipEventRecord(ctx->join_events[li], cs)) != hipSuccess) return e;
     if ((e = hipStreamWaitEvent(stream, ctx->join_events[li], 0)) != hipSuccess) return e;
   }
@@ -658,22 +687,23 @@ hipError_t enqueue_batched(soap_dp_ctx *ctx, const soap_dp_batch *in, const soap
     q.defer = 1;
     q.slot_dwords = bp.redo_plan.slot_dwords;
     q.ok_status = kTaskRedone;
-    q.score_only = bp.score;
+    q.score_only = bp.redo_score;
     if ((e = launch_dp_i32(bp.redo_shape, bp.redo_plan.grid, stream, q)) != hipSuccess) return e;
   }
   return hipSuccess;
 }
 
 int align_batched(soap_dp_ctx *ctx, const soap_dp_batch *in, const soap_dp_scoring *sc,
-                  const soap_dp_result *out, hipStream_t stream, bool score,
+                  const soap_dp_result *out, hipStream_t stream, Mode mode,
                   const int32_t *order = nullptr) {
-  const std::vector<int> live = live_classes(ctx, in->max_n, in->max_m, sc, score);
+  const std::vector<int> live = live_classes(ctx, in->max_n, in->max_m, sc, mode);
   int rc = ensure_task_buffers(ctx, in->n_tasks);
   if (rc) return rc;
   rc = ensure_class_streams(ctx, live.size());
   if (rc) return rc;
-  const BatchedPlan bp = batched_plan(ctx, in->n_tasks, in->max_n, in->max_m, kind_for(sc, score),
-                                      live, any_direct(ctx, live));
+  const BatchedPlan bp = batched_plan(ctx, in->n_tasks, in->max_n, in->max_m,
+                                      kind_for(sc, mode == kModeScore).v, mode, live,
+                                      any_direct(ctx, live));
   rc = ensure_scratch(ctx, bp.bytes());
   if (rc) return rc;
   if (!ctx->use_graphs || ctx->frozen) {
@@ -687,7 +717,7 @@ int align_batched(soap_dp_ctx *ctx, const soap_dp_batch *in, const soap_dp_scori
   key.out = *out;
   key.order = order;
   key.epoch = ctx->epoch;
-  key.flags = score ? SOAP_DP_SCORE_ONLY : 0u;
+  key.flags = uint32_t(mode);
   GraphEntry *hit = nullptr;
   for (auto &g : ctx->graphs)
     if (same_key(g.key, key)) { hit = &g; break; }
@@ -1071,8 +1101,11 @@ int align_two_pass(soap_dp_ctx *ctx, const soap_dp_batch *in, const soap_dp_scor
   if (rc) return rc;
   BandWork w{};
   band_layout(in->n_tasks, static_cast<char *>(ctx->band), &w);
-  const soap_dp_result r1{w.p_score, w.p_begin, w.p_end, nullptr, 0, w.p_clen, w.p_status};
-  rc = batched ? align_batched(ctx, in, sc, &r1, stream, true)
+  // pass 1: score and end (batched form: per class, where two passes pay;
+  // the other classes trace back into the caller's CIGAR rows already)
+  const soap_dp_result r1{w.p_score, w.p_begin, w.p_end, out->cigar, out->cigar_stride, w.p_clen,
+                          w.p_status};
+  rc = batched ? align_batched(ctx, in, sc, &r1, stream, kModeMixed)
                : align_plain(ctx, in, sc, &r1, stream, true);
   if (rc) return rc;
   const BandIn bi{in->ref_base_off, in->read_len, in->ref_len, in->n_tasks, in->max_m,
@@ -1084,7 +1117,7 @@ int align_two_pass(soap_dp_ctx *ctx, const soap_dp_batch *in, const soap_dp_scor
   s2.min_score = INT32_MIN;
   const soap_dp_batch b2{in->read_codes, in->read_word_off, in->read_len, in->ref_codes, w.b_rbo,
                          w.b_ml, in->n_tasks, in->max_n, in->max_m, in->read_words, in->ref_words};
-  rc = batched ? align_batched(ctx, &b2, &s2, out, stream, false, w.order)
+  rc = batched ? align_batched(ctx, &b2, &s2, out, stream, kModeFull, w.order)
                : align_plain(ctx, &b2, &s2, out, stream, false, w.order);
   if (rc) return rc;
   const BandOut bo{out->score, out->ref_begin, out->ref_end, out->cigar_len, out->status};
@@ -1099,7 +1132,7 @@ int align_dispatch(soap_dp_ctx *ctx, const soap_dp_batch *in, const soap_dp_scor
   const bool score = (flags & SOAP_DP_SCORE_ONLY) != 0;
   if (!score && (flags & SOAP_DP_FULL_WINDOW) == 0)
     return align_two_pass(ctx, in, sc, out, stream, batched);
-  return batched ? align_batched(ctx, in, sc, out, stream, score)
+  return batched ? align_batched(ctx, in, sc, out, stream, score ? kModeScore : kModeFull)
                  : align_plain(ctx, in, sc, out, stream, score);
 }
 
@@ -1110,8 +1143,8 @@ std::vector<int> reserve_classes(const soap_dp_ctx *ctx, int32_t max_n, int32_t 
                                  const soap_dp_scoring *sc, bool *redo) {
   std::vector<int> live;
   if (sc) {
-    for (bool score : {false, true})
-      for (int k : live_classes(ctx, max_n, max_m, sc, score))
+    for (Mode mode : {kModeFull, kModeScore})
+      for (int k : live_classes(ctx, max_n, max_m, sc, mode))
         if (std::find(live.begin(), live.end(), k) == live.end()) live.push_back(k);
     *redo = any_direct(ctx, live);
     return live;
@@ -1275,14 +1308,14 @@ int soap_dp_align_multi(soap_dp_ctx *ctx, const soap_dp_multi_batch *in, const s
                          T, in->max_n, in->max_m, 2 * in->read_words, in->ref_words};
   const soap_dp_result r1{w.p_score, w.p_begin, w.p_end, nullptr, 0, w.p_clen, w.p_status};
   const soap_dp_scoring es = effective_scoring(sc, 0);   // no cutoff here
-  if (T > 0 && (rc = align_batched(ctx, &b1, &es, &r1, st, true)) != SOAP_DP_OK) return rc;
+  if (T > 0 && (rc = align_batched(ctx, &b1, &es, &r1, st, kModeScore)) != SOAP_DP_OK) return rc;
   if ((e = launch_reduce(mi, w, mo, st)) != hipSuccess) return hip_fail(ctx, e);
   // each read's best pair again, with traceback, into the caller's outputs
   const soap_dp_batch b2{w.reads2, w.f_rwo, w.f_rl, in->ref_codes, w.f_rbo, w.f_ml,
                          in->n_reads, in->max_n, in->max_m, 2 * in->read_words, in->ref_words};
   const soap_dp_result r2{out->score, out->ref_begin, out->ref_end, out->cigar, out->cigar_stride,
                           out->cigar_len, out->status};
-  rc = align_batched(ctx, &b2, &es, &r2, st, false);
+  rc = align_batched(ctx, &b2, &es, &r2, st, kModeFull);
   if (rc) return rc;
   if ((e = launch_fixup(mi, w, mo, st)) != hipSuccess) return hip_fail(ctx, e);
   return SOAP_DP_OK;

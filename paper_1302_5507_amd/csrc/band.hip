@@ -18,8 +18,9 @@ __global__ void band_zero_kernel(int32_t *bins) {
 }
 
 // One thread per task: the rows [i0, e) that can hold an optimal alignment
-// of a task pass 1 aligned; a task pass 1 left final (invalid, below the
-// score threshold) gets an empty window and is restored by the fixup.
+// of a task pass 1 scored; a task pass 1 left final (invalid, below the
+// score threshold, or traced back already: ref_begin >= 0) gets an empty
+// window and is restored by the fixup.
 __global__ __launch_bounds__(kBlock) void band_kernel(BandIn in, BandWork w) {
   __shared__ int32_t s_cnt[kBandBins];
   for (int k = threadIdx.x; k < kBandBins; k += kBlock) s_cnt[k] = 0;
@@ -29,7 +30,7 @@ __global__ __launch_bounds__(kBlock) void band_kernel(BandIn in, BandWork w) {
     const uint8_t st = w.p_status[t];
     uint64_t rbo = in.ref_base_off[t];
     int32_t len = 0, i0 = -1;
-    if (st == kTaskOk || st == kTaskRedone) {
+    if ((st == kTaskOk || st == kTaskRedone) && w.p_begin[t] < 0) {
       const int64_t n = in.read_len[t], S = w.p_score[t], e = w.p_end[t];
       int64_t lo = 0;
       if (in.ge < 0) {

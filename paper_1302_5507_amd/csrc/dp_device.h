@@ -233,10 +233,10 @@ __device__ __forceinline__ int64_t task_at(const DpParams &p, const int32_t *lis
 }
 
 // The read words covering columns q0 .. q0+K-1 of a lane's strip (q = 0-based
-// read index; negative q lie left of the read).  A strip of K <= 32 columns
-// spans at most three words.  Loads stay inside the read's own words.
+// read index; negative q lie left of the read).  A strip of K <= 48 columns
+// spans at most four words.  Loads stay inside the read's own words.
 struct StripWords {
-  uint32_t w0, w1, w2;
+  uint32_t w0, w1, w2, w3;
   int32_t base;  // word index of w0
   __device__ __forceinline__ void load(const uint32_t *codes, uint64_t first_word, int32_t n,
                                        int32_t q0) {
@@ -245,14 +245,16 @@ struct StripWords {
     const int32_t i0 = base < last ? base : last;
     const int32_t i1 = base + 1 < last ? base + 1 : last;
     const int32_t i2 = base + 2 < last ? base + 2 : last;
+    const int32_t i3 = base + 3 < last ? base + 3 : last;
     w0 = codes[first_word + (uint64_t)i0];
     w1 = codes[first_word + (uint64_t)i1];
     w2 = codes[first_word + (uint64_t)i2];
+    w3 = codes[first_word + (uint64_t)i3];
   }
   // code of read index q (0 <= q < n)
   __device__ __forceinline__ uint32_t code(int32_t q) const {
     const int32_t k = (q >> 4) - base;
-    const uint32_t w = k == 0 ? w0 : (k == 1 ? w1 : w2);
+    const uint32_t w = k == 0 ? w0 : (k == 1 ? w1 : (k == 2 ? w2 : w3));
     return (w >> ((q & 15) * 2)) & 3u;
   }
 };

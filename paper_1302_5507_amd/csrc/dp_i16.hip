@@ -269,6 +269,10 @@ void dp_i16_kernel(DpParams p) {
           // gap extension: free in the offset form, + S_GE in the direct form
           el = max16(ai, kDirect ? add16(el, c_ge) : el);
           const uint32_t f = max16(ad, kDirect ? add16(F[c], c_ge) : F[c]);
+          // score-only: the old H[c] is dead once the next diagonal and the
+          // D-open candidate are formed; keeping the rest below lets the new
+          // G take its register (otherwise it costs a copy per column pair)
+          if constexpr (kScore) __builtin_amdgcn_sched_barrier(0);
           const uint32_t hv = max16(max16(diag, el), f);
           // differences against the maxima, so the old I and D die at the max
           // and the new values take their registers
@@ -286,13 +290,13 @@ void dp_i16_kernel(DpParams p) {
           }
           H[c] = add16(hv, c_go);
           F[c] = f;
-          hl = H[c];
           diag = diag_next;
           // keep each column's decisions next to its scores: without this the
           // optimiser sinks them below all columns and every column's
           // candidates stay live (bounds live registers)
           if constexpr (!kScore) asm volatile("" : "+v"(accA[c / 8]), "+v"(accB[c / 8]));
           else asm volatile("" : "+v"(H[c]));
+          hl = H[c];   // read after the asm above, so it is the register H[c] holds
           __builtin_amdgcn_sched_barrier(0);
         }
         hl_out = hl;
@@ -397,7 +401,7 @@ void dp_i16_kernel(DpParams p) {
 #define SOAPDP_I16_SHAPES(X)                                                            \
   X(2, 8) X(4, 4) X(4, 8) X(2, 16) X(4, 10) X(8, 5) X(4, 14) X(8, 7) X(4, 16) X(8, 8)   \
   X(4, 20) X(8, 10) X(8, 13) X(4, 26) X(16, 7) X(8, 16) X(4, 32) X(16, 8) X(8, 19)      \
-  X(16, 10) X(8, 24)                                                                    \
+  X(16, 10) X(8, 24) X(4, 38) X(8, 32)                                                  \
   X(16, 12) X(16, 16) X(32, 8) X(16, 20) X(32, 10) X(16, 24) X(32, 12) X(32, 16) X(64, 8)
 
 static const Shape kShapesI16[] = {

@@ -216,6 +216,10 @@ void dp_i32_kernel(DpParams p) {
           const int32_t ai = hl;     // G of the cell to the left: I-open candidate
           el = max(ai, el);
           const int32_t f = max(ad, F[c]);
+          // score-only: the old H[c] is dead once the next diagonal and the
+          // D-open candidate are formed; keeping the rest below lets the new
+          // G take its register (otherwise it costs a copy per column)
+          if constexpr (kScore) __builtin_amdgcn_sched_barrier(0);
           const int32_t h = max(max(diag, el), f);
           if constexpr (!kScore) {
             uint32_t a = acc[c / 8];
@@ -227,13 +231,13 @@ void dp_i32_kernel(DpParams p) {
           }
           H[c] = h + c_go;
           F[c] = f;
-          hl = H[c];
           diag = diag_next;
           // keep each column's decisions next to its scores: without this the
           // optimiser sinks them below all columns and every column's
           // candidates stay live (bounds live registers)
           if constexpr (!kScore) asm volatile("" : "+v"(acc[c / 8]));
           else asm volatile("" : "+v"(H[c]));
+          hl = H[c];   // read after the asm above, so it is the register H[c] holds
           __builtin_amdgcn_sched_barrier(0);
         }
         if constexpr (!kScore)
@@ -305,8 +309,8 @@ void dp_i32_kernel(DpParams p) {
 // ---------------------------------------------------------------- dispatch
 
 #define SOAPDP_I32_SHAPES(X) \
-  X(1, 8) X(2, 8) X(4, 9) X(4, 13) X(4, 19) X(4, 25) X(8, 7) X(8, 10) X(8, 13) X(8, 19) \
-  X(16, 10) X(16, 16) X(32, 16) X(64, 8)
+  X(1, 8) X(2, 8) X(4, 9) X(4, 13) X(4, 19) X(4, 25) X(4, 38) X(8, 7) X(8, 10) X(8, 13) \
+  X(8, 19) X(8, 32) X(16, 10) X(16, 16) X(32, 16) X(64, 8)
 
 static const Shape kShapesI32[] = {
 #define X(l, k) {l, k},

@@ -202,7 +202,7 @@ int enqueue_batch(soap_dp_server *srv, Slot &s, int32_t nt, uint64_t nw) {
   out.cigar = d.cigar;
   out.cigar_stride = S;
   out.status = d.status;
-  const int rc = soap_dp_align_batch(s.ctx, &in, &c.scoring, &out, st, SOAP_DP_BATCHED);
+  const int rc = soap_dp_align_batch(s.ctx, &in, &c.scoring, &out, st, SOAP_DP_BATCHED | c.align_flags);
   if (rc) return rc;
   ok = soapdp::launch_gather_cigar_head(d.cigar, S, out.cigar_len, nt, d.head, st) == hipSuccess &&
        soapdp::launch_pack_cigar_rest(d.cigar, S, out.cigar_len, nt, soapdp::kCigarHeadWords,
@@ -423,7 +423,8 @@ int soap_dp_server_create(soap_dp_server **out, const soap_dp_server_config *cfg
   *out = nullptr;
   if (cfg->n_slots < 1 || cfg->n_slots > kMaxSlots || cfg->max_tasks < 1 || cfg->max_read_words < 1 ||
       cfg->max_n < 1 || cfg->max_n > SOAP_DP_MAX_READ || cfg->max_m < 1 ||
-      cfg->max_m > SOAP_DP_MAX_WINDOW || !cfg->genome || cfg->genome_words == 0)
+      cfg->max_m > SOAP_DP_MAX_WINDOW || !cfg->genome || cfg->genome_words == 0 ||
+      (cfg->align_flags & ~SOAP_DP_FULL_WINDOW) != 0)
     return SOAP_DP_EINVAL;
   auto *srv = new (std::nothrow) soap_dp_server();
   if (!srv) return SOAP_DP_ENOMEM;
@@ -465,7 +466,7 @@ int soap_dp_server_create(soap_dp_server **out, const soap_dp_server_config *cfg
   }
   for (size_t k = 0; k < srv->slots.size() && !rc; ++k)
     rc = soapdp::ctx_reserve_for(srv->slots[k].ctx, cfg->max_tasks, cfg->max_n, cfg->max_m,
-                                 SOAP_DP_BATCHED, &cfg->scoring);
+                                 SOAP_DP_BATCHED | cfg->align_flags, &cfg->scoring);
   for (size_t k = 0; k < srv->slots.size() && !rc; ++k) {
     soapdp::ctx_set_frozen(srv->slots[k].ctx, true);
     rc = warm_up(srv, srv->slots[k]);

@@ -22,7 +22,7 @@ class ServerConfig(ctypes.Structure):
                 ("max_tasks", ctypes.c_int32), ("max_read_words", ctypes.c_int64),
                 ("max_n", ctypes.c_int32), ("max_m", ctypes.c_int32), ("scoring", Scoring),
                 ("genome", vp), ("genome_words", ctypes.c_uint64), ("autotune", ctypes.c_int),
-                ("device_bytes", ctypes.c_uint64)]
+                ("device_bytes", ctypes.c_uint64), ("align_flags", ctypes.c_uint32)]
 
 
 class HostResult(ctypes.Structure):
@@ -137,17 +137,19 @@ class HostRequest:
 class Server:
     def __init__(self, genome_words, n_slots=4, max_tasks=16384, max_read_words=None, max_n=250,
                  max_m=410, scoring=(1, -3, -5, -2), autotune=True, device_ordinal=0,
-                 device_bytes=0):
+                 device_bytes=0, align_flags=0):
         """``genome_words``: a device tensor (int32/uint32 view) holding the
         packed genome; it must stay alive while the server runs.
         ``device_bytes``: device memory the batches in flight share (0: room
-        for ``n_slots`` full batches)."""
+        for ``n_slots`` full batches).  ``align_flags``: 0 or
+        binding.FULL_WINDOW (one pass per batch instead of score pass + band
+        pass)."""
         self.genome = genome_words
         if max_read_words is None:
             max_read_words = max_tasks * ((max_n + 15) // 16)
         cfg = ServerConfig(device_ordinal, n_slots, max_tasks, max_read_words, max_n, max_m,
                            Scoring(*scoring), genome_words.data_ptr(), genome_words.numel(),
-                           int(bool(autotune)), int(device_bytes))
+                           int(bool(autotune)), int(device_bytes), int(align_flags))
         h = vp()
         rc = _lib().soap_dp_server_create(ctypes.byref(h), ctypes.byref(cfg))
         if rc != 0:

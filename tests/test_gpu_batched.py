@@ -255,6 +255,40 @@ def test_every_int16_shape(al):
             al.set_class_shape(prec, cap, lanes, cells)
 
 
+def test_every_int32_shape(al):
+    """Force each compiled int32 shape onto the int32 class it can serve and
+    check reads spanning that class, full and score-only.  The scoring
+    (300, -1, -5, -2) fits neither int16 form (its match constant is no byte
+    in the offset form, and 301 steps of 1 in the direct form), so every
+    read runs in the int32 classes."""
+    sc = (300, -1, -5, -2)
+    assert not _direct_fits(1, sc) and not _int16_fits(1, 1, 8, sc)
+    defaults = al.classes()
+    caps32 = [c[1] for c in defaults if c[0] == 32]
+    rng = np.random.default_rng(14)
+    try:
+        for prec, cols, lanes, cells in binding.soap_dp_list_shapes(32):
+            cap = max([c for c in caps32 if c <= cols], default=None)
+            if cap is None:
+                continue
+            prev = max([c for c in caps32 if c < cap], default=0)
+            al.set_class_shape(32, cap, lanes, cells)
+            w = workloads.random_tasks(rng, 300, n_range=(prev + 1, cap), m_range=(1, 400),
+                                       genome_len=20000)
+            g = run(al, w, sc, max_n=cap)
+            assert (g["status"] == binding.TASK_OK_REDONE_INT32).all()
+            ref = oracle_align(w, sc, stride=2 * cap)
+            assert_same(as_oracle_status(g), ref, label=f"int32 shape {lanes}x{cells} in class {cap}")
+            gs = run(al, w, sc, flags=binding.BATCHED | binding.SCORE_ONLY, max_n=cap)
+            for f in ("score", "ref_end"):
+                assert np.array_equal(gs[f], getattr(ref, f)), (f, lanes, cells)
+            d = [c for c in defaults if c[0] == 32 and c[1] == cap][0]
+            al.set_class_shape(32, cap, d[2], d[3])
+    finally:
+        for prec, cap, lanes, cells in defaults:
+            al.set_class_shape(prec, cap, lanes, cells)
+
+
 def test_every_int32_class_and_redo(al):
     """x128 scoring on reads of 60-512 bases: those over about 243 bases go
     to the int32 classes (every one of them is populated), shorter ones to
