@@ -43,8 +43,8 @@ PEAK_INT16_TOPS = 2 * PEAK_INT32_TOPS            # packed 2 x int16 per lane
 # counters read for a plain 1 GiB device copy (FETCH x 2.000, WRITE x 1.000).
 # Keyed by (workload, form); valid only for the kernel sources fingerprinted
 # (any change to them makes `traffic` null until the counters are re-taken).
-KERNEL_SOURCES = ("api.cpp", "batch.h", "batch.hip", "dp_device.h", "dp_i16.hip", "dp_i32.hip",
-                  "dp_internal.h")
+KERNEL_SOURCES = ("api.cpp", "band.h", "band.hip", "batch.h", "batch.hip", "dp_device.h",
+                  "dp_i16.hip", "dp_i32.hip", "dp_internal.h")
 TRAFFIC = {
     ("config2", "plain"): {"fingerprint": "574b7377cdc0bf7b", "kernel": "dp_i32_kernel<4,25,byte>",
                            "fetch_kib": 2456014, "write_kib": 16142110,
@@ -146,7 +146,7 @@ def serve_run(args, qps):
     reqs = serving.requests_from_pool(pool, sizes)
     srv = serving.Server(gw, n_slots=args.slots, max_tasks=args.slot_tasks, max_n=250, max_m=410,
                          autotune=True, device_bytes=args.device_bytes,
-                         align_flags=binding.FULL_WINDOW if args.serve_one_pass else 0)
+                         align_flags=0 if args.serve_two_pass else binding.FULL_WINDOW)
     # the whole schedule is submitted ahead; the server admits each request
     # at its arrival time (all at once when measuring capacity)
     arr, done, lag = serving.run_open_loop(srv, reqs, qps, seed=104)
@@ -175,6 +175,19 @@ def serve_run(args, qps):
         "slowest_1pct_mean": {k: round(float(phases[slow, i].mean()), 3)
                               for i, k in enumerate(names)},
     }
+    # the batches whose enqueue took longest: when (ms after the first
+    # measured arrival), how long, and how many requests and reads waited
+    taken = np.array([r.stamps.taken_ns for r in reqs[meas]], np.int64)
+    ntask = np.array([r.n_tasks for r in reqs[meas]], np.int64)
+    keys, first, inv = np.unique(taken, return_index=True, return_inverse=True)
+    b_launch = phases[first, 1]
+    b_reqs = np.bincount(inv)
+    b_tasks = np.bincount(inv, weights=ntask)
+    t_origin = arr[meas].min()
+    slow_launches = [{"at_ms": round(float((keys[b] - t_origin) * 1e-6), 1),
+                      "launch_ms": round(float(b_launch[b]), 3), "requests": int(b_reqs[b]),
+                      "reads": int(b_tasks[b])}
+                     for b in np.argsort(-b_launch)[:5]]
     rng = np.random.default_rng(4)
     checked = 0
     for k in rng.choice(np.arange(args.serve_warmup, n_total), size=min(20, args.serve_requests),
@@ -205,13 +218,14 @@ def serve_run(args, qps):
         "config": {"workload": "served: Poisson arrivals of 1-4096-read requests (log-uniform), "
                                "reads 50-250 bp vs n+160 windows in a resident 100 Mbp genome",
                    "qps": qps if qps > 0 else "saturation", "slots": args.slots,
-                   "passes": 1 if args.serve_one_pass else 2,
+                   "passes": 2 if args.serve_two_pass else 1,
                    "slot_tasks": args.slot_tasks,
                    "requests": args.serve_requests, "mean_cells_per_request": round(mean_cells)},
         "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3),
                        "p99": round(float(np.percentile(lat, 99)), 3),
                        "max": round(float(lat.max()), 3)},
         "latency_phases_ms": breakdown,
+        "slowest_launches": slow_launches,
         "achieved_qps": round((args.serve_requests if qps > 0 else n_total) / span, 1),
         "late_submissions": int((lag[meas] > 0).sum()),
         "server": {k: (round(v, 4) if isinstance(v, float) else v) for k, v in st.items()},
@@ -379,6 +393,40 @@ def mate_bench(args):
     al.close()
 
 
+LAYOUT_DESC = ("short reads: 2,000,000 reads of 16 bp and of 32 bp vs n + 160 windows (the "
+               "uneven batch's error model), reads stored one after another or word by word "
+               "in groups of 32")
+
+
+def layout_bench(args):
+    """The paper's word-interleaved read layout against reads stored one
+    after another, on the shapes with 32-64 tasks per wavefront (16 and 32
+    bp reads), both forms: device ms per call."""
+    import torch
+    from paper_1302_5507_amd import binding, workloads
+    al = binding.Aligner(0)
+    al.autotune(args.tune_cache)
+    out = {}
+    for n in (16, 32):
+        w = workloads.short_reads(n)
+        res = binding.DeviceResult(w.n_tasks, 2 * n)
+        for inter in (False, True):
+            dw = binding.DeviceWorkload(w, interleaved=inter)
+            for form, flags in (("plain", binding.PLAIN), ("batched", binding.BATCHED)):
+                s, k, host = time_form(al, dw, res, flags, args.steps, args.warmup, SCORING)
+                key = f"{n}bp/{form}/{'interleaved' if inter else 'natural'}"
+                out[key] = {"gcups": round(w.cells / s / 1e9, 2), "device_ms": round(k, 3)}
+                print(f"bench: {key} {out[key]}", file=sys.stderr, flush=True)
+            del dw
+    shapes = {f"i{p}/{c}": f"{l}x{k}" for p, c, l, k in al.classes() if c <= 32}
+    line = {"metric": "device ms per call by read layout", "value": None, "unit": "ms",
+            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "data": "synthetic",
+            "config": {"workload": LAYOUT_DESC, "scoring": list(SCORING)},
+            "layouts": out, "shapes": shapes}
+    print(json.dumps(line), flush=True)
+    al.close()
+
+
 def time_form(al, dw, res, flags, steps, warmup, scoring):
     """Warm up, then time `steps` calls back to back on the current stream:
     (host seconds per call, mean device ms per call from HIP events on the
@@ -474,7 +522,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", choices=sorted(WORKLOADS) + ["config4", "multi", "mate"],
+    ap.add_argument("--workload", choices=sorted(WORKLOADS) + ["config4", "multi", "mate", "layout"],
                     default="config5")
     ap.add_argument("--no-extra", action="store_true",
                     help="default workload only: skip the uneven batch and the served leg")
@@ -488,8 +536,10 @@ def main():
     ap.add_argument("--device-bytes", type=int, default=0,
                     help="served workload: device memory the batches in flight share (0: one "
                          "full batch per slot)")
-    ap.add_argument("--serve-one-pass", action="store_true",
-                    help="served workload: one pass per batch (SOAP_DP_FULL_WINDOW)")
+    ap.add_argument("--serve-two-pass", action="store_true",
+                    help="served workload: score pass + band pass per batch instead of one pass "
+                         "(SOAP_DP_FULL_WINDOW, the default: served batches are short-window "
+                         "and launch-bound, where one pass is faster)")
     ap.add_argument("--serve-warmup", type=int, default=1000)
     ap.add_argument("--serve-requests", type=int, default=20000)
     ap.add_argument("--form", choices=["plain", "batched", "both"], default="both")
@@ -536,6 +586,9 @@ def main():
         return
     if args.workload == "mate":
         mate_bench(args)
+        return
+    if args.workload == "layout":
+        layout_bench(args)
         return
     scoring = tuple(args.score_scale * x for x in SCORING)
     desc, gen, headline = WORKLOADS[args.workload]
@@ -609,6 +662,7 @@ def main():
         line["served"] = {"workload": sv["config"]["workload"], "qps": SERVE_QPS,
                           "gcups": sv["value"], "latency_ms": sv["latency_ms"],
                           "latency_phases_ms": sv["latency_phases_ms"],
+                          "slowest_launches": sv["slowest_launches"],
                           "achieved_qps": sv["achieved_qps"],
                           "slots": sv["config"]["slots"], "slot_tasks": sv["config"]["slot_tasks"],
                           "requests": sv["steps"],

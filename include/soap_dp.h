@@ -92,6 +92,14 @@ extern "C" {
                                   when n S_MA + S_GO < S), so it starts at row
                                   max(0, end - n - Dmax) or later; with S_GE = 0 the band is the
                                   whole window.  Outputs are identical either way. */
+#define SOAP_DP_READS_INTERLEAVED 16u /* soap_dp_align_batch only, OR-ed with either form:
+                                  word k of read t is read_codes[read_word_off[t] + 32 k]
+                                  instead of read_codes[read_word_off[t] + k], i.e. reads
+                                  stored word by word in groups of 32 (the paper's layout
+                                  for a warp of one-problem threads, Methods section 1).
+                                  A read whose last word lies at or past read_words gets
+                                  SOAP_DP_TASK_INVALID_OFFSET.  Outputs are the same as
+                                  for the same reads stored one after another. */
 
 /*
  * Scores, all signed and added.  A gap of k bases scores
@@ -406,7 +414,7 @@ typedef struct soap_dp_server soap_dp_server;
 
 typedef struct {
   int device_ordinal;
-  int n_slots;                 /* batches in flight at once (worker threads, streams), 1..4 */
+  int n_slots;                 /* batches in flight at once (worker threads, streams), 1..8 */
   int32_t max_tasks;           /* tasks per merged batch */
   int64_t max_read_words;      /* packed read words per merged batch */
   int32_t max_n, max_m;        /* bounds on every task of every request */

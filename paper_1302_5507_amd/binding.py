@@ -42,6 +42,8 @@ BATCHED = 1
 SCORE_ONLY = 2   # OR-ed with either form: score and end only
 MIN_SCORE = 4    # OR-ed with either form: tasks below Scoring.min_score skip the traceback
 FULL_WINDOW = 8  # OR-ed with either form: one pass with decision bits over the whole window
+READS_INTERLEAVED = 16   # reads stored word by word in groups of READ_GROUP
+READ_GROUP = 32
 
 EXPORTED = [
     "soap_dp_create", "soap_dp_destroy", "soap_dp_align_batch", "soap_dp_workspace_bytes",
@@ -285,15 +287,45 @@ def pack_reads(read_codes, read_off, read_len):
     return words, word_off.astype(np.uint64)
 
 
+def pack_reads_interleaved(read_codes, read_off, read_len, group=READ_GROUP):
+    """Pack reads word by word in groups of `group` consecutive reads: word
+    k of read t is words[word_off[t] + group * k], word_off[t] = (start of
+    t's group) + t % group.  A group spans group * (its longest read's
+    words) words.  Returns (words uint32, word_off uint64)."""
+    natural, noff = pack_reads(read_codes, read_off, read_len)
+    read_len = np.asarray(read_len, dtype=np.int64)
+    T = read_len.size
+    nw = (np.maximum(read_len, 0) + 15) // 16
+    G = (T + group - 1) // group
+    span = np.zeros(G, dtype=np.int64)
+    if T:
+        np.maximum.at(span, np.arange(T) // group, nw)
+    gbase = np.zeros(G, dtype=np.int64)
+    if G:
+        gbase[1:] = np.cumsum(span * group)[:-1]
+    total = int((span * group).sum())
+    words = np.zeros(max(total, 1), dtype=np.uint32)
+    word_off = gbase[np.arange(T) // group] + np.arange(T) % group
+    if T and nw.sum():
+        rep = np.repeat(np.arange(T), nw)
+        k = np.arange(int(nw.sum())) - np.repeat(np.cumsum(nw) - nw, nw)
+        words[word_off[rep] + group * k] = natural[noff.astype(np.int64)[rep] + k]
+    return words, word_off.astype(np.uint64)
+
+
 # ---------------------------------------------------------------- convenience
 
 class DeviceWorkload:
     """A workload resident in device memory in the library's input format."""
 
-    def __init__(self, w, device="cuda", genome_words=None):
+    def __init__(self, w, device="cuda", genome_words=None, interleaved=False):
+        """interleaved: store the reads word by word in groups of READ_GROUP
+        (align with the READS_INTERLEAVED flag)."""
         import torch
         self.n_tasks = w.n_tasks
-        rw, rwo = pack_reads(w.read_codes, w.read_off, w.read_len)
+        self.interleaved = bool(interleaved)
+        pack = pack_reads_interleaved if interleaved else pack_reads
+        rw, rwo = pack(w.read_codes, w.read_off, w.read_len)
         dev = torch.device(device)
         t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
         self.read_words = t(rw.view(np.int32))
@@ -518,6 +550,8 @@ class Aligner:
         if min_score is not None:
             sc.min_score = int(min_score)
             flags |= MIN_SCORE
+        if getattr(dw, "interleaved", False):
+            flags |= READS_INTERLEAVED
         rc = soap_dp_align_batch(self.ctx, dw.batch(max_n, max_m), sc, res.abi(), stream, flags)
         if rc != SOAP_DP_OK:
             raise SoapDpError(rc, "soap_dp_align_batch")

@@ -34,16 +34,32 @@ constexpr size_t kScratchCap = size_t(16) << 30;  // decision-bit scratch budget
 constexpr int kSmallInts = 6 * kMaxClasses + 4 * kMaxClasses + 4;
 constexpr int kGraphCacheMax = 16;
 
+// Kernel kind of a launch: which int32 diagonal variant (byte table,
+// general, or -- for sizing before the scoring is known -- whichever holds
+// more workgroups; int16 kernels have one) and whether only scores are
+// computed.
+enum Variant { kGeneral = 0, kByte = 1, kEither = 2 };
+
 struct ClassSpec {
   int prec;          // kPrecI16 (offset form), kPrecI16Direct or kPrecI32
   int cap;           // upper bound on read length
   Shape shape;       // kernel shape with traceback
   Shape score_shape; // kernel shape of the score-only kernels ({0, 0}: as `shape`)
+  // int32 classes under scorings that need the general (compare and
+  // select) diagonal: their own shapes ({0, 0}: as above)
+  Shape gen_shape{0, 0};
+  Shape gen_score_shape{0, 0};
 };
 
 // The shape a class runs with: score-only kernels carry no decision words,
-// so fewer lanes with more columns each can pay off for them.
-Shape shape_of(const ClassSpec &c, bool score) {
+// so fewer lanes with more columns each can pay off for them; the int32
+// general diagonal holds a code and a constant per column, so it may prefer
+// other shapes than the byte table.
+Shape shape_of(const ClassSpec &c, bool score, Variant v = kByte) {
+  if (v == kGeneral && c.prec == kPrecI32) {
+    const Shape g = score && c.gen_score_shape.lanes ? c.gen_score_shape : c.gen_shape;
+    if (g.lanes) return g;
+  }
   return score && c.score_shape.lanes ? c.score_shape : c.shape;
 }
 
@@ -104,6 +120,7 @@ struct GraphKey {
   const int32_t *order;
   uint64_t epoch;
   uint32_t flags;
+  uint32_t read_stride;
 };
 
 bool same_batch(const soap_dp_batch &a, const soap_dp_batch &b) {
@@ -133,7 +150,8 @@ struct GraphEntry {
 
 bool same_key(const GraphKey &a, const GraphKey &b) {
   return same_batch(a.in, b.in) && same_scoring(a.sc, b.sc) && same_result(a.out, b.out) &&
-         a.order == b.order && a.epoch == b.epoch && a.flags == b.flags;
+         a.order == b.order && a.epoch == b.epoch && a.flags == b.flags &&
+         a.read_stride == b.read_stride;
 }
 
 }  // namespace
@@ -229,11 +247,6 @@ bool shape_compiled(int prec, Shape s) {
   return false;
 }
 
-// Kernel kind of a launch: which int32 diagonal variant (byte table,
-// general, or -- for sizing before the scoring is known -- whichever holds
-// more workgroups; int16 kernels have one) and whether only scores are
-// computed.
-enum Variant { kGeneral = 0, kByte = 1, kEither = 2 };
 struct Kind {
   Variant v;
   bool score;
@@ -266,11 +279,10 @@ uint64_t slot_dwords(int prec, Shape s, int32_t max_m) {
 
 // Plain form: the compiled int32 shape covering max_n with the least work
 // per task (columns times sweep steps, the anti-diagonal skew included).
-// Kernels with decision bits keep to at most 25 columns per lane (their
-// decision words and staging grow with the columns); the score-only
-// kernels may take the wider strips, which spread each step's fixed work
-// (neighbour shifts, table, end tracking) over more columns.
-Shape plain_shape(int32_t max_n, int32_t max_m, bool score = false) {
+// Among shapes of equal columns that prefers fewer lanes with more columns
+// each, which also spreads each step's fixed work (neighbour shifts, table,
+// end tracking) over more columns.
+Shape plain_shape(int32_t max_n, int32_t max_m) {
   int cnt = 0;
   const Shape *all = shapes_i32(&cnt);
   Shape best{0, 0};
@@ -279,7 +291,6 @@ Shape plain_shape(int32_t max_n, int32_t max_m, bool score = false) {
     const Shape s = all[k];
     if (s.lanes * s.cells < max_n) continue;
     if (s.lanes == 1 && max_n > 8) continue;
-    if (!score && s.cells > 25) continue;
     const double cost = double(s.lanes) * s.cells * double(max_m + s.lanes - 1);
     if (best.lanes == 0 || cost < best_cost) { best = s; best_cost = cost; }
   }
@@ -391,6 +402,7 @@ DpParams make_params(const soap_dp_batch *in, const soap_dp_scoring *sc, const s
   p.ok_status = kTaskOk;
   p.min_score = sc->min_score;
   p.defer = 1;
+  p.read_stride = 1;
   return p;
 }
 
@@ -454,15 +466,15 @@ BucketBuffers bucket_buffers(const soap_dp_ctx *ctx) {
 
 size_t plain_scratch_bytes(const soap_dp_ctx *ctx, int64_t n_tasks, int32_t max_n, int32_t max_m,
                            Kind k) {
-  const Shape s = plain_shape(max_n, max_m, k.score);
+  const Shape s = plain_shape(max_n, max_m);
   if (s.lanes == 0) return 0;
   return plan_launch(ctx, 32, s, n_tasks, max_m, k, kScratchCap).bytes();
 }
 
 int align_plain(soap_dp_ctx *ctx, const soap_dp_batch *in, const soap_dp_scoring *sc,
                 const soap_dp_result *out, hipStream_t stream, bool score,
-                const int32_t *order = nullptr) {
-  const Shape s = plain_shape(in->max_n, in->max_m, score);
+                const int32_t *order = nullptr, uint32_t read_stride = 1) {
+  const Shape s = plain_shape(in->max_n, in->max_m);
   if (s.lanes == 0) return SOAP_DP_EINVAL;
   const LaunchPlan q = plan_launch(ctx, 32, s, in->n_tasks, in->max_m, kind_for(sc, score), kScratchCap);
   const int rc = ensure_scratch(ctx, q.bytes());
@@ -476,6 +488,7 @@ int align_plain(soap_dp_ctx *ctx, const soap_dp_batch *in, const soap_dp_scoring
   // items would leave the launch waiting on the most crowded SIMDs
   p.work_counter = bucket_buffers(ctx).work_counter;
   p.task_list = order;   // work items take consecutive tasks of this order
+  p.read_stride = read_stride;
   hipError_t e = launch_zero(p.work_counter, 1, stream);
   if (e == hipSuccess) e = launch_dp_i32(s, q.grid, stream, p);
   if (e != hipSuccess) return hip_fail(ctx, e);
@@ -549,6 +562,7 @@ bool any_direct(const soap_dp_ctx *ctx, const std::vector<int> &live) {
 // bounds and reuses the scratch from its start (the class kernels are done
 // by then), at deferral 1; the budget holds its full grid of slots too.
 struct BatchedPlan {
+  Variant v = kByte;             // int32 diagonal of the call's scoring
   std::vector<char> cls_score;   // per class: score-only kernel (no decision scratch)
   std::vector<int> grids;
   uint64_t budget_dwords = 0;
@@ -562,12 +576,14 @@ struct BatchedPlan {
 BatchedPlan batched_plan(const soap_dp_ctx *ctx, int64_t n_tasks, int32_t max_n, int32_t max_m,
                          Variant v, Mode mode, const std::vector<int> &live, bool redo) {
   BatchedPlan bp;
+  bp.v = v;
   for (const ClassSpec &c : ctx->classes) bp.cls_score.push_back(class_score(c, max_m, mode));
   uint64_t need = 0, want = 0;
   for (int cls : live) {
     const ClassSpec &c = ctx->classes[size_t(cls)];
     const Kind k{v, bp.cls_score[size_t(cls)] != 0};
-    const LaunchPlan q = plan_launch(ctx, c.prec, shape_of(c, k.score), n_tasks, max_m, k, SIZE_MAX);
+    const LaunchPlan q =
+        plan_launch(ctx, c.prec, shape_of(c, k.score, v), n_tasks, max_m, k, SIZE_MAX);
     bp.grids.push_back(q.grid);
     need += round64(uint64_t(q.grid) * q.slot_dwords);
     want += round64(uint64_t(q.grid) * uint64_t(q.defer) * q.slot_dwords);
@@ -588,6 +604,10 @@ BatchedPlan batched_plan(const soap_dp_ctx *ctx, int64_t n_tasks, int32_t max_n,
 
 size_t batched_scratch_bytes(const soap_dp_ctx *ctx, int64_t n_tasks, int32_t max_n, int32_t max_m,
                              Kind k, const std::vector<int> &live, bool redo) {
+  if (k.v == kEither)   // the scoring is not known: room for either diagonal's shapes
+    return std::max(batched_scratch_bytes(ctx, n_tasks, max_n, max_m, Kind{kByte, k.score}, live, redo),
+                    batched_scratch_bytes(ctx, n_tasks, max_n, max_m, Kind{kGeneral, k.score}, live,
+                                          redo));
   return batched_plan(ctx, n_tasks, max_n, max_m, k.v, k.score ? kModeScore : kModeFull, live, redo)
       .bytes();
 }
@@ -618,7 +638,7 @@ ClassTable class_table(const soap_dp_ctx *ctx, const std::vector<int> &live,
   for (size_t k = 0; k < ctx->classes.size(); ++k) {
     const ClassSpec &c = ctx->classes[k];
     const bool score = bp.cls_score[k] != 0;
-    const Shape sh = shape_of(c, score);
+    const Shape sh = shape_of(c, score, bp.v);
     ct.cap[k] = c.cap;
     ct.cols[k] = sh.lanes * sh.cells;
     ct.prec[k] = c.prec;
@@ -641,8 +661,10 @@ ClassTable class_table(const soap_dp_ctx *ctx, const std::vector<int> &live,
 // so the launch plans are computed beforehand: no runtime queries in between).
 hipError_t enqueue_batched(soap_dp_ctx *ctx, const soap_dp_batch *in, const soap_dp_scoring *sc,
                            const soap_dp_result *out, const std::vector<int> &live,
-                           const BatchedPlan &bp, const int32_t *order, hipStream_t stream) {
+                           const BatchedPlan &bp, const int32_t *order, uint32_t read_stride,
+                           hipStream_t stream) {
   DpParams p = make_params(in, sc, out);
+  p.read_stride = read_stride;
   const BucketBuffers b = bucket_buffers(ctx);
   p.redo_list = b.redo_list;
   p.redo_count = b.redo_count;
@@ -671,7 +693,8 @@ hipError_t enqueue_batched(soap_dp_ctx *ctx, const soap_dp_batch *in, const soap
     q.scratch_off_dev = b.scratch_off + k;
     q.ok_status = packed16(c.prec) ? kTaskOk : kTaskRedone;
     q.score_only = bp.cls_score[size_t(k)];
-    if ((e = launch_shape(c.prec, shape_of(c, q.score_only != 0), bp.grids[li], cs, q)) != hipSuccess)
+    if ((e = launch_shape(c.prec, shape_of(c, q.score_only != 0, bp.v), bp.grids[li], cs, q)) !=
+        hipSuccess)
       return e;
     if ((e = hipEventRecord(ctx->join_events[li], cs)) != hipSuccess) return e;
     if ((e = hipStreamWaitEvent(stream, ctx->join_events[li], 0)) != hipSuccess) return e;
@@ -695,7 +718,7 @@ hipError_t enqueue_batched(soap_dp_ctx *ctx, const soap_dp_batch *in, const soap
 
 int align_batched(soap_dp_ctx *ctx, const soap_dp_batch *in, const soap_dp_scoring *sc,
                   const soap_dp_result *out, hipStream_t stream, Mode mode,
-                  const int32_t *order = nullptr) {
+                  const int32_t *order = nullptr, uint32_t read_stride = 1) {
   const std::vector<int> live = live_classes(ctx, in->max_n, in->max_m, sc, mode);
   int rc = ensure_task_buffers(ctx, in->n_tasks);
   if (rc) return rc;
@@ -707,7 +730,7 @@ int align_batched(soap_dp_ctx *ctx, const soap_dp_batch *in, const soap_dp_scori
   rc = ensure_scratch(ctx, bp.bytes());
   if (rc) return rc;
   if (!ctx->use_graphs || ctx->frozen) {
-    const hipError_t e = enqueue_batched(ctx, in, sc, out, live, bp, order, stream);
+    const hipError_t e = enqueue_batched(ctx, in, sc, out, live, bp, order, read_stride, stream);
     return e == hipSuccess ? SOAP_DP_OK : hip_fail(ctx, e);
   }
   GraphKey key;
@@ -716,6 +739,7 @@ int align_batched(soap_dp_ctx *ctx, const soap_dp_batch *in, const soap_dp_scori
   key.sc = *sc;
   key.out = *out;
   key.order = order;
+  key.read_stride = read_stride;
   key.epoch = ctx->epoch;
   key.flags = uint32_t(mode);
   GraphEntry *hit = nullptr;
@@ -727,7 +751,8 @@ int align_batched(soap_dp_ctx *ctx, const soap_dp_batch *in, const soap_dp_scori
       return hip_fail(ctx, hipGetLastError());
     hipError_t e = hipStreamBeginCapture(ctx->capture_stream, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return hip_fail(ctx, e);
-    const hipError_t le = enqueue_batched(ctx, in, sc, out, live, bp, order, ctx->capture_stream);
+    const hipError_t le =
+        enqueue_batched(ctx, in, sc, out, live, bp, order, read_stride, ctx->capture_stream);
     hipGraph_t graph = nullptr;
     e = hipStreamEndCapture(ctx->capture_stream, &graph);
     if (le != hipSuccess || e != hipSuccess) {
@@ -776,6 +801,8 @@ struct TuneData {
   uint32_t *cigar = nullptr;
   uint8_t *status = nullptr;
   int64_t tasks = 0;
+  int32_t max_m = 0;
+  double cells = 0;
   ~TuneData() {
     for (void *q : {(void *)reads, (void *)genome, (void *)rwo, (void *)rbo, (void *)rl, (void *)ml,
                     (void *)i32, (void *)cigar, (void *)status})
@@ -783,10 +810,17 @@ struct TuneData {
   }
 };
 
+// Window lengths a class is timed on: half of its tasks have windows of
+// n + 160 (short windows, as in uneven and served batches), half of
+// 4 n + 160 (long windows, as in low-similarity batches and the score pass
+// of two-pass calls), so a shape is chosen for both.
+int32_t tune_window(int32_t n, int64_t t, int64_t tasks) {
+  return t < tasks / 2 ? n + 160 : std::min<int32_t>(4 * n + 160, SOAP_DP_MAX_WINDOW);
+}
+
 // Synthetic tasks for timing one class: reads of length n copied from random
-// windows of length n + 160 with 5% substitutions.
+// windows (tune_window) with 5% substitutions.
 bool make_tune_data(TuneData &d, int32_t n, int64_t tasks) {
-  const int32_t m = n + 160;
   const int64_t glen = 1 << 20;
   uint64_t seed = 0x5eed0000u + uint64_t(n);
   std::vector<uint8_t> g(static_cast<size_t>(glen));
@@ -795,10 +829,16 @@ bool make_tune_data(TuneData &d, int32_t n, int64_t tasks) {
   std::vector<uint32_t> gw(static_cast<size_t>(glen / 16), 0u), rw(static_cast<size_t>(tasks * nw), 0u);
   for (int64_t k = 0; k < glen; ++k) gw[size_t(k / 16)] |= uint32_t(g[size_t(k)]) << (2 * (k % 16));
   std::vector<uint64_t> rwo(static_cast<size_t>(tasks)), rbo(static_cast<size_t>(tasks));
-  std::vector<int32_t> rl(static_cast<size_t>(tasks), n), ml(static_cast<size_t>(tasks), m);
+  std::vector<int32_t> rl(static_cast<size_t>(tasks), n), ml(static_cast<size_t>(tasks), 0);
+  d.max_m = 0;
+  d.cells = 0;
   for (int64_t t = 0; t < tasks; ++t) {
+    const int32_t m = tune_window(n, t, tasks);
+    ml[size_t(t)] = m;
+    d.max_m = std::max(d.max_m, m);
+    d.cells += double(n) * double(m);
     const uint64_t off = splitmix(seed) % uint64_t(glen - m);
-    const uint64_t s = splitmix(seed) % 161;
+    const uint64_t s = splitmix(seed) % uint64_t(m - n + 1);
     rbo[size_t(t)] = off;
     rwo[size_t(t)] = uint64_t(t) * uint64_t(nw);
     for (int32_t q = 0; q < n; ++q) {
@@ -822,7 +862,7 @@ bool make_tune_data(TuneData &d, int32_t n, int64_t tasks) {
 
 std::string cache_header(const soap_dp_ctx *ctx) {
   char buf[128];
-  std::snprintf(buf, sizeof buf, "\"arch\": \"%s\", \"cus\": %d, \"version\": 2", ctx->arch.c_str(),
+  std::snprintf(buf, sizeof buf, "\"arch\": \"%s\", \"cus\": %d, \"version\": 3", ctx->arch.c_str(),
                 ctx->cu_count);
   return buf;
 }
@@ -839,18 +879,26 @@ bool load_cache(soap_dp_ctx *ctx, const char *path) {
   std::vector<ClassSpec> cls = ctx->classes;
   size_t pos = 0;
   int found = 0;
+  auto usable = [](int prec, int cap, Shape s) {
+    return s.lanes * s.cells >= cap && shape_compiled(prec, s);
+  };
   while ((pos = text.find("{\"prec\":", pos)) != std::string::npos) {
-    int prec = 0, cap = 0, lanes = 0, cells = 0, sl = 0, sk = 0;
+    int prec = 0, cap = 0, lanes = 0, cells = 0, sl = 0, sk = 0, gl = 0, gk = 0, gsl = 0, gsk = 0;
     if (std::sscanf(text.c_str() + pos,
                     "{\"prec\": %d, \"cap\": %d, \"lanes\": %d, \"cells\": %d, "
-                    "\"score_lanes\": %d, \"score_cells\": %d",
-                    &prec, &cap, &lanes, &cells, &sl, &sk) == 6) {
+                    "\"score_lanes\": %d, \"score_cells\": %d, \"gen_lanes\": %d, "
+                    "\"gen_cells\": %d, \"gen_score_lanes\": %d, \"gen_score_cells\": %d",
+                    &prec, &cap, &lanes, &cells, &sl, &sk, &gl, &gk, &gsl, &gsk) == 10) {
       for (auto &c : cls)
-        if (c.prec == prec && c.cap == cap && lanes * cells >= cap &&
-            shape_compiled(prec, Shape{lanes, cells}) && sl * sk >= cap &&
-            shape_compiled(prec, Shape{sl, sk})) {
+        if (c.prec == prec && c.cap == cap && usable(prec, cap, Shape{lanes, cells}) &&
+            usable(prec, cap, Shape{sl, sk})) {
           c.shape = Shape{lanes, cells};
           c.score_shape = Shape{sl, sk};
+          // general-diagonal shapes: int32 classes only, when tuned
+          const bool gen = prec == kPrecI32 && usable(prec, cap, Shape{gl, gk}) &&
+                           usable(prec, cap, Shape{gsl, gsk});
+          c.gen_shape = gen ? Shape{gl, gk} : Shape{0, 0};
+          c.gen_score_shape = gen ? Shape{gsl, gsk} : Shape{0, 0};
           ++found;
         }
     }
@@ -877,8 +925,11 @@ bool save_cache(const soap_dp_ctx *ctx, const char *path, const std::vector<doub
     const Shape ss = shape_of(c, true);
     std::fprintf(f,
                  "  {\"prec\": %d, \"cap\": %d, \"lanes\": %d, \"cells\": %d, \"score_lanes\": %d, "
-                 "\"score_cells\": %d, \"gcups\": %.1f, \"score_gcups\": %.1f}%s\n",
-                 c.prec, c.cap, c.shape.lanes, c.shape.cells, ss.lanes, ss.cells,
+                 "\"score_cells\": %d, \"gen_lanes\": %d, \"gen_cells\": %d, "
+                 "\"gen_score_lanes\": %d, \"gen_score_cells\": %d, \"gcups\": %.1f, "
+                 "\"score_gcups\": %.1f}%s\n",
+                 c.prec, c.cap, c.shape.lanes, c.shape.cells, ss.lanes, ss.cells, c.gen_shape.lanes,
+                 c.gen_shape.cells, c.gen_score_shape.lanes, c.gen_score_shape.cells,
                  k < gcups.size() ? gcups[k] : 0.0, k < gcups_score.size() ? gcups_score[k] : 0.0,
                  q + 1 < keep.size() ? "," : "");
   }
@@ -889,9 +940,8 @@ bool save_cache(const soap_dp_ctx *ctx, const char *path, const std::vector<doub
 
 // Measure one shape on the class's synthetic tasks: best of three launches.
 double time_shape(soap_dp_ctx *ctx, int prec, Shape s, const TuneData &d, int32_t n, hipStream_t st,
-                  bool score) {
-  const int32_t m = n + 160;
-  soap_dp_scoring sc{1, -3, -5, -2};
+                  bool score, const soap_dp_scoring &sc) {
+  const int32_t m = d.max_m;
   DpParams p{};
   p.read_codes = d.reads; p.read_word_off = d.rwo; p.read_len = d.rl;
   p.ref_codes = d.genome; p.ref_base_off = d.rbo; p.ref_len = d.ml;
@@ -931,7 +981,7 @@ double time_shape(soap_dp_ctx *ctx, int prec, Shape s, const TuneData &d, int32_
   (void)hipEventDestroy(b);
   (void)hipGetLastError();
   if (best_ms >= 1e29) return 0;
-  return double(d.tasks) * double(n) * double(m) / (best_ms * 1e-3) / 1e9;
+  return d.cells / (best_ms * 1e-3) / 1e9;
 }
 
 int autotune(soap_dp_ctx *ctx, std::vector<double> &gcups, std::vector<double> &gcups_score) {
@@ -943,7 +993,8 @@ int autotune(soap_dp_ctx *ctx, std::vector<double> &gcups, std::vector<double> &
   for (size_t k = 0; k < ctx->classes.size() && rc == SOAP_DP_OK; ++k) {
     ClassSpec &c = ctx->classes[k];
     if (c.prec == kPrecI16Direct) continue;   // runs its offset-form class's shapes
-    const int32_t n = c.cap, m = n + 160;
+    const int32_t n = c.cap;
+    const double m = 0.5 * (tune_window(n, 0, 2) + tune_window(n, 1, 2));   // mean window
     // about 1.2e10 cells (a few ms per launch, also for the faster
     // score-only kernels), and never fewer than 65,536 tasks: enough work
     // items that the persistent grid runs many rounds, as it does on real
@@ -954,20 +1005,30 @@ int autotune(soap_dp_ctx *ctx, std::vector<double> &gcups, std::vector<double> &
     if (!make_tune_data(d, n, tasks)) { rc = SOAP_DP_ENOMEM; break; }
     int cnt = 0;
     const Shape *all = c.prec == 16 ? shapes_i16(&cnt) : shapes_i32(&cnt);
-    // with traceback, then score only: the best shape of each kind
-    for (int kind = 0; kind < 2; ++kind) {
+    // with traceback, then score only: the best shape of each kind, timed
+    // with the benchmark scoring (byte-table diagonal); int32 classes also
+    // with a scoring that needs the general diagonal
+    const soap_dp_scoring byte_sc{1, -3, -5, -2, INT32_MIN};
+    const soap_dp_scoring gen_sc{1, -9, -3, -1, INT32_MIN};   // S_MI - S_GE - S_GO < 0
+    for (int kind = 0; kind < (c.prec == kPrecI32 ? 4 : 2); ++kind) {
+      const bool score = kind & 1, general = kind >= 2;
+      const soap_dp_scoring &sc = general ? gen_sc : byte_sc;
+      Shape &slot = general ? (score ? c.gen_score_shape : c.gen_shape)
+                            : (score ? c.score_shape : c.shape);
       double best = -1;
-      Shape best_s = kind ? shape_of(c, true) : c.shape;
+      Shape best_s = shape_of(c, score, general ? kGeneral : kByte);
       for (int q = 0; q < cnt; ++q) {
         const Shape s = all[q];
         const int cols = s.lanes * s.cells;
         if (cols < c.cap || cols > c.cap + std::max(c.cap / 6, 8)) continue;
-        if (c.prec == 16 && !int16_fits(n, n + 160, cols, 1, -3, -5, -2)) continue;
-        const double g = time_shape(ctx, c.prec, s, d, n, st, kind == 1);
+        if (c.prec == 16 && !int16_fits(n, d.max_m, cols, sc.match, sc.mismatch, sc.gap_open,
+                                        sc.gap_extend))
+          continue;
+        const double g = time_shape(ctx, c.prec, s, d, n, st, score, sc);
         if (g > best) { best = g; best_s = s; }
       }
-      (kind ? c.score_shape : c.shape) = best_s;
-      (kind ? gcups_score : gcups)[k] = best;
+      slot = best_s;
+      if (!general) (score ? gcups_score : gcups)[k] = best;
     }
   }
   (void)hipStreamDestroy(st);
@@ -1096,7 +1157,8 @@ int ensure_band(soap_dp_ctx *ctx, size_t bytes) {
 // the window rows that can hold an optimal alignment, in an order that
 // groups tasks of similar band lengths.  Either form runs both passes.
 int align_two_pass(soap_dp_ctx *ctx, const soap_dp_batch *in, const soap_dp_scoring *sc,
-                   const soap_dp_result *out, hipStream_t stream, bool batched) {
+                   const soap_dp_result *out, hipStream_t stream, bool batched,
+                   uint32_t read_stride) {
   int rc = ensure_band(ctx, band_layout(in->n_tasks, nullptr, nullptr));
   if (rc) return rc;
   BandWork w{};
@@ -1105,8 +1167,8 @@ int align_two_pass(soap_dp_ctx *ctx, const soap_dp_batch *in, const soap_dp_scor
   // the other classes trace back into the caller's CIGAR rows already)
   const soap_dp_result r1{w.p_score, w.p_begin, w.p_end, out->cigar, out->cigar_stride, w.p_clen,
                           w.p_status};
-  rc = batched ? align_batched(ctx, in, sc, &r1, stream, kModeMixed)
-               : align_plain(ctx, in, sc, &r1, stream, true);
+  rc = batched ? align_batched(ctx, in, sc, &r1, stream, kModeMixed, nullptr, read_stride)
+               : align_plain(ctx, in, sc, &r1, stream, true, nullptr, read_stride);
   if (rc) return rc;
   const BandIn bi{in->ref_base_off, in->read_len, in->ref_len, in->n_tasks, in->max_m,
                   sc->match, sc->gap_open, sc->gap_extend};
@@ -1117,8 +1179,8 @@ int align_two_pass(soap_dp_ctx *ctx, const soap_dp_batch *in, const soap_dp_scor
   s2.min_score = INT32_MIN;
   const soap_dp_batch b2{in->read_codes, in->read_word_off, in->read_len, in->ref_codes, w.b_rbo,
                          w.b_ml, in->n_tasks, in->max_n, in->max_m, in->read_words, in->ref_words};
-  rc = batched ? align_batched(ctx, &b2, &s2, out, stream, kModeFull, w.order)
-               : align_plain(ctx, &b2, &s2, out, stream, false, w.order);
+  rc = batched ? align_batched(ctx, &b2, &s2, out, stream, kModeFull, w.order, read_stride)
+               : align_plain(ctx, &b2, &s2, out, stream, false, w.order, read_stride);
   if (rc) return rc;
   const BandOut bo{out->score, out->ref_begin, out->ref_end, out->cigar_len, out->status};
   if ((e = launch_band_fixup(in->n_tasks, w, bo, stream)) != hipSuccess) return hip_fail(ctx, e);
@@ -1130,10 +1192,12 @@ int align_dispatch(soap_dp_ctx *ctx, const soap_dp_batch *in, const soap_dp_scor
                    const soap_dp_result *out, hipStream_t stream, uint32_t flags) {
   const bool batched = (flags & SOAP_DP_BATCHED) != 0;
   const bool score = (flags & SOAP_DP_SCORE_ONLY) != 0;
+  const uint32_t stride = (flags & SOAP_DP_READS_INTERLEAVED) ? kReadGroup : 1u;
   if (!score && (flags & SOAP_DP_FULL_WINDOW) == 0)
-    return align_two_pass(ctx, in, sc, out, stream, batched);
-  return batched ? align_batched(ctx, in, sc, out, stream, score ? kModeScore : kModeFull)
-                 : align_plain(ctx, in, sc, out, stream, score);
+    return align_two_pass(ctx, in, sc, out, stream, batched, stride);
+  return batched ? align_batched(ctx, in, sc, out, stream, score ? kModeScore : kModeFull,
+                                 nullptr, stride)
+                 : align_plain(ctx, in, sc, out, stream, score, nullptr, stride);
 }
 
 // Classes a batched call with these bounds can populate: for a known
@@ -1377,7 +1441,8 @@ int soap_dp_align_batch(soap_dp_ctx *ctx, const soap_dp_batch *in, const soap_dp
                         const soap_dp_result *out, void *stream, uint32_t flags) {
   if (!ctx) return SOAP_DP_EINVAL;
   if (!scoring_ok(sc)) return SOAP_DP_EINVAL;
-  if (flags & ~(SOAP_DP_BATCHED | SOAP_DP_SCORE_ONLY | SOAP_DP_MIN_SCORE | SOAP_DP_FULL_WINDOW))
+  if (flags & ~(SOAP_DP_BATCHED | SOAP_DP_SCORE_ONLY | SOAP_DP_MIN_SCORE | SOAP_DP_FULL_WINDOW |
+                SOAP_DP_READS_INTERLEAVED))
     return SOAP_DP_EINVAL;
   const bool score = (flags & SOAP_DP_SCORE_ONLY) != 0;
   const int rc = batch_ok(in, out, score);
@@ -1438,6 +1503,8 @@ int soap_dp_set_class_shape(soap_dp_ctx *ctx, int32_t precision, int32_t capacit
     if (c.prec == precision && c.cap == capacity) {
       c.shape = s;
       c.score_shape = s;
+      c.gen_shape = Shape{0, 0};
+      c.gen_score_shape = Shape{0, 0};
       mirror_direct_shapes(ctx->classes);
       clear_graphs(ctx);
       return SOAP_DP_OK;

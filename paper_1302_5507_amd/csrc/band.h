@@ -20,7 +20,7 @@
 
 namespace soapdp {
 
-constexpr int kBandBins = 64;   // band-length bins of the pass-2 task order
+constexpr int kBandBins = 256;   // band-length bins of the pass-2 task order
 
 // Work arrays of a two-pass call (context-owned, n_tasks entries each).
 struct BandWork {

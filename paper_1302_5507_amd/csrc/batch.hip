@@ -53,7 +53,8 @@ __global__ __launch_bounds__(kBlock) void classify_kernel(DpParams p, ClassTable
     int k = -1;
     if (n < 1 || m < 1 || n > p.max_n || m > p.max_m)
       st = kTaskInvalidLen;
-    else if (rwo + (uint64_t)((n + 15) >> 4) > p.read_words || rbo + (uint64_t)m > p.ref_words * 16)
+    else if (!read_in_bounds(rwo, n, p.read_words, p.read_stride) ||
+             rbo + (uint64_t)m > p.ref_words * 16)
       st = kTaskInvalidOffset;
     else {
       k = class_of(ct, n, m, p.ma, p.mi, p.go, p.ge);

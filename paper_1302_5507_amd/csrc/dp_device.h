@@ -238,18 +238,19 @@ __device__ __forceinline__ int64_t task_at(const DpParams &p, const int32_t *lis
 struct StripWords {
   uint32_t w0, w1, w2, w3;
   int32_t base;  // word index of w0
+  // word i of the read is codes[first_word + i * stride]
   __device__ __forceinline__ void load(const uint32_t *codes, uint64_t first_word, int32_t n,
-                                       int32_t q0) {
+                                       int32_t q0, uint32_t stride) {
     const int32_t last = (n - 1) >> 4;
     base = (q0 > 0 ? q0 : 0) >> 4;
     const int32_t i0 = base < last ? base : last;
     const int32_t i1 = base + 1 < last ? base + 1 : last;
     const int32_t i2 = base + 2 < last ? base + 2 : last;
     const int32_t i3 = base + 3 < last ? base + 3 : last;
-    w0 = codes[first_word + (uint64_t)i0];
-    w1 = codes[first_word + (uint64_t)i1];
-    w2 = codes[first_word + (uint64_t)i2];
-    w3 = codes[first_word + (uint64_t)i3];
+    w0 = codes[first_word + (uint64_t)i0 * stride];
+    w1 = codes[first_word + (uint64_t)i1 * stride];
+    w2 = codes[first_word + (uint64_t)i2 * stride];
+    w3 = codes[first_word + (uint64_t)i3 * stride];
   }
   // code of read index q (0 <= q < n)
   __device__ __forceinline__ uint32_t code(int32_t q) const {

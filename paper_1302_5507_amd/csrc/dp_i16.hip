@@ -157,7 +157,7 @@ void dp_i16_kernel(DpParams p) {
         if (n[h] < 1 || m[h] < 1 || n[h] > p.max_n || m[h] > p.max_m || n[h] > L * K ||
             m[h] > slot_rows)
           st[h] = kTaskInvalidLen;
-        else if (rwo[h] + (uint64_t)((n[h] + 15) >> 4) > p.read_words ||
+        else if (!read_in_bounds(rwo[h], n[h], p.read_words, p.read_stride) ||
                  rbo[h] + (uint64_t)m[h] > p.ref_words * 16)
           st[h] = kTaskInvalidOffset;
         else if (kDirect ? !int16_direct_fits(n[h], ma, mi, go, ge)
@@ -185,7 +185,7 @@ void dp_i16_kernel(DpParams p) {
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       rw[h] = StripWords{0, 0, 0, 0};
-      if (mg[h] > 0) rw[h].load(p.read_codes, rwo[h], n[h], lg * K - pad[h]);
+      if (mg[h] > 0) rw[h].load(p.read_codes, rwo[h], n[h], lg * K - pad[h], p.read_stride);
     }
     uint32_t Rc[K], H[K], F[K];
 #pragma unroll

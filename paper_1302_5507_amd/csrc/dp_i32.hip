@@ -91,7 +91,8 @@ void dp_i32_kernel(DpParams p) {
       rbo = p.ref_base_off[task];
       if (n < 1 || m < 1 || n > p.max_n || m > p.max_m || n > L * K || m > slot_rows)
         st = kTaskInvalidLen;
-      else if (rwo + (uint64_t)((n + 15) >> 4) > p.read_words || rbo + (uint64_t)m > p.ref_words * 16)
+      else if (!read_in_bounds(rwo, n, p.read_words, p.read_stride) ||
+               rbo + (uint64_t)m > p.ref_words * 16)
         st = kTaskInvalidOffset;
     }
     const bool valid = task >= 0 && st == kTaskOk;
@@ -104,7 +105,7 @@ void dp_i32_kernel(DpParams p) {
     if (first) { s_task[u0] = task; s_n[u0] = n; s_pad[u0] = pad; s_st[u0] = st; }
 
     StripWords rw{0, 0, 0, 0};
-    if (valid) rw.load(p.read_codes, rwo, n, lg * K - pad);
+    if (valid) rw.load(p.read_codes, rwo, n, lg * K - pad, p.read_stride);
     const int32_t ge = p.ge;
     const int32_t c_go = p.go - ge;          // gap open in offset form
     // H holds G = M^ + c_go: the gap-open candidate of the cell to the right

@@ -75,7 +75,23 @@ struct DpParams {
   // floor are appended here (atomically counted) for the int32 re-run.
   int32_t *redo_list;
   int32_t *redo_count;
+  // Word k of read t is read_codes[read_word_off[t] + k * read_stride]: 1
+  // for reads stored one after another, kReadGroup for reads interleaved
+  // word by word in groups.
+  uint32_t read_stride;
 };
+
+// Reads interleaved word by word in groups of this many (the paper's
+// layout for a warp of one-problem threads).
+constexpr uint32_t kReadGroup = 32;
+
+// The words of an n-base read at word offset rwo, stride `stride`, lie
+// inside a buffer of read_words words.
+__host__ __device__ inline bool read_in_bounds(uint64_t rwo, int32_t n, uint64_t read_words,
+                                               uint32_t stride) {
+  const uint64_t nw = (uint64_t)((n + 15) >> 4);
+  return nw == 0 || rwo + (nw - 1) * stride < read_words;
+}
 
 // Decision words are stored in blocks of `step_block(K)` sweep steps: within
 // a block each lane's words for consecutive steps are contiguous, so the

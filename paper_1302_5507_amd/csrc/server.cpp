@@ -416,7 +416,7 @@ extern "C" {
 
 uint64_t soap_dp_now_ns(void) { return now_ns(); }
 
-constexpr int kMaxSlots = 4;
+constexpr int kMaxSlots = 8;
 
 int soap_dp_server_create(soap_dp_server **out, const soap_dp_server_config *cfg) {
   if (!out || !cfg) return SOAP_DP_EINVAL;

@@ -259,6 +259,22 @@ def config3(seed: int = 103, genome_seed: int = 1, n_reads: int = 2_000_000,
     return w
 
 
+def short_reads(n: int, n_reads: int = 2_000_000, seed: int = 108, genome_seed: int = 1) -> Workload:
+    """Short reads of n bases against windows of n + 160 (the uneven batch's
+    window rule and error model): the shapes with 32-64 tasks per wavefront,
+    where the paper's word-interleaved read layout could matter."""
+    g = random_genome(1_000_000, genome_seed)
+    rng = np.random.Generator(np.random.PCG64(seed + n))
+    nn = np.full(n_reads, n)
+    m = nn + 160
+    law = lambda r, idx: r.integers(0, 161, size=idx.size)
+    w = simulate(f"short{n}", g, nn, m, law, 0.04, 0.005,
+                 lambda r, k: _geometric_trunc(r, 0.25, k, 30), rng,
+                 params=dict(p_sub=0.04, p_ind=0.005, indel="geometric(1/4)<=30"))
+    w.seed = seed + n
+    return w
+
+
 def config5(seed: int = 105, genome_seed: int = 1, n_reads: int = 500_000) -> Workload:
     """Low-similarity tail: reads x 150 bp vs 1,000 bp windows; per-read
     identity p ~ U[0.60, 0.75], divergence d = 1 - p split as p_sub = 0.75 d

@@ -86,6 +86,23 @@ def test_pack_reads_word_aligned():
         assert np.array_equal(got, codes[offs[t]:offs[t] + lens[t]])
 
 
+def test_pack_reads_interleaved():
+    """Reads stored word by word in groups of 32: word k of read t at
+    word_off[t] + 32 k, every read's bases intact, groups back to back."""
+    rng = np.random.default_rng(2)
+    lens = rng.integers(0, 90, size=101)
+    offs = np.concatenate([[0], np.cumsum(lens)[:-1]])
+    codes = rng.integers(0, 4, size=int(lens.sum())).astype(np.uint8)
+    words, woff = binding.pack_reads_interleaved(codes, offs, lens)
+    for t in range(len(lens)):
+        k = np.arange(int(lens[t]))
+        got = (words[int(woff[t]) + 32 * (k // 16)] >> (2 * (k % 16)).astype(np.uint32)) & 3
+        assert np.array_equal(got.astype(np.uint8), codes[offs[t]:offs[t] + lens[t]])
+    assert list(woff[:33] % 32) == list(range(32)) + [0]
+    nw = (lens + 15) // 16
+    assert words.size == sum(32 * int(nw[g:g + 32].max()) for g in range(0, len(lens), 32))
+
+
 def test_ctypes_structs_match_header_layout(tmp_path):
     """Every ctypes mirror has the size and field offsets the C compiler gives
     the header's struct."""
@@ -120,14 +137,16 @@ def test_ctypes_structs_match_header_layout(tmp_path):
             assert got[(cname, f[0])] == getattr(py, f[0]).offset, (cname, f[0])
 
 
-def test_server_rejects_slot_counts_outside_1_to_4():
-    """Argument checks of soap_dp_server_create run before any device call."""
+def test_server_rejects_bad_slot_counts_and_flags():
+    """Argument checks of soap_dp_server_create run before any device call:
+    1..8 slots, and align_flags 0 or SOAP_DP_FULL_WINDOW."""
     import ctypes
     from paper_1302_5507_amd import serving
     L = serving._lib()
-    for n in (0, 5, 16):
+    for n, flags in ((0, 0), (9, 0), (16, 0), (2, binding.BATCHED), (2, binding.SCORE_ONLY),
+                     (2, 16)):
         cfg = serving.ServerConfig(0, n, 1024, 1024 * 16, 250, 410, binding.Scoring(1, -3, -5, -2),
-                                   ctypes.c_void_p(64), 1, 0)
+                                   ctypes.c_void_p(64), 1, 0, 0, flags)
         h = ctypes.c_void_p()
         assert L.soap_dp_server_create(ctypes.byref(h), ctypes.byref(cfg)) == binding.SOAP_DP_EINVAL
         assert not h.value

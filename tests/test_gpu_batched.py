@@ -365,5 +365,15 @@ def test_autotune_and_cache(tmp_path):
     w = workloads.config3(n_reads=6000)
     g = run(b, w, CONFIG_SCORING)
     assert_same(g, oracle_align(w, CONFIG_SCORING), label="tuned")
+    # the int32 classes' shapes tuned for the general diagonal: a scoring
+    # that needs it and fits neither int16 form
+    sc = (300, -1, -5, -2)
+    text = open(path).read()
+    assert '"gen_lanes"' in text
+    rng = np.random.default_rng(15)
+    w2 = workloads.random_tasks(rng, 3000, n_range=(1, 250), m_range=(1, 420), genome_len=30000)
+    g2 = run(b, w2, sc, max_n=250)
+    assert (g2["status"] == binding.TASK_OK_REDONE_INT32).all()
+    assert_same(as_oracle_status(g2), oracle_align(w2, sc, stride=500), label="tuned general")
     a.close()
     b.close()

@@ -64,7 +64,7 @@ def test_threshold_ignored_without_the_flag():
                                        binding.BATCHED) == binding.SOAP_DP_OK
     torch.cuda.synchronize()
     assert not (res.status.cpu().numpy() == binding.TASK_BELOW_CUTOFF).any()
-    assert binding.soap_dp_align_batch(aligner().ctx, dw.batch(), sc, res.abi(), st, 16) == \
+    assert binding.soap_dp_align_batch(aligner().ctx, dw.batch(), sc, res.abi(), st, 64) == \
         binding.SOAP_DP_EINVAL
 
 

@@ -115,3 +115,57 @@ def test_order_invariance():
     g2 = gpu_align(w.subset(perm), CONFIG_SCORING)
     for f in ("score", "ref_begin", "ref_end", "cigar_len", "status"):
         assert np.array_equal(g1[f][perm], g2[f])
+
+
+@pytest.mark.parametrize("flags", [binding.PLAIN, binding.BATCHED, binding.PLAIN | binding.FULL_WINDOW,
+                                   binding.BATCHED | binding.SCORE_ONLY])
+def test_interleaved_reads_equal_natural(flags):
+    """Reads stored word by word in groups of 32 (READS_INTERLEAVED) give the
+    outputs of the same reads stored one after another, on reads of 1-300
+    bases (groups mixing lengths), in every form."""
+    import torch
+    from tests.gpu_util import aligner
+    rng = np.random.default_rng(90 + flags)
+    w = workloads.random_tasks(rng, 2500, n_range=(1, 300), m_range=(1, 500), genome_len=30000)
+    outs = []
+    for inter in (False, True):
+        dw = binding.DeviceWorkload(w, interleaved=inter)
+        res = binding.DeviceResult(w.n_tasks, 0 if flags & binding.SCORE_ONLY else 2 * dw.max_n)
+        aligner().align(dw, CONFIG_SCORING, flags=flags, res=res)
+        torch.cuda.synchronize()
+        outs.append(res.to_host())
+    for f in ("status", "score", "ref_begin", "ref_end", "cigar_len"):
+        assert np.array_equal(outs[0][f], outs[1][f]), f
+    if not flags & binding.SCORE_ONLY:
+        assert np.array_equal(outs[0]["cigar"], outs[1]["cigar"])
+        st = np.where(outs[1]["status"] == binding.TASK_OK_REDONE_INT32, 0, outs[1]["status"])
+        assert_same(dict(outs[1], status=st), oracle_align(w, CONFIG_SCORING, stride=600),
+                    label="interleaved")
+
+
+def test_interleaved_read_past_the_buffer_is_invalid_offset():
+    """With the interleaved layout a read's last word lies 32 (words - 1)
+    past its offset: a read buffer cut short there gives INVALID_OFFSET for
+    exactly the reads it cuts, in both forms."""
+    import torch
+    from tests.gpu_util import aligner
+    rng = np.random.default_rng(91)
+    w = workloads.random_tasks(rng, 64, n_range=(17, 48), m_range=(60, 120), genome_len=5000)
+    dw = binding.DeviceWorkload(w, interleaved=True)
+    words, woff = binding.pack_reads_interleaved(w.read_codes, w.read_off, w.read_len)
+    nw = (w.read_len.astype(np.int64) + 15) // 16
+    last = woff.astype(np.int64) + 32 * (nw - 1)
+    cut = int(np.sort(last)[40])   # keep words [0, cut): reads whose last word is >= cut fail
+    dw.read_words = dw.read_words[:cut]
+    bad = last >= cut
+    assert bad.any() and (~bad).any()
+    ok = np.nonzero(~bad)[0]
+    for flags in (binding.PLAIN, binding.BATCHED):
+        res = binding.DeviceResult(w.n_tasks, 2 * dw.max_n)
+        aligner().align(dw, CONFIG_SCORING, flags=flags, res=res)
+        torch.cuda.synchronize()
+        g = res.to_host()
+        assert (g["status"][bad] == binding.TASK_INVALID_OFFSET).all()
+        st = np.where(g["status"] == binding.TASK_OK_REDONE_INT32, 0, g["status"])
+        assert_same(dict(g, status=st), oracle_align(w, CONFIG_SCORING, idx=ok, stride=2 * dw.max_n),
+                    idx=ok, label=f"cut flags {flags}")
