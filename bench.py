@@ -175,12 +175,14 @@ def serve_run(args, qps):
         "slowest_1pct_mean": {k: round(float(phases[slow, i].mean()), 3)
                               for i, k in enumerate(names)},
     }
-    # the batches whose enqueue took longest: when (ms after the first
-    # measured arrival), how long, and how many requests and reads waited
-    taken = np.array([r.stamps.taken_ns for r in reqs[meas]], np.int64)
-    ntask = np.array([r.n_tasks for r in reqs[meas]], np.int64)
+    # the batches whose enqueue took longest, warm-up included: when (ms
+    # after the first measured arrival; negative in the warm-up), how long,
+    # and how many requests and reads waited
+    taken = np.array([r.stamps.taken_ns for r in reqs], np.int64)
+    ntask = np.array([r.n_tasks for r in reqs], np.int64)
+    launch_all = np.array([r.stamps.launched_ns - r.stamps.taken_ns for r in reqs], np.float64) * 1e-6
     keys, first, inv = np.unique(taken, return_index=True, return_inverse=True)
-    b_launch = phases[first, 1]
+    b_launch = launch_all[first]
     b_reqs = np.bincount(inv)
     b_tasks = np.bincount(inv, weights=ntask)
     t_origin = arr[meas].min()

@@ -71,7 +71,9 @@ extern "C" {
 #define SOAP_DP_PLAIN 0u    /* one int32 launch, one kernel shape for the whole batch */
 #define SOAP_DP_BATCHED 1u  /* device-side length bucketing, packed int16 with int32 redo of
                                tasks outside the int16 range, persistent kernels with a
-                               work queue, autotuned shapes, replayed as a hipGraph */
+                               work queue, autotuned shapes; with SOAPDP_GRAPHS=1 in the
+                               environment each distinct call is captured once and
+                               replayed as a hipGraph */
 #define SOAP_DP_SCORE_ONLY 2u  /* OR-ed with either form: score and ref_end only (same values
                                   as the full call); no traceback: ref_begin is -1, cigar_len
                                   0, `cigar` untouched and may be NULL with any stride */

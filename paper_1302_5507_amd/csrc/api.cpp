@@ -183,7 +183,10 @@ struct soap_dp_ctx {
   // once: launch planning runs on every call
   mutable std::unordered_map<uint32_t, int> occupancy;
   uint64_t use_clock = 0;
-  bool use_graphs = true;
+  // Replay batched calls as captured hipGraphs (opt-in, SOAPDP_GRAPHS=1):
+  // off by default since host crashes of unknown cause were seen only in
+  // processes that captured and replayed graphs.
+  bool use_graphs = false;
   // serving: no growth, no graph capture (see ctx_set_frozen)
   bool frozen = false;
   // multi-candidate work arrays (task slots, reverse complements)
@@ -1292,8 +1295,8 @@ int soap_dp_create(soap_dp_ctx **out, int device_ordinal) {
   ctx->cu_count = prop.multiProcessorCount;
   ctx->arch = "gfx950";
   ctx->classes.assign(std::begin(kDefaultClasses), std::end(kDefaultClasses));
-  const char *ng = std::getenv("SOAPDP_NO_GRAPH");
-  ctx->use_graphs = !(ng && ng[0] && ng[0] != '0');
+  const char *ug = std::getenv("SOAPDP_GRAPHS");
+  ctx->use_graphs = ug && ug[0] && ug[0] != '0';
   {
     DeviceGuard dg(device_ordinal);
     if (hipMalloc(reinterpret_cast<void **>(&ctx->small), kSmallInts * sizeof(int32_t)) != hipSuccess) {
@@ -1453,7 +1456,6 @@ int soap_dp_align_batch(soap_dp_ctx *ctx, const soap_dp_batch *in, const soap_dp
   const soap_dp_scoring es = effective_scoring(sc, flags);
   return align_dispatch(ctx, in, &es, out, st, flags);
 }
-
 
 size_t soap_dp_workspace_bytes(const soap_dp_ctx *ctx, int64_t n_tasks, int32_t max_n,
                                int32_t max_m, uint32_t flags) {

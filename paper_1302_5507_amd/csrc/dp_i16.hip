@@ -260,6 +260,43 @@ void dp_i16_kernel(DpParams p) {
         // The diagonal candidate of column c+1 is formed from the old H[c]
         // before H[c] is overwritten, so every update happens in place.
         uint32_t diag = add16(hd, dconst(Rc[0] ^ T));
+        if constexpr (kScore) {
+          // Score only: the same recurrences in a fixed issue order.  A
+          // packed result read by the next packed instruction costs a wait
+          // state, so the serial chain of a column (I, max, max, new G, then
+          // the next column's I) is interleaved with independent work: the
+          // next column's diagonal constant and this column's D candidate.
+          // The next diagonal reads the old H[c] before the new G overwrites
+          // it, so the update stays in place.
+#pragma unroll
+          for (int c = 0; c < K; ++c) {
+            uint32_t fg = F[c], eg = el;
+            if constexpr (kDirect) {
+              fg = add16(F[c], c_ge);
+              __builtin_amdgcn_sched_barrier(0);
+              eg = add16(el, c_ge);
+              __builtin_amdgcn_sched_barrier(0);
+            }
+            const uint32_t f = max16(H[c], fg);      // D: open from above or extend
+            __builtin_amdgcn_sched_barrier(0);
+            el = max16(hl, eg);                      // I: open from the left or extend
+            __builtin_amdgcn_sched_barrier(0);
+            const uint32_t x = c + 1 < K ? Rc[c + 1] ^ T : 0u;
+            __builtin_amdgcn_sched_barrier(0);
+            const uint32_t tv = max16(diag, el);
+            __builtin_amdgcn_sched_barrier(0);
+            const uint32_t dc = c + 1 < K ? dconst(x) : 0u;
+            __builtin_amdgcn_sched_barrier(0);
+            const uint32_t hv = max16(tv, f);
+            __builtin_amdgcn_sched_barrier(0);
+            if (c + 1 < K) diag = add16(H[c], dc);
+            __builtin_amdgcn_sched_barrier(0);
+            H[c] = add16(hv, c_go);
+            F[c] = f;
+            hl = H[c];
+            __builtin_amdgcn_sched_barrier(0);
+          }
+        } else
 #pragma unroll
         for (int c = 0; c < K; ++c) {
           const uint32_t ad = H[c];   // G of the cell above: D-open candidate
@@ -269,14 +306,10 @@ void dp_i16_kernel(DpParams p) {
           // gap extension: free in the offset form, + S_GE in the direct form
           el = max16(ai, kDirect ? add16(el, c_ge) : el);
           const uint32_t f = max16(ad, kDirect ? add16(F[c], c_ge) : F[c]);
-          // score-only: the old H[c] is dead once the next diagonal and the
-          // D-open candidate are formed; keeping the rest below lets the new
-          // G take its register (otherwise it costs a copy per column pair)
-          if constexpr (kScore) __builtin_amdgcn_sched_barrier(0);
           const uint32_t hv = max16(max16(diag, el), f);
           // differences against the maxima, so the old I and D die at the max
           // and the new values take their registers
-          if constexpr (!kScore) {
+          {
             const uint32_t tA = __builtin_amdgcn_perm(sub16(ai, el), sub16(ad, f), kSignSel);
             const uint32_t tB = __builtin_amdgcn_perm(sub16(diag, hv), sub16(f, hv), kSignSel);
             const uint32_t msk = 0x01010101u << (c & 7);
@@ -294,9 +327,8 @@ void dp_i16_kernel(DpParams p) {
           // keep each column's decisions next to its scores: without this the
           // optimiser sinks them below all columns and every column's
           // candidates stay live (bounds live registers)
-          if constexpr (!kScore) asm volatile("" : "+v"(accA[c / 8]), "+v"(accB[c / 8]));
-          else asm volatile("" : "+v"(H[c]));
-          hl = H[c];   // read after the asm above, so it is the register H[c] holds
+          asm volatile("" : "+v"(accA[c / 8]), "+v"(accB[c / 8]));
+          hl = H[c];
           __builtin_amdgcn_sched_barrier(0);
         }
         hl_out = hl;

@@ -379,6 +379,41 @@ void slot_worker(soap_dp_server *srv, size_t k) {
   }
 }
 
+// The first large host<->device copies on a stream cost milliseconds once
+// (the copy path is set up on first use); a served batch should not pay
+// that.  Move every staging buffer to and from the device once at its full
+// size (or the largest batch the device budget holds), on the slot's stream.
+int warm_copies(soap_dp_server *srv, Slot &s) {
+  int64_t tasks = srv->cfg.max_tasks;
+  uint64_t words = uint64_t(srv->cfg.max_read_words);
+  size_t region = 0;
+  soapdp::serve::BatchLayout L = soapdp::serve::batch_layout(tasks, words, srv->stride);
+  while (!srv->arena.alloc(L.bytes, &region)) {
+    if (tasks == 1 && words == 1) return SOAP_DP_OK;   // the budget holds only tiny batches
+    tasks = std::max<int64_t>(1, tasks / 2);
+    words = std::max<uint64_t>(1, words / 2);
+    L = soapdp::serve::batch_layout(tasks, words, srv->stride);
+  }
+  const DeviceBatch d = carve(srv->arena_base + region, L);
+  const size_t T = size_t(tasks);
+  hipStream_t st = s.stream;
+  const bool ok =
+      hipMemcpyAsync(d.reads, s.h_reads, words * 4, hipMemcpyHostToDevice, st) == hipSuccess &&
+      hipMemcpyAsync(d.rwo, s.h_rwo, T * 8, hipMemcpyHostToDevice, st) == hipSuccess &&
+      hipMemcpyAsync(d.rbo, s.h_rbo, T * 8, hipMemcpyHostToDevice, st) == hipSuccess &&
+      hipMemcpyAsync(d.rl, s.h_rl, T * 4, hipMemcpyHostToDevice, st) == hipSuccess &&
+      hipMemcpyAsync(d.ml, s.h_ml, T * 4, hipMemcpyHostToDevice, st) == hipSuccess &&
+      hipMemcpyAsync(s.h_i32, d.i32, 4 * T * 4, hipMemcpyDeviceToHost, st) == hipSuccess &&
+      hipMemcpyAsync(s.h_status, d.status, T, hipMemcpyDeviceToHost, st) == hipSuccess &&
+      hipMemcpyAsync(s.h_head, d.head, T * soapdp::kCigarHeadWords * 4, hipMemcpyDeviceToHost,
+                     st) == hipSuccess &&
+      hipMemcpyAsync(s.h_rest, d.rest, size_t(L.rest_words_cap) * 4, hipMemcpyDeviceToHost,
+                     st) == hipSuccess &&
+      hipStreamSynchronize(st) == hipSuccess;
+  srv->arena.release(region);
+  return ok ? SOAP_DP_OK : SOAP_DP_EHIP;
+}
+
 // Run one batch of a single empty read through a slot at creation, before
 // the workers start: every kernel a batch launches is loaded, and the
 // context's stream set is made, on the creating thread.
@@ -401,6 +436,7 @@ int warm_up(soap_dp_server *srv, Slot &s) {
   srv->arena.release(s.region);
   s.reqs.clear();
   s.first_task.clear();
+  if (!rc) rc = warm_copies(srv, s);
   return rc;
 }
 

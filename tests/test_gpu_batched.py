@@ -330,14 +330,14 @@ def test_graph_replays_match_eager():
     eager work and synchronisations between, equals an eager run."""
     import torch
     w = workloads.config3(n_reads=5000)
-    os.environ["SOAPDP_NO_GRAPH"] = "1"
-    try:
-        eager_al = binding.Aligner(0)
-    finally:
-        del os.environ["SOAPDP_NO_GRAPH"]
+    eager_al = binding.Aligner(0)
     eager = run(eager_al, w, CONFIG_SCORING)
     eager_al.close()
-    al = binding.Aligner(0)
+    os.environ["SOAPDP_GRAPHS"] = "1"
+    try:
+        al = binding.Aligner(0)
+    finally:
+        del os.environ["SOAPDP_GRAPHS"]
     dw = binding.DeviceWorkload(w)
     res = binding.DeviceResult(w.n_tasks, 2 * dw.max_n)
     for rep in range(4):
