@@ -66,6 +66,7 @@ extern "C" {
 #define SOAP_DP_MAX_READ 512      /* n; the paper does not recommend reads over 500 bp */
 #define SOAP_DP_MAX_WINDOW 8192   /* m */
 #define SOAP_DP_MAX_SCORE_ABS 16384
+#define SOAP_DP_NOALLOC_BYTES ((size_t)256 << 20)   /* fixed memory of soap_dp_align_batch_noalloc */
 
 /* ---- flags for soap_dp_align_batch ---- */
 #define SOAP_DP_PLAIN 0u    /* one int32 launch, one kernel shape for the whole batch */
@@ -189,6 +190,31 @@ int soap_dp_destroy(soap_dp_ctx *ctx);
  */
 int soap_dp_align_batch(soap_dp_ctx *ctx, const soap_dp_batch *in, const soap_dp_scoring *sc,
                         const soap_dp_result *out, void *stream, uint32_t flags);
+
+/*
+ * For callers that cannot allocate device memory (code under hipGraph
+ * capture, tight serving loops, hosts that forbid allocation): the plain
+ * form of soap_dp_align_batch with the same outputs, which allocates
+ * nothing.  Its work counter and decision slots live in one fixed device
+ * array of SOAP_DP_NOALLOC_BYTES per device (256 MiB), which each device
+ * holds from soap_dp_create until the process ends.
+ *  - flags: SOAP_DP_SCORE_ONLY, SOAP_DP_MIN_SCORE, SOAP_DP_READS_INTERLEAVED
+ *    and SOAP_DP_FULL_WINDOW as for soap_dp_align_batch; SOAP_DP_BATCHED and
+ *    other bits are SOAP_DP_EINVAL.  The call always sweeps whole windows in
+ *    one pass (the two-pass arrays would need memory per task).
+ *  - When the decision slots of every workgroup do not fit the array, fewer
+ *    workgroups run (slower, same results).  A window so long that one
+ *    workgroup's slot exceeds the array is SOAP_DP_E2BIG.
+ *  - Every call on one device shares that device's array and overwrites
+ *    what the last call left there: calls that overlap in time on one
+ *    device, from any context or stream, race and give wrong results.
+ *    Order them (one stream, or events).
+ * Argument meaning, layout, ownership and the other errors are those of
+ * soap_dp_align_batch.
+ */
+int soap_dp_align_batch_noalloc(soap_dp_ctx *ctx, const soap_dp_batch *in,
+                                const soap_dp_scoring *sc, const soap_dp_result *out,
+                                void *stream, uint32_t flags);
 
 /* Device bytes of workspace a call with these bounds needs (allocated by the
  * context on first use and kept). */

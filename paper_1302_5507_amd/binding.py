@@ -49,8 +49,9 @@ EXPORTED = [
     "soap_dp_create", "soap_dp_destroy", "soap_dp_align_batch", "soap_dp_workspace_bytes",
     "soap_dp_reserve", "soap_dp_strerror", "soap_dp_last_hip_error", "soap_dp_autotune",
     "soap_dp_get_classes", "soap_dp_set_class_shape", "soap_dp_list_shapes",
-    "soap_dp_align_multi", "soap_dp_mate_rescue",
+    "soap_dp_align_multi", "soap_dp_mate_rescue", "soap_dp_align_batch_noalloc",
 ]
+NOALLOC_BYTES = 256 << 20   # fixed device memory of soap_dp_align_batch_noalloc
 
 
 class Scoring(ctypes.Structure):
@@ -150,6 +151,8 @@ def lib():
         L.soap_dp_align_batch.argtypes = [vp, ctypes.POINTER(Batch), ctypes.POINTER(Scoring),
                                           ctypes.POINTER(Result), vp, ctypes.c_uint32]
         L.soap_dp_align_batch.restype = ctypes.c_int
+        L.soap_dp_align_batch_noalloc.argtypes = L.soap_dp_align_batch.argtypes
+        L.soap_dp_align_batch_noalloc.restype = ctypes.c_int
         L.soap_dp_workspace_bytes.argtypes = [vp, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
                                               ctypes.c_uint32]
         L.soap_dp_workspace_bytes.restype = ctypes.c_size_t
@@ -196,6 +199,12 @@ def soap_dp_destroy(ctx) -> int:
 def soap_dp_align_batch(ctx, batch: Batch, sc: Scoring, res: Result, stream: int, flags: int) -> int:
     return lib().soap_dp_align_batch(ctx, ctypes.byref(batch), ctypes.byref(sc), ctypes.byref(res),
                                      ctypes.c_void_p(stream), int(flags))
+
+
+def soap_dp_align_batch_noalloc(ctx, batch: Batch, sc: Scoring, res: Result, stream: int,
+                                flags: int) -> int:
+    return lib().soap_dp_align_batch_noalloc(ctx, ctypes.byref(batch), ctypes.byref(sc),
+                                             ctypes.byref(res), ctypes.c_void_p(stream), int(flags))
 
 
 def soap_dp_workspace_bytes(ctx, n_tasks, max_n, max_m, flags) -> int:
@@ -555,6 +564,27 @@ class Aligner:
         rc = soap_dp_align_batch(self.ctx, dw.batch(max_n, max_m), sc, res.abi(), stream, flags)
         if rc != SOAP_DP_OK:
             raise SoapDpError(rc, "soap_dp_align_batch")
+        return res
+
+    def align_noalloc(self, dw: DeviceWorkload, scoring=(1, -3, -5, -2), flags=PLAIN, res=None,
+                      stream=None, max_n=None, max_m=None, min_score=None) -> DeviceResult:
+        """The plain form through soap_dp_align_batch_noalloc: no device
+        allocation by the library (its slots are in a fixed device array)."""
+        import torch
+        if res is None:
+            res = DeviceResult(dw.n_tasks, 2 * (max_n or dw.max_n))
+        if stream is None:
+            stream = torch.cuda.current_stream().cuda_stream
+        sc = Scoring(*scoring)
+        if min_score is not None:
+            sc.min_score = int(min_score)
+            flags |= MIN_SCORE
+        if getattr(dw, "interleaved", False):
+            flags |= READS_INTERLEAVED
+        rc = soap_dp_align_batch_noalloc(self.ctx, dw.batch(max_n, max_m), sc, res.abi(), stream,
+                                         flags)
+        if rc != SOAP_DP_OK:
+            raise SoapDpError(rc, "soap_dp_align_batch_noalloc")
         return res
 
     def mate_rescue(self, dm: DeviceMateWorkload, scoring=(1, -3, -5, -2), flags=BATCHED,

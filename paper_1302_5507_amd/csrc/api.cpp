@@ -10,6 +10,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <iterator>
+#include <mutex>
 #include <new>
 #include <string>
 #include <unordered_map>
@@ -195,6 +196,8 @@ struct soap_dp_ctx {
   // two-pass work arrays (pass-1 results, bands, pass-2 order)
   void *band = nullptr;
   size_t band_bytes = 0;
+  // this device's copy of the fixed array behind soap_dp_align_batch_noalloc
+  char *fixed = nullptr;
 };
 
 namespace {
@@ -1275,6 +1278,40 @@ int soapdp::ctx_reserve_for(soap_dp_ctx *ctx, int64_t n_tasks, int32_t max_n, in
   return ensure_scratch(ctx, scratch);
 }
 
+// Fixed device memory of soap_dp_align_batch_noalloc: a 256-byte block for
+// the work counter, then the decision slots.  Each device that loads the
+// library holds its own copy until the process ends.  In host code the
+// array's name is no device address: the address of a device's copy comes
+// from hipGetSymbolAddress (fixed_array_of) and only that is used.
+static __device__ __align__(256) uint32_t scratch[SOAP_DP_NOALLOC_BYTES / 4];
+
+namespace {
+
+constexpr size_t kFixedHead = 256;   // work counter block
+constexpr int kMaxDevices = 64;
+std::mutex g_fixed_mu;
+char *g_fixed[kMaxDevices] = {};
+
+// Address of `device`'s copy of the fixed array, looked up once per device
+// with that device current.
+int fixed_array_of(int device, char **out) {
+  if (device < 0 || device >= kMaxDevices) return SOAP_DP_EINVAL;
+  std::lock_guard<std::mutex> lk(g_fixed_mu);
+  if (!g_fixed[device]) {
+    DeviceGuard dg(device);
+    void *p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+      (void)hipGetLastError();
+      return SOAP_DP_EHIP;
+    }
+    g_fixed[device] = static_cast<char *>(p);
+  }
+  *out = g_fixed[device];
+  return SOAP_DP_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 int soap_dp_create(soap_dp_ctx **out, int device_ordinal) {
@@ -1297,6 +1334,10 @@ int soap_dp_create(soap_dp_ctx **out, int device_ordinal) {
   ctx->classes.assign(std::begin(kDefaultClasses), std::end(kDefaultClasses));
   const char *ug = std::getenv("SOAPDP_GRAPHS");
   ctx->use_graphs = ug && ug[0] && ug[0] != '0';
+  if (const int frc = fixed_array_of(device_ordinal, &ctx->fixed)) {
+    delete ctx;
+    return frc;
+  }
   {
     DeviceGuard dg(device_ordinal);
     if (hipMalloc(reinterpret_cast<void **>(&ctx->small), kSmallInts * sizeof(int32_t)) != hipSuccess) {
@@ -1455,6 +1496,48 @@ int soap_dp_align_batch(soap_dp_ctx *ctx, const soap_dp_batch *in, const soap_dp
   const hipStream_t st = static_cast<hipStream_t>(stream);
   const soap_dp_scoring es = effective_scoring(sc, flags);
   return align_dispatch(ctx, in, &es, out, st, flags);
+}
+
+int soap_dp_align_batch_noalloc(soap_dp_ctx *ctx, const soap_dp_batch *in,
+                                const soap_dp_scoring *sc, const soap_dp_result *out,
+                                void *stream, uint32_t flags) {
+  if (!ctx || !scoring_ok(sc)) return SOAP_DP_EINVAL;
+  if (flags & ~(SOAP_DP_SCORE_ONLY | SOAP_DP_MIN_SCORE | SOAP_DP_FULL_WINDOW |
+                SOAP_DP_READS_INTERLEAVED))
+    return SOAP_DP_EINVAL;
+  const bool score = (flags & SOAP_DP_SCORE_ONLY) != 0;
+  const int rc = batch_ok(in, out, score);
+  if (rc) return rc;
+  if (in->n_tasks == 0) return SOAP_DP_OK;
+  if (!ctx->fixed) return SOAP_DP_EHIP;
+  DeviceGuard dg(ctx->device);
+  const hipStream_t st = static_cast<hipStream_t>(stream);
+  const soap_dp_scoring es = effective_scoring(sc, flags);
+  // the plain form in one pass (whole windows), its decision slots in the
+  // fixed array: fewer workgroups when all of them would not fit
+  const Shape s = plain_shape(in->max_n, in->max_m);
+  if (s.lanes == 0) return SOAP_DP_EINVAL;
+  const size_t avail = SOAP_DP_NOALLOC_BYTES - kFixedHead;
+  LaunchPlan q = plan_launch(ctx, 32, s, in->n_tasks, in->max_m, kind_for(&es, score), avail);
+  if (!score) {
+    const uint64_t slot = q.slot_dwords * 4;
+    if (slot > avail) return SOAP_DP_E2BIG;
+    q.grid = int(std::min<uint64_t>(uint64_t(q.grid), avail / slot));
+    while (q.defer > 1 && q.bytes() > avail) --q.defer;
+  }
+  DpParams p = make_params(in, &es, out);
+  p.score_only = score;
+  p.work_counter = reinterpret_cast<int32_t *>(ctx->fixed);
+  p.scratch = reinterpret_cast<uint32_t *>(ctx->fixed + kFixedHead);
+  p.slot_dwords = q.slot_dwords;
+  p.defer = q.defer;
+  p.read_stride = (flags & SOAP_DP_READS_INTERLEAVED) ? kReadGroup : 1u;
+  // the previous call left its count: clear it (a kernel, so that a
+  // captured call replays the clear)
+  hipError_t e = launch_zero(p.work_counter, 1, st);
+  if (e == hipSuccess) e = launch_dp_i32(s, q.grid, st, p);
+  if (e != hipSuccess) return hip_fail(ctx, e);
+  return SOAP_DP_OK;
 }
 
 size_t soap_dp_workspace_bytes(const soap_dp_ctx *ctx, int64_t n_tasks, int32_t max_n,

@@ -50,6 +50,8 @@ def test_strerror_and_null_arguments():
     for code in (-1, -2, -3, -4, -5, -6):
         assert binding.soap_dp_strerror(code) != "unknown error"
     assert lib.soap_dp_align_batch(None, None, None, None, None, 0) == binding.SOAP_DP_EINVAL
+    assert (lib.soap_dp_align_batch_noalloc(None, None, None, None, None, 0)
+            == binding.SOAP_DP_EINVAL)
     assert lib.soap_dp_create(None, 0) == binding.SOAP_DP_EINVAL
     assert lib.soap_dp_destroy(None) == binding.SOAP_DP_EINVAL
     assert binding.soap_dp_workspace_bytes(None, 10, 100, 250, 0) == 0
