@@ -542,7 +542,9 @@ def main():
                     help="served workload: score pass + band pass per batch instead of one pass "
                          "(SOAP_DP_FULL_WINDOW, the default: served batches are short-window "
                          "and launch-bound, where one pass is faster)")
-    ap.add_argument("--serve-warmup", type=int, default=1000)
+    # about 55 ms of arrivals at 72,000/s: each slot's first few batches
+    # enqueue slowly (up to 10 ms), which is start-up, not steady serving
+    ap.add_argument("--serve-warmup", type=int, default=4000)
     ap.add_argument("--serve-requests", type=int, default=20000)
     ap.add_argument("--form", choices=["plain", "batched", "both"], default="both")
     ap.add_argument("--cpu-tasks", type=int, default=250_000,

@@ -816,17 +816,20 @@ struct TuneData {
   }
 };
 
-// Window lengths a class is timed on: half of its tasks have windows of
-// n + 160 (short windows, as in uneven and served batches), half of
-// 4 n + 160 (long windows, as in low-similarity batches and the score pass
-// of two-pass calls), so a shape is chosen for both.
-int32_t tune_window(int32_t n, int64_t t, int64_t tasks) {
+// Window lengths a class is timed on.  Kernels with traceback: half of the
+// tasks have windows of n + 160 (short windows, as in uneven and served
+// batches), half of 4 n + 160 (long windows, as in low-similarity batches),
+// so a shape is chosen for both.  Score-only kernels mostly run the first
+// pass of two-pass calls, which a class takes only when its windows reach
+// three times its reads: they are timed on windows of 6 n + 160.
+int32_t tune_window(int32_t n, int64_t t, int64_t tasks, bool score) {
+  if (score) return std::min<int32_t>(6 * n + 160, SOAP_DP_MAX_WINDOW);
   return t < tasks / 2 ? n + 160 : std::min<int32_t>(4 * n + 160, SOAP_DP_MAX_WINDOW);
 }
 
 // Synthetic tasks for timing one class: reads of length n copied from random
 // windows (tune_window) with 5% substitutions.
-bool make_tune_data(TuneData &d, int32_t n, int64_t tasks) {
+bool make_tune_data(TuneData &d, int32_t n, int64_t tasks, bool score) {
   const int64_t glen = 1 << 20;
   uint64_t seed = 0x5eed0000u + uint64_t(n);
   std::vector<uint8_t> g(static_cast<size_t>(glen));
@@ -839,7 +842,7 @@ bool make_tune_data(TuneData &d, int32_t n, int64_t tasks) {
   d.max_m = 0;
   d.cells = 0;
   for (int64_t t = 0; t < tasks; ++t) {
-    const int32_t m = tune_window(n, t, tasks);
+    const int32_t m = tune_window(n, t, tasks, score);
     ml[size_t(t)] = m;
     d.max_m = std::max(d.max_m, m);
     d.cells += double(n) * double(m);
@@ -868,7 +871,7 @@ bool make_tune_data(TuneData &d, int32_t n, int64_t tasks) {
 
 std::string cache_header(const soap_dp_ctx *ctx) {
   char buf[128];
-  std::snprintf(buf, sizeof buf, "\"arch\": \"%s\", \"cus\": %d, \"version\": 3", ctx->arch.c_str(),
+  std::snprintf(buf, sizeof buf, "\"arch\": \"%s\", \"cus\": %d, \"version\": 4", ctx->arch.c_str(),
                 ctx->cu_count);
   return buf;
 }
@@ -995,20 +998,30 @@ int autotune(soap_dp_ctx *ctx, std::vector<double> &gcups, std::vector<double> &
   if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) return hip_fail(ctx, hipGetLastError());
   gcups.assign(ctx->classes.size(), 0.0);
   gcups_score.assign(ctx->classes.size(), 0.0);
+  // SOAPDP_TUNE_LOG=1: every timed candidate on stderr
+  const char *tl = std::getenv("SOAPDP_TUNE_LOG");
+  const bool tune_log = tl && tl[0] && tl[0] != '0';
   int rc = SOAP_DP_OK;
   for (size_t k = 0; k < ctx->classes.size() && rc == SOAP_DP_OK; ++k) {
     ClassSpec &c = ctx->classes[k];
     if (c.prec == kPrecI16Direct) continue;   // runs its offset-form class's shapes
     const int32_t n = c.cap;
-    const double m = 0.5 * (tune_window(n, 0, 2) + tune_window(n, 1, 2));   // mean window
-    // about 1.2e10 cells (a few ms per launch, also for the faster
-    // score-only kernels), and never fewer than 65,536 tasks: enough work
+    // about 1.2e10 cells with traceback and 6e10 score only (a few ms per
+    // launch either way), and never fewer than 65,536 tasks: enough work
     // items that the persistent grid runs many rounds, as it does on real
-    // batches
-    const int64_t tasks =
-        std::max<int64_t>(65536, std::min<int64_t>(1 << 20, int64_t(1.2e10 / (double(n) * m))));
-    TuneData d;
-    if (!make_tune_data(d, n, tasks)) { rc = SOAP_DP_ENOMEM; break; }
+    // batches (with too few, the last round's tail decides: a score-only
+    // shape with fewer, longer work items was timed 20% below its speed in
+    // a 500,000-read batch)
+    auto tasks_for = [&](bool score) {
+      const double m = 0.5 * (tune_window(n, 0, 2, score) + tune_window(n, 1, 2, score));
+      const double cells = score ? 6e10 : 1.2e10;
+      return std::max<int64_t>(65536, std::min<int64_t>(1 << 20, int64_t(cells / (double(n) * m))));
+    };
+    TuneData dt, ds;   // windows of the kernels with traceback / score only
+    if (!make_tune_data(dt, n, tasks_for(false), false) || !make_tune_data(ds, n, tasks_for(true), true)) {
+      rc = SOAP_DP_ENOMEM;
+      break;
+    }
     int cnt = 0;
     const Shape *all = c.prec == 16 ? shapes_i16(&cnt) : shapes_i32(&cnt);
     // with traceback, then score only: the best shape of each kind, timed
@@ -1019,6 +1032,7 @@ int autotune(soap_dp_ctx *ctx, std::vector<double> &gcups, std::vector<double> &
     for (int kind = 0; kind < (c.prec == kPrecI32 ? 4 : 2); ++kind) {
       const bool score = kind & 1, general = kind >= 2;
       const soap_dp_scoring &sc = general ? gen_sc : byte_sc;
+      const TuneData &d = score ? ds : dt;
       Shape &slot = general ? (score ? c.gen_score_shape : c.gen_shape)
                             : (score ? c.score_shape : c.shape);
       double best = -1;
@@ -1031,6 +1045,10 @@ int autotune(soap_dp_ctx *ctx, std::vector<double> &gcups, std::vector<double> &
                                         sc.gap_extend))
           continue;
         const double g = time_shape(ctx, c.prec, s, d, n, st, score, sc);
+        if (tune_log)
+          std::fprintf(stderr, "autotune: int%d class %d %s%s %dx%d: %.1f GCUPS\n",
+                       c.prec == kPrecI32 ? 32 : 16, c.cap, score ? "score-only" : "traceback",
+                       general ? " general" : "", s.lanes, s.cells, g);
         if (g > best) { best = g; best_s = s; }
       }
       slot = best_s;

@@ -93,7 +93,7 @@ __device__ __forceinline__ void traceback_task(const DpParams &p, int64_t task, 
       state = next;
     }
     if (!miss) break;
-    tr.fill();
+    tr.fill(i, j);
   }
   int32_t begin = i;
   if (!bad && state == 0 && i == 0 && j > 0) {   // base case M(0, j): j insertions
@@ -168,45 +168,78 @@ __device__ __forceinline__ void flush_block(const Word *stage, int lane, Word *d
 // Decision words of one task as the traceback reads them.  Cell (i, j) (j
 // counted from the read's first base) lies in strip column jp = j + pad - 1,
 // i.e. lane lq = jp / K, column c = jp % K, group w = c / 8, and was computed
-// at step ts = i - 1 + lq.  The block of B steps holding ts for (lq, w) is
-// cached in LDS (`cache`: this lane's B entries); a refill is B contiguous
-// words.  `Decode(word, c)` extracts the nibble of column c.
+// at step ts = i - 1 + lq.  A block is the B steps of one (lq, w) holding ts.
+// A refill loads up to NB blocks at once into this lane's LDS cache: the
+// missed block, the one before it (the walk only goes to lower steps and
+// columns), and the same two of the column group to the left (the previous
+// lane's last group when w = 0, whose steps are one lower): one memory wait
+// serves a diagonal run of about 2B rows and 16 columns.  `Decode(word, c)`
+// extracts the nibble of column c.
+// Blocks one refill loads: up to four, as many as the sweep's staging
+// buffer (W groups of B steps per lane) has room for.
+__host__ __device__ constexpr int tracer_blocks(int W) { return W < 4 ? W : 4; }
+
 template <class Word, int K, int W, int B, class Decode>
 struct BlockTracer {
+  static constexpr int NB = tracer_blocks(W);
   const Word *slot;   // the task's slot
-  Word *cache;        // B LDS entries, 16-byte aligned
+  Word *cache;        // NB * B LDS entries, 16-byte aligned
   int32_t lane0;      // first lane of the task in the wavefront
   int32_t pad;
   Decode decode;
-  int32_t lq = -1, w = -1, blk = -1;   // cached block
-  int32_t want_lq = 0, want_w = 0, want_blk = 0;
+  int32_t tag[NB];    // cached block k: (lq * W + w) << 20 | blk, -1 if none
 
-  __device__ __forceinline__ bool get(int32_t i, int32_t j, uint32_t &nib) {
+  __device__ __forceinline__ static int32_t key(int32_t lq, int32_t w, int32_t blk) {
+    return (lq * W + w) << 20 | blk;
+  }
+  // strip lane, column group, column and sweep step of cell (i, j)
+  __device__ __forceinline__ void locate(int32_t i, int32_t j, int32_t &lq, int32_t &w, uint32_t &c,
+                                         int32_t &ts) const {
     const uint32_t jp = (uint32_t)(j + pad - 1);
-    const int32_t lq_ = (int32_t)(jp / K);
-    const uint32_t c = jp - (uint32_t)lq_ * K;
-    const int32_t w_ = (int32_t)(c >> 3);
-    const int32_t ts = i - 1 + lq_;   // >= 0: i >= 1
-    const int32_t blk_ = ts / B;
-    if (lq_ != lq || w_ != w || blk_ != blk) {
-      want_lq = lq_;
-      want_w = w_;
-      want_blk = blk_;
-      return false;
-    }
-    nib = decode(cache[ts & (B - 1)], c);
+    lq = (int32_t)(jp / K);
+    c = jp - (uint32_t)lq * K;
+    w = (int32_t)(c >> 3);
+    ts = i - 1 + lq;   // >= 0: i >= 1
+  }
+  __device__ __forceinline__ bool get(int32_t i, int32_t j, uint32_t &nib) {
+    int32_t lq, w, ts;
+    uint32_t c;
+    locate(i, j, lq, w, c, ts);
+    const int32_t k_ = key(lq, w, ts / B);
+    int32_t hit = -1;
+#pragma unroll
+    for (int k = 0; k < NB; ++k) hit = tag[k] == k_ ? k : hit;
+    if (hit < 0) return false;
+    nib = decode(cache[hit * B + (ts & (B - 1))], c);
     return true;
   }
-  __device__ __forceinline__ void fill() {
+  // Refill after get(i, j) missed.
+  __device__ __forceinline__ void fill(int32_t i, int32_t j) {
     constexpr int V = B * (int)sizeof(Word) / 16;
-    const uint4 *src = reinterpret_cast<const uint4 *>(
-        slot + ((uint64_t)(want_blk * W + want_w) * kWave + (uint64_t)(lane0 + want_lq)) * B);
-    uint4 *dst = reinterpret_cast<uint4 *>(cache);
+    int32_t lq0, w0, ts0;
+    uint32_t c0;
+    locate(i, j, lq0, w0, c0, ts0);
+    // candidate blocks: (lq, w) at the missed step's block and the one
+    // before, then the group to the left at its own steps
+    const bool left_lane = w0 == 0;
+    const int32_t lq2 = left_lane ? lq0 - 1 : lq0;
+    const int32_t w2 = left_lane ? W - 1 : w0 - 1;
+    const int32_t ts2 = left_lane ? ts0 - 1 : ts0;
 #pragma unroll
-    for (int k = 0; k < V; ++k) dst[k] = src[k];
-    lq = want_lq;
-    w = want_w;
-    blk = want_blk;
+    for (int k = 0; k < NB; ++k) {
+      const int32_t lq = k < 2 ? lq0 : lq2;
+      const int32_t w = k < 2 ? w0 : w2;
+      const int32_t blk = (k < 2 ? ts0 : ts2) / B - (k & 1);
+      const bool ok = lq >= 0 && blk >= 0 && (k < 2 || ts2 >= 0);
+      tag[k] = ok ? key(lq, w, blk) : -1;
+      if (ok) {
+        const uint4 *src = reinterpret_cast<const uint4 *>(
+            slot + ((uint64_t)(blk * W + w) * kWave + (uint64_t)(lane0 + lq)) * B);
+        uint4 *dst = reinterpret_cast<uint4 *>(cache + k * B);
+#pragma unroll
+        for (int v = 0; v < V; ++v) dst[v] = src[v];
+      }
+    }
   }
 };
 
@@ -214,6 +247,8 @@ template <class Word, int K, int W, int B, class Decode>
 __device__ __forceinline__ BlockTracer<Word, K, W, B, Decode> make_tracer(
     const Word *slot, Word *cache, int32_t lane0, int32_t pad, Decode dec) {
   BlockTracer<Word, K, W, B, Decode> t{slot, cache, lane0, pad, dec};
+#pragma unroll
+  for (int k = 0; k < t.NB; ++k) t.tag[k] = -1;
   return t;
 }
 
@@ -222,7 +257,7 @@ __device__ __forceinline__ BlockTracer<Word, K, W, B, Decode> make_tracer(
 template <class Word, int W, int B>
 struct StageOrCache {
   static constexpr int kStageWords = W * B * kStageRow;
-  static constexpr int kCacheWords = kWave * B;
+  static constexpr int kCacheWords = kWave * B * tracer_blocks(W);
   static constexpr int kWords = kStageWords > kCacheWords ? kStageWords : kCacheWords;
 };
 

@@ -413,7 +413,7 @@ void dp_i16_kernel(DpParams p) {
             const uint2 *slot = reinterpret_cast<const uint2 *>(slots + (uint64_t)rs * slot_dwords);
             const uint32_t shA = 8u * (2 + h), shD = 8u * h;
             auto tr = make_tracer<uint2, K, W, B>(
-                slot, s_lds + lane * B, gq * L, tpad, [shA, shD](uint2 v, uint32_t c) {
+                slot, s_lds + lane * B * tracer_blocks(W), gq * L, tpad, [shA, shD](uint2 v, uint32_t c) {
                   const uint32_t b = c & 7u;
                   return ((v.x >> (shA + b)) & 1u) << 3 | ((v.x >> (shD + b)) & 1u) << 2 |
                          ((v.y >> (shA + b)) & 1u) << 1 | ((v.y >> (shD + b)) & 1u);

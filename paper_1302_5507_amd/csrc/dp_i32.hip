@@ -209,37 +209,6 @@ void dp_i32_kernel(DpParams p) {
         // The diagonal candidate of column c+1 is formed from the old H[c]
         // before H[c] is overwritten, so every update happens in place.
         int32_t diag = hd + delta(0);
-        if constexpr (kScore) {
-          // Score only: the same recurrences in a fixed order, with no
-          // register pinning (an empty asm statement costs a wait state per
-          // column).  The next diagonal reads the old H[c] before the new G
-          // overwrites it, so the update stays in place.
-#pragma unroll
-          for (int c = 0; c < K; ++c) {
-            // general variant: the match test of the next column goes first,
-            // away from the select that reads it
-            bool eq = false;
-            if constexpr (!kByte)
-              if (c + 1 < K) eq = Rc[c + 1] == T;
-            __builtin_amdgcn_sched_barrier(0);
-            const int32_t f = max(H[c], F[c]);       // D: open from above or extend
-            __builtin_amdgcn_sched_barrier(0);
-            el = max(hl, el);                        // I: open from the left or extend
-            __builtin_amdgcn_sched_barrier(0);
-            const int32_t h = max(max(diag, el), f);
-            __builtin_amdgcn_sched_barrier(0);
-            if constexpr (kByte) {
-              if (c + 1 < K) diag = H[c] + delta(c + 1);
-            } else {
-              if (c + 1 < K) diag = H[c] + (eq ? c_ma : Mi[c + 1]);
-            }
-            __builtin_amdgcn_sched_barrier(0);
-            H[c] = h + c_go;
-            F[c] = f;
-            hl = H[c];
-            __builtin_amdgcn_sched_barrier(0);
-          }
-        } else
 #pragma unroll
         for (int c = 0; c < K; ++c) {
           const int32_t ad = H[c];   // G of the cell above: D-open candidate
@@ -248,8 +217,12 @@ void dp_i32_kernel(DpParams p) {
           const int32_t ai = hl;     // G of the cell to the left: I-open candidate
           el = max(ai, el);
           const int32_t f = max(ad, F[c]);
+          // score-only: the old H[c] is dead once the next diagonal and the
+          // D-open candidate are formed; keeping the rest below lets the new
+          // G take its register (otherwise it costs a copy per column)
+          if constexpr (kScore) __builtin_amdgcn_sched_barrier(0);
           const int32_t h = max(max(diag, el), f);
-          {
+          if constexpr (!kScore) {
             uint32_t a = acc[c / 8];
             a = push_sign(a, ai - el);
             a = push_sign(a, ad - f);
@@ -263,8 +236,9 @@ void dp_i32_kernel(DpParams p) {
           // keep each column's decisions next to its scores: without this the
           // optimiser sinks them below all columns and every column's
           // candidates stay live (bounds live registers)
-          asm volatile("" : "+v"(acc[c / 8]));
-          hl = H[c];
+          if constexpr (!kScore) asm volatile("" : "+v"(acc[c / 8]));
+          else asm volatile("" : "+v"(H[c]));
+          hl = H[c];   // read after the asm above, so it is the register H[c] holds
           __builtin_amdgcn_sched_barrier(0);
         }
         if constexpr (!kScore)
@@ -321,7 +295,7 @@ void dp_i32_kernel(DpParams p) {
             const int rs = lane / G, gq = lane % G;
             const uint32_t *slot = slots + (uint64_t)rs * slot_dwords;
             auto tr = make_tracer<uint32_t, K, W, B>(
-                slot, s_lds + lane * B, gq * L, tpad,
+                slot, s_lds + lane * B * tracer_blocks(W), gq * L, tpad,
                 [](uint32_t wd, uint32_t c) { return (wd >> (4 * (7 - (c & 7)))) & 15u; });
             traceback_task(p, tk, tn, tend, (int32_t)slot_rows, tr);
           }
