@@ -38,17 +38,28 @@ OPS_PER_CELL_SCORE = 10      # score-only pass: no decision comparisons
 PEAK_INT32_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12   # CUs x SIMDs x lanes x clock = 39.3 T lane-ops/s
 PEAK_INT16_TOPS = 2 * PEAK_INT32_TOPS            # packed 2 x int16 per lane
 
-# HBM traffic of the dominant kernel per launch, from two rocprofv3 --pmc
-# runs (FETCH_SIZE, WRITE_SIZE; KiB per dispatch) scaled by what the same
-# counters read for a plain 1 GiB device copy (FETCH x 2.000, WRITE x 1.000).
-# Keyed by (workload, form); valid only for the kernel sources fingerprinted
-# (any change to them makes `traffic` null until the counters are re-taken).
+# HBM traffic of one call (the score-pass and decision-pass DP kernels; the
+# band and fix-up kernels move a few MB), from two rocprofv3 --pmc runs
+# (FETCH_SIZE, WRITE_SIZE; KiB per dispatch, summed over the call's
+# kernels) scaled by what the same counters read for a plain 1 GiB device
+# copy (FETCH x 2.000, WRITE x 1.000).  Keyed by (workload, form); valid
+# only for the kernel sources fingerprinted (any change to them makes
+# `traffic` null until the counters are re-taken).
 KERNEL_SOURCES = ("api.cpp", "band.h", "band.hip", "batch.h", "batch.hip", "dp_device.h",
                   "dp_i16.hip", "dp_i32.hip", "dp_internal.h")
 TRAFFIC = {
-    ("config2", "plain"): {"fingerprint": "574b7377cdc0bf7b", "kernel": "dp_i32_kernel<4,25,byte>",
-                           "fetch_kib": 2456014, "write_kib": 16142110,
+    # per call: the score-pass and decision-pass kernels together; the
+    # batched entry holds for the class shapes named (the autotuner runs at
+    # the start of every bench run and may pick others)
+    ("config5", "plain"): {"fingerprint": "134d4c417dd7e120",
+                           "kernel": "dp_i32_kernel<4,38,byte> score pass + decision pass",
+                           "fetch_kib": 2011734, "write_kib": 9366714,
                            "fetch_scale": 2.000, "write_scale": 1.000},
+    ("config5", "batched"): {"fingerprint": "134d4c417dd7e120",
+                             "kernel": "dp_i16_kernel class 152: 4x38 score pass + 8x19 decision pass",
+                             "shapes": {"i16/152": "8x19"},
+                             "fetch_kib": 2504345, "write_kib": 11395007,
+                             "fetch_scale": 2.000, "write_scale": 1.000},
 }
 
 
@@ -63,24 +74,37 @@ def kernel_fingerprint() -> str:
     return h.hexdigest()[:16]
 
 
-def traffic_bytes(workload: str, form: str):
-    t = TRAFFIC.get((workload, form))
+def _entry_holds(t, shapes) -> bool:
+    """The counters were taken on these sources and, for the batched form,
+    with these class shapes."""
     if t is None or t["fingerprint"] != kernel_fingerprint():
+        return False
+    want = t.get("shapes")
+    return not want or all((shapes or {}).get(k) == v for k, v in want.items())
+
+
+def traffic_bytes(workload: str, form: str, shapes=None):
+    t = TRAFFIC.get((workload, form))
+    if not _entry_holds(t, shapes):
         return None
     return int(round((t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"]) * 1024))
 
 
-# VALU wave-instructions per dispatch of the dominant kernel (rocprofv3
-# --pmc SQ_INSTS_VALU), same keying and fingerprint rule as TRAFFIC.  The
-# issue fraction divides them by what the chip can issue in the measured
-# kernel time: one wave64 VALU instruction per SIMD every 4 cycles.
+# VALU wave-instructions of one call's DP kernels (rocprofv3 --pmc
+# SQ_INSTS_VALU), same keying and fingerprint rule as TRAFFIC.  The issue
+# fraction divides them by what the chip can issue in the measured device
+# time of the call: one wave64 VALU instruction per SIMD every 4 cycles.
 VALU_ISSUE_PER_S = 256 * 4 * 2.4e9 / 4
-VALU_INSTS = {}
+VALU_INSTS = {
+    ("config5", "plain"): {"fingerprint": "134d4c417dd7e120", "sq_insts_valu": 11015783834},
+    ("config5", "batched"): {"fingerprint": "134d4c417dd7e120", "shapes": {"i16/152": "8x19"},
+                             "sq_insts_valu": 7980621280},
+}
 
 
-def valu_issue_frac(workload: str, form: str, kernel_ms: float):
+def valu_issue_frac(workload: str, form: str, kernel_ms: float, shapes=None):
     t = VALU_INSTS.get((workload, form))
-    if t is None or t["fingerprint"] != kernel_fingerprint():
+    if not _entry_holds(t, shapes):
         return None
     return round(t["sq_insts_valu"] / (kernel_ms * 1e-3 * VALU_ISSUE_PER_S), 4)
 
@@ -635,20 +659,23 @@ def main():
             "unit": "TOP/s",
             "frac": d["valu_frac"],
             "traffic": None if args.score_only or args.full_window or args.score_scale != 1
-                       else traffic_bytes(args.workload, main_form),
+                       else traffic_bytes(args.workload, main_form, d.get("shapes")),
             "ops_model": ops_model,
             "kernel_ms": d["device_ms"],
         },
         "forms": {f: v[2] for f, v in legs.items()},
     }
     default_run = not (args.score_only or args.full_window or args.score_scale != 1)
-    issue = valu_issue_frac(args.workload, main_form, d["device_ms"])
+    issue = valu_issue_frac(args.workload, main_form, d["device_ms"], d.get("shapes"))
     if issue is not None and default_run:
         line["roofline"]["valu_issue_frac"] = issue
     for f in legs:
-        fi = valu_issue_frac(args.workload, f, legs[f][2]["device_ms"])
+        fi = valu_issue_frac(args.workload, f, legs[f][2]["device_ms"], legs[f][2].get("shapes"))
         if fi is not None and default_run:
             line["forms"][f]["valu_issue_frac"] = fi
+        tf = traffic_bytes(args.workload, f, legs[f][2].get("shapes"))
+        if tf is not None and default_run:
+            line["forms"][f]["traffic"] = tf
     if args.workload == "config5" and not args.no_extra and default_run:
         del w
         print("bench: generating config3", file=sys.stderr, flush=True)

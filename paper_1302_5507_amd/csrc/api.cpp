@@ -29,6 +29,8 @@ using namespace soapdp;
 namespace {
 
 constexpr size_t kScratchCap = size_t(16) << 30;  // decision-bit scratch budget
+constexpr size_t kForkStreams = 2;   // forked streams of a large batched call (see enqueue_batched)
+constexpr int64_t kSpreadTasks = 262144;   // below: one forked stream per class
 // Small device buffer (int32 units): hist | max_m | offset | cursor |
 // work_counter | defer, then two uint64 tables (slot_dwords, scratch_off),
 // then the int32 re-run's task count and work counter.
@@ -173,8 +175,8 @@ struct soap_dp_ctx {
   // batched form
   std::vector<ClassSpec> classes;
   hipStream_t capture_stream = nullptr;
-  // class kernels run concurrently: one stream and join event per class,
-  // forked from the caller's stream after bucketing
+  // class kernels run on streams forked from the caller's stream after
+  // bucketing (one join event each; see enqueue_batched)
   std::vector<hipStream_t> class_streams;
   std::vector<hipEvent_t> join_events;
   hipEvent_t fork_event = nullptr;
@@ -676,20 +678,35 @@ hipError_t enqueue_batched(soap_dp_ctx *ctx, const soap_dp_batch *in, const soap
   p.redo_count = b.redo_count;
   hipError_t e = launch_bucketing(p, class_table(ctx, live, bp), b, order, stream);
   if (e != hipSuccess) return e;
-  // fork: every class kernel waits for the bucketing only, then they run
-  // concurrently; the caller's stream joins them all
+  // Class kernels, largest capacity first.  A large batch runs its largest
+  // live class on the caller's stream and the others, taking turns, on
+  // kForkStreams forked streams, which wait for the bucketing only; the
+  // caller's stream joins them at the end.  The classes that have work
+  // overlap (one kernel's tail leaves CUs that another fills), while at
+  // most kForkStreams kernels sit pending beside the largest class: with
+  // one stream per class, a batch of 100 bp reads (all in one class) had a
+  // dozen kernels of empty classes pending beside its class kernel and took
+  // 8.0 ms per call against 7.5, and with one forked stream the uneven batch
+  // lost its overlap (20.9 against 19.7 ms).  A small batch (under
+  // kSpreadTasks reads, as served batches are) gives every class its own
+  // forked stream: its class kernels are short, and running them all at
+  // once sets its latency (served p50 at 26,000 requests/s: 2.7 ms against
+  // 4.7 with the large-batch arrangement).
+  const bool spread = in->n_tasks < kSpreadTasks;
   if ((e = hipEventRecord(ctx->fork_event, stream)) != hipSuccess) return e;
   p.task_list = ctx->task_list;
   p.scratch = static_cast<uint32_t *>(ctx->scratch);
-  // Largest capacity first: the classes of long reads run longest, and the
-  // class streams share a few hardware queues, where a kernel enqueued
-  // behind another waits for it to finish.  Longest first keeps the batch
-  // close to its longest kernel.
-  for (size_t li = live.size(); li-- > 0;) {
+  const size_t nl = live.size();
+  for (size_t li = nl; li-- > 0;) {
     const int k = live[li];
     const ClassSpec &c = ctx->classes[size_t(k)];
-    hipStream_t cs = ctx->class_streams[li];
-    if ((e = hipStreamWaitEvent(cs, ctx->fork_event, 0)) != hipSuccess) return e;
+    const size_t turn = nl - 2 - li;   // launch order among the forked classes
+    const size_t fs = spread ? li : turn % kForkStreams;
+    const bool on_caller = !spread && li == nl - 1;
+    hipStream_t cs = on_caller ? stream : ctx->class_streams[fs];
+    if (!on_caller && (spread || turn < kForkStreams) &&
+        (e = hipStreamWaitEvent(cs, ctx->fork_event, 0)) != hipSuccess)
+      return e;
     DpParams q = p;
     q.task_off = b.offset + k;
     q.task_count = b.hist + k;
@@ -702,8 +719,10 @@ hipError_t enqueue_batched(soap_dp_ctx *ctx, const soap_dp_batch *in, const soap
     if ((e = launch_shape(c.prec, shape_of(c, q.score_only != 0, bp.v), bp.grids[li], cs, q)) !=
         hipSuccess)
       return e;
-    if ((e = hipEventRecord(ctx->join_events[li], cs)) != hipSuccess) return e;
-    if ((e = hipStreamWaitEvent(stream, ctx->join_events[li], 0)) != hipSuccess) return e;
+    // join a forked stream after its last kernel
+    if (on_caller || (!spread && turn + kForkStreams < nl - 1)) continue;
+    if ((e = hipEventRecord(ctx->join_events[fs], cs)) != hipSuccess) return e;
+    if ((e = hipStreamWaitEvent(stream, ctx->join_events[fs], 0)) != hipSuccess) return e;
   }
   if (bp.redo) {
     // the int32 re-run of the tasks the direct-form kernels flagged, after
@@ -728,7 +747,7 @@ int align_batched(soap_dp_ctx *ctx, const soap_dp_batch *in, const soap_dp_scori
   const std::vector<int> live = live_classes(ctx, in->max_n, in->max_m, sc, mode);
   int rc = ensure_task_buffers(ctx, in->n_tasks);
   if (rc) return rc;
-  rc = ensure_class_streams(ctx, live.size());
+  rc = ensure_class_streams(ctx, in->n_tasks < kSpreadTasks ? live.size() : kForkStreams);
   if (rc) return rc;
   const BatchedPlan bp = batched_plan(ctx, in->n_tasks, in->max_n, in->max_m,
                                       kind_for(sc, mode == kModeScore).v, mode, live,
@@ -1288,10 +1307,11 @@ int soapdp::ctx_reserve_for(soap_dp_ctx *ctx, int64_t n_tasks, int32_t max_n, in
     scratch -= size_t(n_tasks) * 9;
     int rc = ensure_task_buffers(ctx, n_tasks);
     if (rc) return rc;
-    // one stream per class a call with these bounds can populate
+    // the forked streams of the class kernels: one per class a call with
+    // these bounds can populate (small batches), at least kForkStreams
     bool redo = false;
     const size_t n_live = reserve_classes(ctx, max_n, max_m, sc, &redo).size();
-    if ((rc = ensure_class_streams(ctx, n_live)) != SOAP_DP_OK) return rc;
+    if ((rc = ensure_class_streams(ctx, std::max(n_live, kForkStreams))) != SOAP_DP_OK) return rc;
   }
   return ensure_scratch(ctx, scratch);
 }

@@ -69,8 +69,11 @@ constexpr uint32_t kSignSel = 0x0b0a0908u;   // v_perm: replicate the four sign 
 }  // namespace
 
 // Shapes with at most 8 columns per lane fit five wavefronts per SIMD (96
-// VGPRs) without spilling once the compiler is asked to; wider ones would
-// spill and keep the default.
+// VGPRs) without spilling once the compiler is asked to; wider ones keep
+// the default.  (Asking 4 waves of the 13-column kernels with traceback and
+// 3 of the 19-column ones also fits without spilling, but served batches
+// then ran 3% below capacity and 9% slower at low load: their short class
+// kernels lose more to the slower waves than they gain.)
 // kScore: score and end only -- no decision bits, no scratch, no traceback.
 template <int L, int K, bool kScore, bool kDirect>
 __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(K <= 8 ? 5 : 1)))
