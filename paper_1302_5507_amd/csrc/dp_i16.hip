@@ -68,15 +68,18 @@ constexpr uint32_t kSignSel = 0x0b0a0908u;   // v_perm: replicate the four sign 
 
 }  // namespace
 
-// Shapes with at most 8 columns per lane fit five wavefronts per SIMD (96
-// VGPRs) without spilling once the compiler is asked to; wider ones keep
-// the default.  (Asking 4 waves of the 13-column kernels with traceback and
-// 3 of the 19-column ones also fits without spilling, but served batches
-// then ran 3% below capacity and 9% slower at low load: their short class
-// kernels lose more to the slower waves than they gain.)
+// Waves per SIMD asked of the register allocator.  Shapes with at most 8
+// columns per lane fit five (96 VGPRs) without spilling once the compiler
+// is asked to.  The offset-form score sweeps are asked for three: the
+// 4 x 38 one then spills a few values outside its row loop and made the
+// low-similarity batched call 0.8% faster.  The kernels with traceback keep
+// the default: asked for 4 waves at 13 columns and 3 at 19 (which also fit
+// without spilling), served batches ran 3% below capacity and 9% slower at
+// low load, their short class kernels losing more to the slower waves than
+// they gain.
 // kScore: score and end only -- no decision bits, no scratch, no traceback.
 template <int L, int K, bool kScore, bool kDirect>
-__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(K <= 8 ? 5 : 1)))
+__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(K <= 8 ? 5 : (kScore && !kDirect ? 3 : 1))))
 void dp_i16_kernel(DpParams p) {
   static_assert(kWave % L == 0, "lanes per task must divide the wavefront");
   constexpr int G = kWave / L;       // lane groups per wavefront
