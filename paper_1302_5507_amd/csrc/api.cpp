@@ -258,6 +258,7 @@ bool shape_compiled(int prec, Shape s) {
 struct Kind {
   Variant v;
   bool score;
+  bool dense = false;   // int16 kernels with traceback: the variant for more waves per SIMD
 };
 
 Kind kind_for(const soap_dp_scoring *sc, bool score) {
@@ -270,11 +271,12 @@ int occupancy(const soap_dp_ctx *ctx, int prec, Shape s, Kind k) {
   if (prec == 32 && k.v == kEither)
     return std::max(occupancy(ctx, prec, s, Kind{kGeneral, k.score}),
                     occupancy(ctx, prec, s, Kind{kByte, k.score}));
-  const uint32_t key = uint32_t(k.score) << 26 | uint32_t(k.v) << 24 | uint32_t(prec) << 16 |
-                       uint32_t(s.lanes) << 8 | uint32_t(s.cells);
+  const bool dense = k.dense && packed16(prec);
+  const uint32_t key = uint32_t(dense) << 27 | uint32_t(k.score) << 26 | uint32_t(k.v) << 24 |
+                       uint32_t(prec) << 16 | uint32_t(s.lanes) << 8 | uint32_t(s.cells);
   auto it = ctx->occupancy.find(key);
   if (it != ctx->occupancy.end()) return it->second;
-  int o = packed16(prec) ? occupancy_dp_i16(s, k.score, prec == kPrecI16Direct)
+  int o = packed16(prec) ? occupancy_dp_i16(s, k.score, prec == kPrecI16Direct, dense)
                          : occupancy_dp_i32(s, k.v == kByte, k.score);
   o = o < 1 ? 1 : o;
   ctx->occupancy.emplace(key, o);
@@ -446,8 +448,9 @@ LaunchPlan plan_launch(const soap_dp_ctx *ctx, int prec, Shape s, int64_t n_task
   return q;
 }
 
-hipError_t launch_shape(int prec, Shape s, int grid, hipStream_t stream, const DpParams &p) {
-  return packed16(prec) ? launch_dp_i16(s, grid, stream, p, prec == kPrecI16Direct)
+hipError_t launch_shape(int prec, Shape s, int grid, hipStream_t stream, const DpParams &p,
+                        bool dense = false) {
+  return packed16(prec) ? launch_dp_i16(s, grid, stream, p, prec == kPrecI16Direct, dense)
                         : launch_dp_i32(s, grid, stream, p);
 }
 
@@ -571,6 +574,7 @@ bool any_direct(const soap_dp_ctx *ctx, const std::vector<int> &live) {
 // by then), at deferral 1; the budget holds its full grid of slots too.
 struct BatchedPlan {
   Variant v = kByte;             // int32 diagonal of the call's scoring
+  bool dense = false;            // large call: int16 kernels with traceback at more waves per SIMD
   std::vector<char> cls_score;   // per class: score-only kernel (no decision scratch)
   std::vector<int> grids;
   uint64_t budget_dwords = 0;
@@ -585,11 +589,12 @@ BatchedPlan batched_plan(const soap_dp_ctx *ctx, int64_t n_tasks, int32_t max_n,
                          Variant v, Mode mode, const std::vector<int> &live, bool redo) {
   BatchedPlan bp;
   bp.v = v;
+  bp.dense = n_tasks >= kSpreadTasks;
   for (const ClassSpec &c : ctx->classes) bp.cls_score.push_back(class_score(c, max_m, mode));
   uint64_t need = 0, want = 0;
   for (int cls : live) {
     const ClassSpec &c = ctx->classes[size_t(cls)];
-    const Kind k{v, bp.cls_score[size_t(cls)] != 0};
+    const Kind k{v, bp.cls_score[size_t(cls)] != 0, bp.dense};
     const LaunchPlan q =
         plan_launch(ctx, c.prec, shape_of(c, k.score, v), n_tasks, max_m, k, SIZE_MAX);
     bp.grids.push_back(q.grid);
@@ -716,8 +721,8 @@ hipError_t enqueue_batched(soap_dp_ctx *ctx, const soap_dp_batch *in, const soap
     q.scratch_off_dev = b.scratch_off + k;
     q.ok_status = packed16(c.prec) ? kTaskOk : kTaskRedone;
     q.score_only = bp.cls_score[size_t(k)];
-    if ((e = launch_shape(c.prec, shape_of(c, q.score_only != 0, bp.v), bp.grids[li], cs, q)) !=
-        hipSuccess)
+    if ((e = launch_shape(c.prec, shape_of(c, q.score_only != 0, bp.v), bp.grids[li], cs, q,
+                          bp.dense)) != hipSuccess)
       return e;
     // join a forked stream after its last kernel
     if (on_caller || (!spread && turn + kForkStreams < nl - 1)) continue;

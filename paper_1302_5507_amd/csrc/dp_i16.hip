@@ -72,14 +72,21 @@ constexpr uint32_t kSignSel = 0x0b0a0908u;   // v_perm: replicate the four sign 
 // columns per lane fit five (96 VGPRs) without spilling once the compiler
 // is asked to.  The offset-form score sweeps are asked for three: the
 // 4 x 38 one then spills a few values outside its row loop and made the
-// low-similarity batched call 0.8% faster.  The kernels with traceback keep
-// the default: asked for 4 waves at 13 columns and 3 at 19 (which also fit
-// without spilling), served batches ran 3% below capacity and 9% slower at
-// low load, their short class kernels losing more to the slower waves than
-// they gain.
+// low-similarity batched call 0.8% faster.  The kernels with traceback at
+// 13-14 and 19-20 columns sit a few registers above four and three waves;
+// their dense variant (kDense) is asked for those and fits without
+// spilling.  It serves large calls only: there each class kernel has work
+// for many times its resident waves.  In served batches, whose class
+// kernels are short and run side by side, it ran 2% below capacity and
+// slower at low load, so small calls keep the default.
+constexpr int waves_i16(int K, bool score, bool direct, bool dense) {
+  return K <= 8 ? 5 : (score && !direct ? 3 : (!dense ? 1 : (K <= 16 ? 4 : 3)));
+}
+constexpr bool has_dense_i16(int K) { return K == 13 || K == 14 || K == 19 || K == 20; }
+
 // kScore: score and end only -- no decision bits, no scratch, no traceback.
-template <int L, int K, bool kScore, bool kDirect>
-__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(K <= 8 ? 5 : (kScore && !kDirect ? 3 : 1))))
+template <int L, int K, bool kScore, bool kDirect, bool kDense>
+__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(waves_i16(K, kScore, kDirect, kDense))))
 void dp_i16_kernel(DpParams p) {
   static_assert(kWave % L == 0, "lanes per task must divide the wavefront");
   constexpr int G = kWave / L;       // lane groups per wavefront
@@ -459,46 +466,71 @@ uint64_t slot_dwords_i16(Shape s, int32_t max_m) {
   return steps * uint64_t((s.cells + 7) / 8) * kWave * 2;
 }
 
+template <int L, int K, bool kScore, bool kDirect>
+void launch_v16(int grid, hipStream_t stream, const DpParams &p, bool dense) {
+  if constexpr (!kScore && has_dense_i16(K)) {
+    if (dense) {
+      hipLaunchKernelGGL((dp_i16_kernel<L, K, kScore, kDirect, true>), dim3(grid), dim3(kWave), 0,
+                         stream, p);
+      return;
+    }
+  }
+  hipLaunchKernelGGL((dp_i16_kernel<L, K, kScore, kDirect, false>), dim3(grid), dim3(kWave), 0,
+                     stream, p);
+}
+
 template <int L, int K>
-hipError_t launch_i16(int grid, hipStream_t stream, const DpParams &p, bool direct) {
+hipError_t launch_i16(int grid, hipStream_t stream, const DpParams &p, bool direct, bool dense) {
   const bool score = p.score_only != 0;
   if (score && direct)
-    hipLaunchKernelGGL((dp_i16_kernel<L, K, true, true>), dim3(grid), dim3(kWave), 0, stream, p);
+    launch_v16<L, K, true, true>(grid, stream, p, dense);
   else if (score)
-    hipLaunchKernelGGL((dp_i16_kernel<L, K, true, false>), dim3(grid), dim3(kWave), 0, stream, p);
+    launch_v16<L, K, true, false>(grid, stream, p, dense);
   else if (direct)
-    hipLaunchKernelGGL((dp_i16_kernel<L, K, false, true>), dim3(grid), dim3(kWave), 0, stream, p);
+    launch_v16<L, K, false, true>(grid, stream, p, dense);
   else
-    hipLaunchKernelGGL((dp_i16_kernel<L, K, false, false>), dim3(grid), dim3(kWave), 0, stream, p);
+    launch_v16<L, K, false, false>(grid, stream, p, dense);
   return hipGetLastError();
 }
 
+template <int L, int K, bool kScore, bool kDirect>
+hipError_t occupancy_v16(int *blocks, bool dense) {
+  if constexpr (!kScore && has_dense_i16(K)) {
+    if (dense)
+      return hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          blocks, dp_i16_kernel<L, K, kScore, kDirect, true>, kWave, 0);
+  }
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(
+      blocks, dp_i16_kernel<L, K, kScore, kDirect, false>, kWave, 0);
+}
+
 template <int L, int K>
-int occupancy_i16(bool score, bool direct) {
+int occupancy_i16(bool score, bool direct, bool dense) {
   int blocks = 0;
   hipError_t e;
   if (score && direct)
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, dp_i16_kernel<L, K, true, true>, kWave, 0);
+    e = occupancy_v16<L, K, true, true>(&blocks, dense);
   else if (score)
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, dp_i16_kernel<L, K, true, false>, kWave, 0);
+    e = occupancy_v16<L, K, true, false>(&blocks, dense);
   else if (direct)
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, dp_i16_kernel<L, K, false, true>, kWave, 0);
+    e = occupancy_v16<L, K, false, true>(&blocks, dense);
   else
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, dp_i16_kernel<L, K, false, false>, kWave, 0);
+    e = occupancy_v16<L, K, false, false>(&blocks, dense);
   return e == hipSuccess ? blocks : 0;
 }
 
-hipError_t launch_dp_i16(Shape s, int grid, hipStream_t stream, const DpParams &p, bool direct) {
+hipError_t launch_dp_i16(Shape s, int grid, hipStream_t stream, const DpParams &p, bool direct,
+                         bool dense) {
 #define X(l, k) \
-  if (s.lanes == l && s.cells == k) return launch_i16<l, k>(grid, stream, p, direct);
+  if (s.lanes == l && s.cells == k) return launch_i16<l, k>(grid, stream, p, direct, dense);
   SOAPDP_I16_SHAPES(X)
 #undef X
   return hipErrorInvalidValue;
 }
 
-int occupancy_dp_i16(Shape s, bool score_only, bool direct) {
+int occupancy_dp_i16(Shape s, bool score_only, bool direct, bool dense) {
 #define X(l, k) \
-  if (s.lanes == l && s.cells == k) return occupancy_i16<l, k>(score_only, direct);
+  if (s.lanes == l && s.cells == k) return occupancy_i16<l, k>(score_only, direct, dense);
   SOAPDP_I16_SHAPES(X)
 #undef X
   return 0;

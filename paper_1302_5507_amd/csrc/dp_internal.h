@@ -206,9 +206,12 @@ int occupancy_dp_i32(Shape s, bool byte_delta, bool score_only);
 const Shape *shapes_i32(int *count);
 
 // Same for the packed int16 kernel (two tasks per lane, lo and hi halves),
-// offset form or direct form.
-hipError_t launch_dp_i16(Shape s, int grid, hipStream_t stream, const DpParams &p, bool direct);
-int occupancy_dp_i16(Shape s, bool score_only, bool direct);
+// offset form or direct form.  `dense` asks for the variant built for more
+// waves per SIMD where the shape has one (kernels with traceback at 13-14
+// and 19-20 columns); other shapes ignore it.
+hipError_t launch_dp_i16(Shape s, int grid, hipStream_t stream, const DpParams &p, bool direct,
+                         bool dense);
+int occupancy_dp_i16(Shape s, bool score_only, bool direct, bool dense);
 const Shape *shapes_i16(int *count);
 // Decision-scratch dwords of one workgroup slot.
 uint64_t slot_dwords_i32(Shape s, int32_t max_m);

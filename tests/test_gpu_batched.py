@@ -255,6 +255,60 @@ def test_every_int16_shape(al):
             al.set_class_shape(prec, cap, lanes, cells)
 
 
+def _tiled(w, reps):
+    """The tasks of `w` repeated `reps` times, as one workload."""
+    size = len(w.read_codes)
+    return workloads.Workload(
+        w.name, w.genome, np.tile(w.read_codes, reps),
+        np.concatenate([w.read_off + r * size for r in range(reps)]), np.tile(w.read_len, reps),
+        np.tile(w.ref_off, reps), np.tile(w.ref_len, reps), np.tile(w.true_off, reps), w.seed,
+        w.params)
+
+
+@pytest.mark.parametrize("k", [1, 50])
+def test_large_call_dense_shapes(al, k):
+    """A batched call of at least 262,144 tasks runs the int16 kernels with
+    traceback at 13-14 and 19-20 columns in their variant built for more
+    waves per SIMD.  Each such shape is forced onto the class it can serve,
+    with 20,000 distinct tasks repeated 14 times in one call (280,000 tasks),
+    windows up to 4x the class width (two passes) and, again, with one pass
+    over the whole window; scores x1 run the offset form, x50 the direct
+    form (with its int32 re-runs).  Every output of every copy equals the
+    oracle's."""
+    sc = tuple(k * x for x in CONFIG_SCORING)
+    defaults = al.classes()
+    caps16 = [c[1] for c in defaults if c[0] == 16]
+    rng = np.random.default_rng(31 + k)
+    reps, distinct = 14, 20_000
+    seen = 0
+    try:
+        for prec, cols, lanes, cells in binding.soap_dp_list_shapes(16):
+            if cells not in (13, 14, 19, 20):
+                continue
+            cap = max([c for c in caps16 if c <= cols], default=None)
+            if cap is None:
+                continue
+            prev = max([c for c in caps16 if c < cap], default=0)
+            al.set_class_shape(16, cap, lanes, cells)
+            w0 = workloads.random_tasks(rng, distinct, n_range=(prev + 1, cap),
+                                        m_range=(1, 4 * cap), genome_len=50000)
+            ref = oracle_align(w0, sc, stride=2 * cap)
+            w = _tiled(w0, reps)
+            assert w.n_tasks >= 262_144
+            for flags in (binding.BATCHED, binding.BATCHED | binding.FULL_WINDOW):
+                g = as_oracle_status(run(al, w, sc, flags=flags))
+                for r in range(reps):
+                    assert_same(g, ref, idx=np.arange(r * distinct, (r + 1) * distinct),
+                                label=f"x{k} {lanes}x{cells} class {cap} flags {flags} copy {r}")
+            seen += 1
+            d = [c for c in defaults if c[0] == 16 and c[1] == cap][0]
+            al.set_class_shape(16, cap, d[2], d[3])
+    finally:
+        for prec, cap, lanes, cells in defaults:
+            al.set_class_shape(prec, cap, lanes, cells)
+    assert seen >= 4
+
+
 def test_every_int32_shape(al):
     """Force each compiled int32 shape onto the int32 class it can serve and
     check reads spanning that class, full and score-only.  The scoring
