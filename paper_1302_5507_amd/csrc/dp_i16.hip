@@ -75,14 +75,16 @@ constexpr uint32_t kSignSel = 0x0b0a0908u;   // v_perm: replicate the four sign 
 // low-similarity batched call 0.8% faster.  The kernels with traceback at
 // 13-14 and 19-20 columns sit a few registers above four and three waves;
 // their dense variant (kDense) is asked for those and fits without
-// spilling.  It serves large calls only: there each class kernel has work
-// for many times its resident waves.  In served batches, whose class
+// spilling.  At 32 columns the dense variant runs three waves instead of
+// two with about 100 bytes spilled, mostly outside the row loop (the
+// uneven batch ran 3% faster).  It serves large calls only: there each
+// class kernel has work for many times its resident waves.  In served batches, whose class
 // kernels are short and run side by side, it ran 2% below capacity and
 // slower at low load, so small calls keep the default.
 constexpr int waves_i16(int K, bool score, bool direct, bool dense) {
   return K <= 8 ? 5 : (score && !direct ? 3 : (!dense ? 1 : (K <= 16 ? 4 : 3)));
 }
-constexpr bool has_dense_i16(int K) { return K == 13 || K == 14 || K == 19 || K == 20; }
+constexpr bool has_dense_i16(int K) { return K == 13 || K == 14 || K == 19 || K == 20 || K == 32; }
 
 // kScore: score and end only -- no decision bits, no scratch, no traceback.
 template <int L, int K, bool kScore, bool kDirect, bool kDense>

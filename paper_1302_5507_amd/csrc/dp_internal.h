@@ -207,8 +207,8 @@ const Shape *shapes_i32(int *count);
 
 // Same for the packed int16 kernel (two tasks per lane, lo and hi halves),
 // offset form or direct form.  `dense` asks for the variant built for more
-// waves per SIMD where the shape has one (kernels with traceback at 13-14
-// and 19-20 columns); other shapes ignore it.
+// waves per SIMD where the shape has one (kernels with traceback at 13-14,
+// 19-20 and 32 columns); other shapes ignore it.
 hipError_t launch_dp_i16(Shape s, int grid, hipStream_t stream, const DpParams &p, bool direct,
                          bool dense);
 int occupancy_dp_i16(Shape s, bool score_only, bool direct, bool dense);
