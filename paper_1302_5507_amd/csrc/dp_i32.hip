@@ -42,11 +42,16 @@ namespace soapdp {
 // compiler is asked to.  The score-only 4 x 25 sweep fits four instead of
 // three with its few spills outside the row loop, which made the
 // mate-rescue plain call 2% faster; asked the same, the 4 x 38 and 8 x 32
-// score sweeps ran 4% and 2% slower, so they keep the default.
+// score sweeps ran 4% and 2% slower, so they keep the default.  The
+// byte-table kernels with traceback above 16 columns are asked for four:
+// 4 x 25 and 8 x 32 then fit without spilling and 4 x 38 spills 72 bytes,
+// and the plain calls ran 1.2% (low-similarity) and 1.2-2.0% (mate rescue)
+// faster.  Their general-table twins would spill 100-300 bytes at four and
+// keep the default.
 // kScore: score and end only -- no decision bits, no scratch, no traceback.
 template <int L, int K, bool kByte, bool kScore>
 __global__ __launch_bounds__(kWave)
-__attribute__((amdgpu_waves_per_eu((kByte || kScore) && K <= 16 ? 5 : (kByte && kScore && K >= 20 && K <= 25 ? 4 : 1))))
+__attribute__((amdgpu_waves_per_eu((kByte || kScore) && K <= 16 ? 5 : (kByte && (!kScore || (K >= 20 && K <= 25)) ? 4 : 1))))
 void dp_i32_kernel(DpParams p) {
   static_assert(kWave % L == 0, "lanes per task must divide the wavefront");
   constexpr int G = kWave / L;       // tasks per wavefront
