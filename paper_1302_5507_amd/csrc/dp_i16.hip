@@ -530,6 +530,8 @@ hipError_t launch_dp_i16(Shape s, int grid, hipStream_t stream, const DpParams &
   return hipErrorInvalidValue;
 }
 
+bool has_dense_dp_i16(Shape s) { return has_dense_i16(s.cells); }
+
 int occupancy_dp_i16(Shape s, bool score_only, bool direct, bool dense) {
 #define X(l, k) \
   if (s.lanes == l && s.cells == k) return occupancy_i16<l, k>(score_only, direct, dense);

@@ -212,6 +212,8 @@ const Shape *shapes_i32(int *count);
 hipError_t launch_dp_i16(Shape s, int grid, hipStream_t stream, const DpParams &p, bool direct,
                          bool dense);
 int occupancy_dp_i16(Shape s, bool score_only, bool direct, bool dense);
+// Whether the int16 kernel with traceback of shape `s` has the denser variant.
+bool has_dense_dp_i16(Shape s);
 const Shape *shapes_i16(int *count);
 // Decision-scratch dwords of one workgroup slot.
 uint64_t slot_dwords_i32(Shape s, int32_t max_m);
