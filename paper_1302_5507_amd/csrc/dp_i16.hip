@@ -78,9 +78,9 @@ constexpr uint32_t kSignSel = 0x0b0a0908u;   // v_perm: replicate the four sign 
 // spilling.  At 32 columns the dense variant runs three waves instead of
 // two with about 100 bytes spilled, mostly outside the row loop (the
 // uneven batch ran 3% faster).  It serves large calls only: there each
-// class kernel has work for many times its resident waves.  In served batches, whose class
-// kernels are short and run side by side, it ran 2% below capacity and
-// slower at low load, so small calls keep the default.
+// class kernel has work for many times its resident waves.  In served
+// batches, whose class kernels are short and run side by side, it ran 2%
+// below capacity and slower at low load, so small calls keep the default.
 constexpr int waves_i16(int K, bool score, bool direct, bool dense) {
   return K <= 8 ? 5 : (score && !direct ? 3 : (!dense ? 1 : (K <= 16 ? 4 : 3)));
 }
